@@ -1,0 +1,154 @@
+"""Seeded synthetic node sets (input generation only).
+
+This module places nodes; it computes nothing of the method itself (no
+neighbour search, classification, weights or operators).  Tests, the bench
+and the smoke check feed the same node sets to the FP64 CPU oracle and to the
+GPU library, so it is kept apart from both.
+
+The node sets follow the paper's recipe for a hybrid discretisation
+(Section 2): a regular lattice, with lattice nodes removed in a band around
+irregular boundaries, and the band refilled by a scattered Poisson-disk
+placement (Bridson 2007, radius h, 30 candidates; the paper's own fill
+algorithm is external to it).  Circles and spheres stand in for the paper's
+duck-shaped obstacles (Section 4.2), whose geometry exists only as a figure.
+
+Workloads (seeds are 2303017600 + the workload number):
+  1. differentially heated cavity, h=0.02, scattered band 0.1 along the walls
+     (left wall T=1, right wall T=0, top/bottom adiabatic)      ~2.6k nodes
+  2. unit square minus 20 circles (r ~ U(0.02, 0.08)), h=0.002, band 0.05
+     around the circles, box walls adiabatic, circles T=0/1       ~230k nodes
+  4. unit cube minus 8 spheres (r ~ U(0.05, 0.15)), h=0.01, band 0.05  ~950k
+  5. workload 2 at h=0.001                                        ~900k nodes
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libhsm_nodegen.so")
+_lib = None
+
+KIND_INTERIOR, KIND_DIRICHLET, KIND_NEUMANN = 0, 1, 2
+SEED_BASE = 2303017600
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [
+        ("d", ctypes.c_int32), ("n_obst", ctypes.c_int32),
+        ("h", ctypes.c_double), ("wall_band", ctypes.c_double), ("obst_band", ctypes.c_double),
+        ("rmin", ctypes.c_double), ("rmax", ctypes.c_double), ("gap", ctypes.c_double),
+        ("wall_kind", ctypes.c_int32 * 6), ("wall_T", ctypes.c_double * 6),
+        ("obst_T", ctypes.c_double * 2), ("obst_kind", ctypes.c_int32),
+        ("n_candidates", ctypes.c_int32), ("seed", ctypes.c_uint64),
+    ]
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise RuntimeError(f"node generator library not built: {_LIB_PATH} (run __graft_entry__.build())")
+        lib = ctypes.CDLL(_LIB_PATH)
+        lib.ng_generate.restype = ctypes.c_void_p
+        lib.ng_generate.argtypes = [ctypes.POINTER(_Params), ctypes.POINTER(ctypes.c_int64)]
+        lib.ng_copy.restype = None
+        lib.ng_copy.argtypes = [ctypes.c_void_p] + [ctypes.c_void_p] * 6
+        lib.ng_obstacles.restype = ctypes.c_int32
+        lib.ng_obstacles.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+        lib.ng_free.restype = None
+        lib.ng_free.argtypes = [ctypes.c_void_p]
+        _lib = lib
+    return _lib
+
+
+@dataclass
+class NodeSet:
+    """A node set of one domain.  Arrays are numpy; positions are SoA [d][N]."""
+    d: int
+    h: float                      # regular lattice spacing h_r
+    x: np.ndarray                 # float64 [d, N]
+    kind: np.ndarray              # uint8 [N]: 0 interior, 1 Dirichlet-T, 2 Neumann-T
+    normal: np.ndarray            # float64 [d, N], outward unit normal (0 inside)
+    tbc: np.ndarray               # float64 [N], Dirichlet temperature (0 elsewhere)
+    origin: np.ndarray            # int8 [N]: 0 lattice, 1 boundary, 2 scattered fill
+    group: np.ndarray             # int32 [N]: -1 fluid, 0..5 box face, 6+i obstacle i
+    obstacles: np.ndarray = field(default_factory=lambda: np.zeros((0, 3)))
+    name: str = ""
+
+    @property
+    def n(self) -> int:
+        return int(self.x.shape[1])
+
+
+def generate(d: int, h: float, *, wall_band: float = 0.0, obst_band: float = 0.0,
+             n_obst: int = 0, rmin: float = 0.0, rmax: float = 0.0, gap: float = 4.0,
+             wall_kind=None, wall_T=None, obst_T=(0.0, 1.0), obst_kind: int = KIND_DIRICHLET,
+             n_candidates: int = 30, seed: int = SEED_BASE, name: str = "") -> NodeSet:
+    lib = _load()
+    p = _Params()
+    p.d, p.n_obst, p.h = d, n_obst, h
+    p.wall_band, p.obst_band, p.rmin, p.rmax, p.gap = wall_band, obst_band, rmin, rmax, gap
+    wk = list(wall_kind) if wall_kind is not None else [KIND_NEUMANN] * 6
+    wt = list(wall_T) if wall_T is not None else [0.0] * 6
+    for i in range(6):
+        p.wall_kind[i] = int(wk[i]) if i < len(wk) else KIND_NEUMANN
+        p.wall_T[i] = float(wt[i]) if i < len(wt) else 0.0
+    p.obst_T[0], p.obst_T[1] = float(obst_T[0]), float(obst_T[1])
+    p.obst_kind, p.n_candidates, p.seed = obst_kind, n_candidates, seed & 0xFFFFFFFFFFFFFFFF
+    n = ctypes.c_int64(0)
+    hnd = lib.ng_generate(ctypes.byref(p), ctypes.byref(n))
+    if not hnd:
+        raise ValueError("node generation failed (invalid parameters or obstacles could not be placed)")
+    try:
+        N = n.value
+        x = np.empty((d, N), np.float64)
+        kind = np.empty(N, np.uint8)
+        nrm = np.empty((d, N), np.float64)
+        tbc = np.empty(N, np.float64)
+        origin = np.empty(N, np.int8)
+        group = np.empty(N, np.int32)
+        lib.ng_copy(hnd, x.ctypes.data, kind.ctypes.data, nrm.ctypes.data, tbc.ctypes.data,
+                    origin.ctypes.data, group.ctypes.data)
+        nob = lib.ng_obstacles(hnd, None)
+        obst = np.zeros((nob, d + 1), np.float64)
+        if nob:
+            lib.ng_obstacles(hnd, obst.ctypes.data)
+    finally:
+        lib.ng_free(hnd)
+    return NodeSet(d=d, h=h, x=x, kind=kind, normal=nrm, tbc=tbc, origin=origin, group=group,
+                   obstacles=obst, name=name)
+
+
+def cavity2d(h: float = 0.02, wall_band: float = 0.1, seed: int = SEED_BASE + 1,
+             T_hot: float = 1.0, T_cold: float = 0.0) -> NodeSet:
+    """Differentially heated cavity: left wall hot, right wall cold, top/bottom adiabatic."""
+    return generate(2, h, wall_band=wall_band,
+                    wall_kind=[KIND_DIRICHLET, KIND_DIRICHLET, KIND_NEUMANN, KIND_NEUMANN],
+                    wall_T=[T_hot, T_cold, 0.0, 0.0], seed=seed, name=f"cavity2d_h{h}")
+
+
+def obstacles2d(h: float = 0.002, n_obst: int = 20, rmin: float = 0.02, rmax: float = 0.08,
+                band: float = 0.05, seed: int = SEED_BASE + 2) -> NodeSet:
+    """Unit square minus seeded circles; adiabatic box, circles alternately T=0 / T=1."""
+    return generate(2, h, obst_band=band, n_obst=n_obst, rmin=rmin, rmax=rmax,
+                    wall_kind=[KIND_NEUMANN] * 4, seed=seed, name=f"obstacles2d_h{h}_n{n_obst}")
+
+
+def obstacles3d(h: float = 0.01, n_obst: int = 8, rmin: float = 0.05, rmax: float = 0.15,
+                band: float = 0.05, seed: int = SEED_BASE + 4) -> NodeSet:
+    """Unit cube minus seeded spheres; adiabatic box, spheres alternately T=0 / T=1."""
+    return generate(3, h, obst_band=band, n_obst=n_obst, rmin=rmin, rmax=rmax,
+                    wall_kind=[KIND_NEUMANN] * 6, seed=seed, name=f"obstacles3d_h{h}_n{n_obst}")
+
+
+def random_cloud(n: int, d: int = 2, seed: int = 0, h: float = 0.1) -> NodeSet:
+    """Uniform random interior points in the unit box (tests only; no boundary)."""
+    rng = np.random.default_rng(seed)
+    x = rng.random((d, n))
+    z = np.zeros(n)
+    return NodeSet(d=d, h=h, x=x, kind=np.zeros(n, np.uint8), normal=np.zeros((d, n)), tbc=z.copy(),
+                   origin=np.full(n, 2, np.int8), group=np.full(n, -1, np.int32), name=f"cloud{d}d_{n}")
