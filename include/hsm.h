@@ -1,0 +1,224 @@
+/*
+ * hsm.h -- C ABI of the MI355X (gfx950) hybrid scattered-regular meshless library.
+ *
+ * The library implements the hot path of the hybrid method of Jancic, Rot and
+ * Kosec, "Spatially-varying meshless approximation method for enhanced
+ * computational efficiency" (arXiv 2303.01760):
+ *   - per-node stencils and weights of d/dx, d/dy (, d/dz) and the Laplacian,
+ *     built once: RBF-FD (PHS r^3 + monomials up to degree m over
+ *     n = 2 C(m+d, m) nearest nodes) on scattered nodes, MON (monomials
+ *     {1, x_k, x_k^2} over the 2d+1 node axis cross) on regular nodes
+ *     (Section 2; Section 2.1 for the local system M w = l);
+ *   - the operator approximation of Eq. (1), (L u)(x_c) ~ sum_i w_i u(x_i),
+ *     applied many times inside explicit time steps;
+ *   - explicit Euler steps of the Boussinesq natural-convection equations
+ *     (Eqs. (2)-(4)) with Chorin's pressure projection (Section 3).
+ *
+ * Every computation runs in hand-written HIP kernels on one GPU.  There is no
+ * CPU fallback: without a usable gfx950 device every call that computes
+ * returns HSM_E_HIP.
+ *
+ * Conventions
+ *   - Pointers named host_* are host memory; every other array pointer is
+ *     device memory (e.g. from torch tensors).  The caller owns all arrays it
+ *     passes and must keep them alive for the duration of the call.
+ *   - Handles (hsm_stencils, hsm_sim) are owned by the library and released
+ *     with the matching *_destroy function.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *   - Functions return HSM_OK (0) or a negative hsm_status.  On error
+ *     hsm_last_error() gives a message and hsm_last_error_node() the node
+ *     (caller numbering) the error refers to, or -1; both are per thread.
+ *   - Positions, normals and fields are SoA: component a of node i is at
+ *     [a * N + i].
+ *   - Node classes: 0 = regular (MON stencil), 1 = scattered (RBF-FD).
+ *   - Node kinds (input): 0 = interior, 1 = Dirichlet-T wall, 2 = Neumann-T
+ *     (adiabatic) wall.  Every wall node is no-slip for velocity.
+ */
+#ifndef HSM_H
+#define HSM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t hsm_status;
+enum {
+  HSM_OK = 0,
+  HSM_E_INVALID = -1,        /* bad argument; nothing was computed */
+  HSM_E_SINGULAR = -2,       /* a local system M w = l has no usable pivot */
+  HSM_E_DUPLICATE_NODE = -3, /* two nodes of one domain coincide */
+  HSM_E_NOT_CONVERGED = -4,  /* pressure Krylov solve hit its iteration cap */
+  HSM_E_NONFINITE = -5,      /* a field became Inf/NaN during stepping */
+  HSM_E_HIP = -6,            /* HIP runtime error (no device, launch failure) */
+  HSM_E_OOM = -7,            /* device allocation failed */
+  HSM_E_AMBIGUOUS = -8       /* too many nodes within h_r of a node to classify it */
+};
+
+/* operator bits */
+enum { HSM_OP_DX = 1, HSM_OP_DY = 2, HSM_OP_DZ = 4, HSM_OP_LAP = 8, HSM_OP_DN = 16 };
+/* data types of fields and weights */
+enum { HSM_F64 = 0, HSM_F32 = 1, HSM_F32_COMP = 2 };
+/* approximation layout */
+enum { HSM_MODE_HYBRID = 0, HSM_MODE_ALL_SCATTERED = 1 };
+/* direction of hsm_permute */
+enum { HSM_TO_INTERNAL = 0, HSM_TO_CALLER = 1 };
+
+typedef struct hsm_stencils hsm_stencils;
+typedef struct hsm_sim hsm_sim;
+
+/* A node set: one or more independent domains stored back to back.
+ * Stencils never cross a domain boundary. */
+typedef struct {
+  int32_t d;                           /* dimension, 2 or 3 */
+  int32_t n_domains;                   /* >= 1 */
+  const int64_t *host_domain_offsets;  /* [n_domains+1]; domain k = nodes [off[k], off[k+1]) */
+  const double *x;                     /* device [d][N] positions */
+  const uint8_t *kind;                 /* device [N] 0 interior, 1 Dirichlet-T, 2 Neumann-T */
+  const double *normal;                /* device [d][N] outward unit normal (read at wall nodes) */
+  const double *host_h_regular;        /* [n_domains] regular lattice spacing h_r (> 0) */
+  const int32_t *host_m;               /* [n_domains] monomial degree of RBF-FD stencils */
+  const int32_t *host_n;               /* [n_domains] RBF-FD stencil size, or NULL for 2 C(m+d, m) */
+} hsm_nodeset;
+
+/* Summary of a built stencil set. */
+typedef struct {
+  int32_t d, mode, n_domains, n_buckets;
+  int64_t n_nodes, nnz;                /* nnz = total stencil entries over all nodes */
+  int64_t n_regular, n_scattered;      /* by class */
+  int64_t n_boundary;
+  int32_t bucket_width[16];            /* per width bucket, in internal order */
+  int32_t bucket_type[16];             /* 0 regular, 1 scattered interior, 2 Dirichlet wall, 3 Neumann wall */
+  int64_t bucket_count[16];
+  double build_ms[4];                  /* device time of: neighbour search, classify+order, local solves, total */
+} hsm_stencils_info;
+
+/*
+ * hsm_build_stencils -- stencils and FP64 weights of d/dx_a and the Laplacian
+ * at every node (Section 2; Eq. (1); Section 2.1).
+ *
+ * Stencil selection (text before Eq. (1)): an interior node takes the n nodes
+ * of its domain nearest to it, ordered by (squared distance, caller index)
+ * with squared distance dx*dx + dy*dy (+ dz*dz) rounded step by step in that
+ * order; the node itself comes first.  A wall node takes itself and its n-1
+ * nearest interior nodes.  Classification (Section 2, Fig. 1): in
+ * HSM_MODE_HYBRID an interior node is regular if, for each axis a and sign s,
+ * exactly one node lies within 1e-6 h_r (max-norm) of x + s h_r e_a; its
+ * stencil is then [i, -x, +x, -y, +y (, -z, +z)] with MON weights.  All other
+ * nodes (every node in HSM_MODE_ALL_SCATTERED) get RBF-FD weights.  Wall
+ * nodes also get normal-derivative weights sum_a n_a w_a (HSM_OP_DN).
+ * Weights solve the local system in coordinates centred at the node and
+ * scaled by the stencil radius, by LU with partial pivoting.
+ *
+ * Supported: d = 2 with 1 <= m <= 4, d = 3 with 1 <= m <= 3, and
+ * n + C(m+d, d) <= 64 (so 2D m=4 n=30 and 3D m=2 n=20 or 30 fit).
+ *
+ * Synchronises `stream`.  Errors: HSM_E_INVALID (arguments, a domain with
+ * fewer than n usable nodes), HSM_E_DUPLICATE_NODE, HSM_E_AMBIGUOUS,
+ * HSM_E_SINGULAR (hsm_last_error_node names the node), HSM_E_OOM, HSM_E_HIP.
+ * On success *out is a new handle.
+ */
+hsm_status hsm_build_stencils(const hsm_nodeset *nodes, int32_t mode, void *stream, hsm_stencils **out);
+
+hsm_status hsm_stencils_get_info(const hsm_stencils *st, hsm_stencils_info *out);
+
+/*
+ * hsm_stencils_export -- copy classes, stencils and weights to host memory in
+ * the caller's node numbering (CSR).  host_offsets [N+1]; host_idx [nnz]
+ * (caller indices, stencil order); host_w [d+2][nnz] holding d/dx_0..d/dx_{d-1},
+ * the Laplacian and the normal derivative (0 at interior nodes).  Any output
+ * pointer may be NULL.  Synchronises `stream`.
+ */
+hsm_status hsm_stencils_export(const hsm_stencils *st, uint8_t *host_class, int64_t *host_offsets,
+                               int32_t *host_idx, double *host_w, void *stream);
+
+/*
+ * hsm_permute -- move a field between the caller's node order and the
+ * library's internal order (width buckets; spatially sorted inside each
+ * bucket), in which hsm_apply_operator reads and writes fields.
+ * dtype HSM_F64 or HSM_F32; src and dst are device [N] and must not overlap.
+ * Asynchronous on `stream`.
+ */
+hsm_status hsm_permute(const hsm_stencils *st, int32_t direction, int32_t dtype, const void *src,
+                       void *dst, void *stream);
+
+/*
+ * hsm_apply_operator -- Eq. (1) at every node: out_op[i] = sum_j w_op[i][j] u[idx[i][j]]
+ * for every operator bit set in op_mask (HSM_OP_DX .. HSM_OP_LAP; HSM_OP_DN
+ * only on wall nodes, 0 elsewhere).  u is device [N] and out device
+ * [popcount(op_mask)][N], both in internal order, operators in ascending bit
+ * order.  dtype: HSM_F64 (FP64 weights and fields), HSM_F32 (FP32 weights
+ * and fields, FP32 sums) or HSM_F32_COMP (FP32 weights and fields, products
+ * and sums compensated: Ogita-Rump-Oishi Dot2).  u and out must not overlap.
+ * Asynchronous on `stream`; only argument errors are returned.
+ */
+hsm_status hsm_apply_operator(const hsm_stencils *st, uint32_t op_mask, int32_t dtype, const void *u,
+                              void *out, void *stream);
+
+/* Number of (operator, node) pairs one hsm_apply_operator call computes. */
+int64_t hsm_apply_node_count(const hsm_stencils *st, uint32_t op_mask);
+
+/* Simulation parameters (Section 3).  rho = 1; gravity points along the last
+ * axis, g = -e_y (2D) or -e_z (3D); T_Delta = T - T_ref in Eq. (3). */
+typedef struct {
+  double Ra, Pr, dt, T_ref;
+  double krylov_tol;       /* relative residual of the pressure solve, e.g. 1e-12 */
+  int32_t krylov_maxiter;  /* iteration cap per step */
+  int32_t field_dtype;     /* HSM_F64, or HSM_F32_COMP for FP32 fields with compensated applies */
+  int32_t krylov_chunk;    /* iterations per device-side batch between convergence checks (0 = default) */
+  int32_t launch_mode;     /* 0: replay captured HIP graphs, 1: launch kernels directly (same kernels) */
+} hsm_sim_params;
+
+typedef struct {
+  int64_t steps;                 /* steps completed */
+  int64_t krylov_iters_total;    /* over all steps */
+  int32_t krylov_iters_last;     /* of the last step */
+  int32_t status;                /* latched hsm_status of the stepping */
+  double last_relres;            /* relative residual reached in the last step */
+  int64_t node_applies;          /* (operator, field, node) triples evaluated so far */
+} hsm_sim_stats;
+
+/*
+ * hsm_sim_create -- a simulation state on a stencil set.  v [d][N], T [N] and
+ * p [N] (may be NULL for zero) are device arrays in the caller's numbering,
+ * copied in; T at Dirichlet nodes is their wall temperature.  The pressure
+ * problem of each step is the Poisson equation of the projection with
+ * dp/dn = 0 at walls and zero mean (readings in the design notes).  Uses
+ * `stream` for the copies and synchronises it.
+ */
+hsm_status hsm_sim_create(const hsm_stencils *st, const hsm_sim_params *prm, const double *v,
+                          const double *T, const double *p, void *stream, hsm_sim **out);
+
+/*
+ * hsm_step -- advance nsteps explicit Euler steps (Section 3):
+ *   v* = v + dt(-(v.grad)v + Pr Lap v - Ra Pr g T_Delta)  (interior), 0 at walls;
+ *   Lap p = div(v*) / dt  (interior), dp/dn = 0 (walls), sum p = 0;
+ *   v = v* - dt grad p; T = T + dt(-v.grad T + Lap T) with the new v;
+ *   Dirichlet walls keep T; Neumann walls take the T that zeroes dT/dn.
+ * Work is ordered on `stream` (device-side batches replayed from HIP graphs);
+ * the call returns once the work is queued, except that it waits for each
+ * step's Krylov convergence flag.  Numerical failures are latched and read
+ * by hsm_sim_get_stats.
+ */
+hsm_status hsm_step(hsm_sim *sim, int32_t nsteps, void *stream);
+
+/* Synchronises and returns the latched status (HSM_OK, HSM_E_NONFINITE, HSM_E_NOT_CONVERGED). */
+hsm_status hsm_sim_get_stats(hsm_sim *sim, hsm_sim_stats *out);
+
+/* Copy v [d][N], T [N], p [N] (caller numbering, FP64) out; NULL skips a field. */
+hsm_status hsm_sim_read(hsm_sim *sim, double *v, double *T, double *p, void *stream);
+
+void hsm_sim_destroy(hsm_sim *sim);
+void hsm_stencils_destroy(hsm_stencils *st);
+
+const char *hsm_last_error(void);
+int64_t hsm_last_error_node(void);
+
+/* Library version string. */
+const char *hsm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HSM_H */

@@ -1,0 +1,421 @@
+// Batched local solves M w = l for the stencil weights (Section 2.1).
+//
+// RBF-FD (scattered nodes): M = [[A, P], [P^T, 0]] with A_jl = |y_j - y_l|^3
+// (PHS of order 3) and P_ja = y_j^alpha for all monomials of degree <= m
+// (Section 2 and the choice k = 3, m = 2 of Section 4), in coordinates y
+// centred at the node and scaled by the stencil radius.  Right-hand sides
+// are the operator applied to each basis function at the centre:
+//   d/dx_a : -3 |y_j| y_j,a  and 1 on the monomial x_a
+//   Lap    : 3 (d+1) |y_j|   and 2 on each monomial x_a^2.
+// One wave64 per system, one matrix row per lane, so S = n + Q <= 64.
+//
+// MON (regular nodes): the 2d+1 monomials {1, x_a, x_a^2} on the 2d+1 node
+// axis cross (Section 2 and its footnote); one thread per node.
+//
+// Both use LU with partial pivoting in one fixed form: in column k the pivot
+// is the not-yet-used row of largest magnitude, the lowest row on ties; rows
+// are not moved; back substitution runs columns from last to first.  The
+// file is compiled with -ffp-contract=off, so every product and sum is
+// rounded as written and the pivoting decisions are reproducible.
+#include <hip/hip_runtime.h>
+
+#include "hsm_internal.h"
+
+namespace hsm {
+namespace {
+
+constexpr double kPivotRel = 1e-14;  // pivot below kPivotRel * max|M| => singular
+
+template <int D, int M>
+struct Monos {
+  static constexpr int count() {
+    int q = 1;
+    for (int k = 1; k <= D; ++k) q = q * (M + k) / k;
+    return q;
+  }
+  static constexpr int Q = count();
+  int e[Q][3];
+  // graded; inside a degree, descending power of x, then of y
+  constexpr Monos() : e{} {
+    int q = 0;
+    for (int deg = 0; deg <= M; ++deg) {
+      if (D == 2) {
+        for (int ax = deg; ax >= 0; --ax) { e[q][0] = ax; e[q][1] = deg - ax; e[q][2] = 0; ++q; }
+      } else {
+        for (int ax = deg; ax >= 0; --ax)
+          for (int ay = deg - ax; ay >= 0; --ay) { e[q][0] = ax; e[q][1] = ay; e[q][2] = deg - ax - ay; ++q; }
+      }
+    }
+  }
+};
+
+__device__ __forceinline__ double rdlane(double v, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+struct SolveArgs {
+  const double *x;        // [D][N] internal order
+  const double *normal;   // [D][N] internal order
+  int64_t N;
+  const int32_t *idx;     // [W][count]
+  int64_t count, start;
+  double *w;              // [nops][W][count]
+  int wall;               // also write normal-derivative weights
+  const int32_t *perm;
+  DevStatus *status;
+};
+
+template <int D, int M, int NS>
+__global__ __launch_bounds__(64) void k_rbffd(SolveArgs a) {
+  constexpr Monos<D, M> mono{};
+  constexpr int Q = Monos<D, M>::Q;
+  constexpr int S = NS + Q;
+  constexpr int R = D + 1;
+  static_assert(S <= 64, "one system row per lane");
+  const int lane = threadIdx.x;
+  const int64_t t = blockIdx.x;
+  const int64_t cnt = a.count, N = a.N;
+  __shared__ double sy[NS][D];
+  __shared__ double smono[NS][Q];
+
+  // local coordinates y_j = (x_j - x_c) / s, s = max_j |x_j - x_c|
+  const int32_t c = a.idx[t];
+  double dxv[D], r = 0.0;
+#pragma unroll
+  for (int q = 0; q < D; ++q) dxv[q] = 0.0;
+  if (lane < NS) {
+    const int32_t nj = a.idx[(int64_t)lane * cnt + t];
+    double sq = 0.0;
+#pragma unroll
+    for (int q = 0; q < D; ++q) {
+      dxv[q] = a.x[q * N + nj] - a.x[q * N + c];
+      const double v = dxv[q] * dxv[q];
+      sq = (q == 0) ? v : sq + v;
+    }
+    r = sqrt(sq);
+  }
+  const double s = wave_max(r);
+  double y[D];
+#pragma unroll
+  for (int q = 0; q < D; ++q) y[q] = dxv[q] / s;
+  if (lane < NS) {
+#pragma unroll
+    for (int q = 0; q < D; ++q) sy[lane][q] = y[q];
+#pragma unroll
+    for (int al = 0; al < Q; ++al) {
+      double p = 1.0;
+#pragma unroll
+      for (int q = 0; q < D; ++q)
+#pragma unroll
+        for (int e = 0; e < mono.e[al][q]; ++e) p = p * y[q];
+      smono[lane][al] = p;
+    }
+  }
+  __syncthreads();
+
+  // this lane's row of M and of the right-hand sides
+  double Rw[S], B[R];
+#pragma unroll
+  for (int k = 0; k < S; ++k) Rw[k] = 0.0;
+#pragma unroll
+  for (int q = 0; q < R; ++q) B[q] = 0.0;
+  if (lane < NS) {
+#pragma unroll
+    for (int l = 0; l < NS; ++l) {
+      double sq = 0.0;
+#pragma unroll
+      for (int q = 0; q < D; ++q) {
+        const double dv = y[q] - sy[l][q];
+        const double v = dv * dv;
+        sq = (q == 0) ? v : sq + v;
+      }
+      const double rr = sqrt(sq);
+      Rw[l] = rr * rr * rr;
+    }
+#pragma unroll
+    for (int al = 0; al < Q; ++al) Rw[NS + al] = smono[lane][al];
+    double sq = 0.0;
+#pragma unroll
+    for (int q = 0; q < D; ++q) {
+      const double v = y[q] * y[q];
+      sq = (q == 0) ? v : sq + v;
+    }
+    const double rl = sqrt(sq);
+#pragma unroll
+    for (int q = 0; q < D; ++q) B[q] = -((3.0 * rl) * y[q]);
+    B[D] = (3.0 * (D + 1)) * rl;
+  } else if (lane < S) {
+#pragma unroll
+    for (int al = 0; al < Q; ++al) {
+      if (lane - NS != al) continue;
+#pragma unroll
+      for (int l = 0; l < NS; ++l) Rw[l] = smono[l][al];
+      const int deg = mono.e[al][0] + mono.e[al][1] + mono.e[al][2];
+#pragma unroll
+      for (int q = 0; q < D; ++q) {
+        if (deg == 1 && mono.e[al][q] == 1) B[q] = 1.0;
+        if (deg == 2 && mono.e[al][q] == 2) B[D] = 2.0;
+      }
+    }
+  }
+
+  // elimination
+  double amax = 0.0;
+#pragma unroll
+  for (int k = 0; k < S; ++k) amax = fmax(amax, fabs(Rw[k]));
+  amax = wave_max(amax);
+  const double thr = kPivotRel * amax;
+  bool used = lane >= S;
+  int pstep = used ? S : -1;
+  int piv[S];
+  bool singular = false;
+#pragma unroll
+  for (int k = 0; k < S; ++k) {
+    const double cand = used ? -1.0 : fabs(Rw[k]);
+    const double best = wave_max(cand);
+    if (!(best > thr)) { singular = true; break; }
+    const unsigned long long mask = __ballot(!used && cand == best);
+    const int p = __ffsll((long long)mask) - 1;
+    piv[k] = p;
+    const double pk = rdlane(Rw[k], p);
+    double pr[S];
+#pragma unroll
+    for (int j = k + 1; j < S; ++j) pr[j] = rdlane(Rw[j], p);
+    double pb[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) pb[q] = rdlane(B[q], p);
+    if (lane == p) {
+      used = true;
+      pstep = k;
+    } else if (!used) {
+      const double l = Rw[k] / pk;
+#pragma unroll
+      for (int j = k + 1; j < S; ++j) Rw[j] = Rw[j] - l * pr[j];
+#pragma unroll
+      for (int q = 0; q < R; ++q) B[q] = B[q] - l * pb[q];
+    }
+  }
+  if (singular) {
+    if (lane == 0) latch(a.status, BE_SINGULAR, a.perm[a.start + t]);
+    return;
+  }
+  // back substitution, last column first
+  double myw[R];
+#pragma unroll
+  for (int q = 0; q < R; ++q) myw[q] = 0.0;
+#pragma unroll
+  for (int k = S - 1; k >= 0; --k) {
+    const int p = piv[k];
+    const double den = rdlane(Rw[k], p);
+    double xk[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) xk[q] = rdlane(B[q], p) / den;
+    if (k < NS && lane == k) {
+#pragma unroll
+      for (int q = 0; q < R; ++q) myw[q] = xk[q];
+    }
+    if (pstep < k) {
+#pragma unroll
+      for (int q = 0; q < R; ++q) B[q] = B[q] - Rw[k] * xk[q];
+    }
+  }
+  if (lane < NS) {
+    const int64_t WC = (int64_t)NS * cnt;
+    const double s2 = s * s;
+    double wv[R];
+#pragma unroll
+    for (int q = 0; q < D; ++q) wv[q] = myw[q] / s;
+    wv[D] = myw[D] / s2;
+#pragma unroll
+    for (int q = 0; q < R; ++q) a.w[q * WC + (int64_t)lane * cnt + t] = wv[q];
+    if (a.wall) {
+      double acc = 0.0;
+#pragma unroll
+      for (int q = 0; q < D; ++q) {
+        const double v = a.normal[q * N + c] * wv[q];
+        acc = (q == 0) ? v : acc + v;
+      }
+      a.w[R * WC + (int64_t)lane * cnt + t] = acc;
+    }
+  }
+}
+
+// MON on the axis cross [c, -x, +x, -y, +y (, -z, +z)], one thread per node.
+template <int D>
+__global__ __launch_bounds__(128) void k_mon(SolveArgs a) {
+  constexpr int S = 2 * D + 1, R = D + 1;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= a.count) return;
+  const int64_t cnt = a.count, N = a.N;
+  const int32_t c = a.idx[t];
+  double y[S][D], s = 0.0;
+#pragma unroll
+  for (int j = 0; j < S; ++j) {
+    const int32_t nj = a.idx[(int64_t)j * cnt + t];
+    double sq = 0.0;
+#pragma unroll
+    for (int q = 0; q < D; ++q) {
+      y[j][q] = a.x[q * N + nj] - a.x[q * N + c];
+      const double v = y[j][q] * y[j][q];
+      sq = (q == 0) ? v : sq + v;
+    }
+    const double r = sqrt(sq);
+    if (r > s) s = r;
+  }
+#pragma unroll
+  for (int j = 0; j < S; ++j)
+#pragma unroll
+    for (int q = 0; q < D; ++q) y[j][q] = y[j][q] / s;
+  // rows: basis functions 1, x_a (a < D), x_a^2; columns: stencil nodes
+  double A[S][S], B[S][R];
+#pragma unroll
+  for (int j = 0; j < S; ++j) {
+    A[0][j] = 1.0;
+#pragma unroll
+    for (int q = 0; q < D; ++q) {
+      A[1 + q][j] = y[j][q];
+      A[1 + D + q][j] = y[j][q] * y[j][q];
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < S; ++r)
+#pragma unroll
+    for (int q = 0; q < R; ++q) B[r][q] = 0.0;
+#pragma unroll
+  for (int q = 0; q < D; ++q) {
+    B[1 + q][q] = 1.0;
+    B[1 + D + q][D] = 2.0;
+  }
+  double amax = 0.0;
+#pragma unroll
+  for (int r = 0; r < S; ++r)
+#pragma unroll
+    for (int j = 0; j < S; ++j) amax = fmax(amax, fabs(A[r][j]));
+  const double thr = kPivotRel * amax;
+  unsigned used = 0;
+  int pivrow[S], stepof[S];
+#pragma unroll
+  for (int r = 0; r < S; ++r) stepof[r] = S;
+#pragma unroll
+  for (int k = 0; k < S; ++k) {
+    double best = -1.0;
+    int p = 0;
+#pragma unroll
+    for (int r = 0; r < S; ++r)
+      if (!((used >> r) & 1u) && fabs(A[r][k]) > best) { best = fabs(A[r][k]); p = r; }
+    if (!(best > thr)) {
+      latch(a.status, BE_SINGULAR, a.perm[a.start + t]);
+      return;
+    }
+    used |= 1u << p;
+    pivrow[k] = p;
+    double pv[S], pb[R];
+#pragma unroll
+    for (int j = 0; j < S; ++j) pv[j] = A[0][j];
+#pragma unroll
+    for (int q = 0; q < R; ++q) pb[q] = B[0][q];
+#pragma unroll
+    for (int r = 1; r < S; ++r)
+      if (p == r) {
+#pragma unroll
+        for (int j = 0; j < S; ++j) pv[j] = A[r][j];
+#pragma unroll
+        for (int q = 0; q < R; ++q) pb[q] = B[r][q];
+      }
+#pragma unroll
+    for (int r = 0; r < S; ++r) {
+      if (r == p) stepof[r] = k;
+      if ((used >> r) & 1u) continue;
+      const double l = A[r][k] / pv[k];
+#pragma unroll
+      for (int j = k + 1; j < S; ++j) A[r][j] = A[r][j] - l * pv[j];
+#pragma unroll
+      for (int q = 0; q < R; ++q) B[r][q] = B[r][q] - l * pb[q];
+    }
+  }
+  double xs[S][R];
+#pragma unroll
+  for (int k = S - 1; k >= 0; --k) {
+    const int p = pivrow[k];
+    double den = A[0][k], num[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) num[q] = B[0][q];
+#pragma unroll
+    for (int r = 1; r < S; ++r)
+      if (p == r) {
+        den = A[r][k];
+#pragma unroll
+        for (int q = 0; q < R; ++q) num[q] = B[r][q];
+      }
+#pragma unroll
+    for (int q = 0; q < R; ++q) xs[k][q] = num[q] / den;
+#pragma unroll
+    for (int r = 0; r < S; ++r)
+      if (stepof[r] < k)
+#pragma unroll
+        for (int q = 0; q < R; ++q) B[r][q] = B[r][q] - A[r][k] * xs[k][q];
+  }
+  const int64_t WC = (int64_t)S * cnt;
+  const double s2 = s * s;
+#pragma unroll
+  for (int j = 0; j < S; ++j) {
+#pragma unroll
+    for (int q = 0; q < D; ++q) a.w[q * WC + (int64_t)j * cnt + t] = xs[j][q] / s;
+    a.w[D * WC + (int64_t)j * cnt + t] = xs[j][D] / s2;
+  }
+}
+
+template <int D, int M, int NS>
+void launch_rbffd(const SolveArgs &a, hipStream_t s) {
+  hipLaunchKernelGGL((k_rbffd<D, M, NS>), dim3((unsigned)a.count), dim3(64), 0, s, a);
+}
+
+}  // namespace
+
+// (d, m, n) combinations with a compiled local-solve kernel
+bool rbffd_supported(int d, int m, int n) {
+  if (d == 2) return (m == 1 && n == 6) || (m == 2 && n == 12) || (m == 3 && n == 20) || (m == 4 && n == 30);
+  if (d == 3) return (m == 1 && n == 8) || (m == 2 && n == 20) || (m == 2 && n == 30) || (m == 3 && n == 40);
+  return false;
+}
+
+hsm_status solve_bucket(const hsm_stencils *st, const Bucket &b, const double *x_int, const double *normal_int,
+                        DevStatus *status, hipStream_t s) {
+  if (b.count == 0) return HSM_OK;
+  SolveArgs a;
+  a.x = x_int; a.normal = normal_int; a.N = st->N; a.idx = b.idx.as<int32_t>(); a.count = b.count;
+  a.start = b.start; a.w = b.w.as<double>(); a.wall = (b.type == B_DIR || b.type == B_NEU);
+  a.perm = st->perm.as<int32_t>(); a.status = status;
+  const int d = st->d;
+  if (b.type == B_REG) {
+    const unsigned g = (unsigned)((b.count + 127) / 128);
+    if (d == 2) hipLaunchKernelGGL(k_mon<2>, dim3(g), dim3(128), 0, s, a);
+    else hipLaunchKernelGGL(k_mon<3>, dim3(g), dim3(128), 0, s, a);
+  } else {
+    const int m = b.m, n = b.width;
+    if (d == 2 && m == 1 && n == 6) launch_rbffd<2, 1, 6>(a, s);
+    else if (d == 2 && m == 2 && n == 12) launch_rbffd<2, 2, 12>(a, s);
+    else if (d == 2 && m == 3 && n == 20) launch_rbffd<2, 3, 20>(a, s);
+    else if (d == 2 && m == 4 && n == 30) launch_rbffd<2, 4, 30>(a, s);
+    else if (d == 3 && m == 1 && n == 8) launch_rbffd<3, 1, 8>(a, s);
+    else if (d == 3 && m == 2 && n == 20) launch_rbffd<3, 2, 20>(a, s);
+    else if (d == 3 && m == 2 && n == 30) launch_rbffd<3, 2, 30>(a, s);
+    else if (d == 3 && m == 3 && n == 40) launch_rbffd<3, 3, 40>(a, s);
+    else {
+      set_error(HSM_E_INVALID, "no local-solve kernel for this (d, m, n)");
+      return HSM_E_INVALID;
+    }
+  }
+  HSM_HIP(hipGetLastError());
+  return HSM_OK;
+}
+
+}  // namespace hsm

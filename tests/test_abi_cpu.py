@@ -1,0 +1,59 @@
+"""CPU checks of the C ABI: the library loads and exports every declared symbol,
+and argument validation rejects bad input before touching the GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hsm.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(hsm_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for required in ("hsm_build_stencils", "hsm_apply_operator", "hsm_step"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2303_01760_amd import hsm
+    L = hsm.lib()
+    missing = [n for n in _declared() if not hasattr(L, n)]
+    assert not missing, missing
+    assert set(hsm.SYMBOLS) == set(_declared())
+    assert b"gfx950" in L.hsm_version()
+
+
+def test_build_rejects_bad_arguments_without_a_gpu():
+    from paper_2303_01760_amd import hsm
+    L = hsm.lib()
+    out = ctypes.c_void_p()
+    assert L.hsm_build_stencils(None, 0, None, ctypes.byref(out)) == hsm.E_INVALID
+    import numpy as np
+    offs = np.array([0, 100], np.int64)
+    h = np.array([0.1]); m = np.array([7], np.int32)
+    ns = hsm.NodeSetC(2, 1, offs.ctypes.data, 1, 1, 1, h.ctypes.data, m.ctypes.data, None)
+    assert L.hsm_build_stencils(ctypes.byref(ns), 0, None, ctypes.byref(out)) == hsm.E_INVALID
+    assert b"unsupported" in L.hsm_last_error()
+    m[0] = 2
+    ns.d = 4
+    assert L.hsm_build_stencils(ctypes.byref(ns), 0, None, ctypes.byref(out)) == hsm.E_INVALID
+    ns.d = 2
+    offs[1] = 5   # domain smaller than the stencil
+    assert L.hsm_build_stencils(ctypes.byref(ns), 0, None, ctypes.byref(out)) == hsm.E_INVALID
+    assert out.value is None
+
+
+def test_apply_rejects_bad_arguments():
+    from paper_2303_01760_amd import hsm
+    L = hsm.lib()
+    assert L.hsm_apply_operator(None, 1, 0, None, None, None) == hsm.E_INVALID
+    assert L.hsm_permute(None, 0, 0, None, None, None) == hsm.E_INVALID
+    assert L.hsm_step(None, 1, None) == hsm.E_INVALID

@@ -1,0 +1,236 @@
+"""GPU parity of the explicit Boussinesq time step against the FP64 oracle.
+
+FP64 form: after 100 steps on the differentially heated cavity, every field
+agrees with the oracle within a relative L2 tolerance of 1e-8.  Both sides
+solve each pressure problem to a relative residual of 1e-12 on a system whose
+condition number is ~3e6, so the two pressures may differ by up to ~3e-6
+relative per step in the worst case; 1e-8 leaves two decades of margin over
+what the two converged solves actually differ by (printed by the test).
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2303_01760_amd import nodegen as ng
+
+pytestmark = pytest.mark.gpu
+
+FIELD_TOL = 1e-8
+
+
+def _hsm():
+    from paper_2303_01760_amd import hsm
+    return hsm
+
+
+def _build(s, m=2, mode=0):
+    hsm = _hsm()
+    dev = torch.device("cuda")
+    return hsm.build_stencils(torch.tensor(s.x, device=dev), torch.tensor(s.kind, device=dev),
+                              torch.tensor(s.normal, device=dev), s.h, m, mode=mode)
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def _cavity_init(s, T_ref=0.5):
+    v = np.zeros((2, s.n))
+    T = np.where(s.kind == 1, s.tbc, T_ref).astype(np.float64)
+    return v, T
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_cavity_100_steps_parity(mode):
+    hsm = _hsm()
+    s = ng.cavity2d()
+    dt = 0.1 * s.h ** 2 / 2      # the paper's time-step rule (Section 3)
+    prm = dict(Ra=1e4, Pr=0.71, dt=dt, T_ref=0.5)
+    st = _build(s, 2, mode)
+    v, T = _cavity_init(s)
+    dev = torch.device("cuda")
+    sim = hsm.Sim(st, torch.tensor(v, device=dev), torch.tensor(T, device=dev), krylov_tol=1e-12, **prm)
+    sim.step(100)
+    stats = sim.stats()
+    assert stats["status"] == 0 and stats["steps"] == 100
+    vg, Tg, pg = [a.cpu().numpy() for a in sim.read()]
+    ora = O.to_csr(O.build(s.x, s.kind, s.normal, s.h, 2, mode=mode))
+    osim = O.Sim(ora, s.kind)
+    vo, To = v.copy(), T.copy()
+    po = np.zeros(s.n + 1)
+    its = osim.step(vo, To, po, 100, tol=1e-12, **prm)
+    ev, eT, ep = _rel(vg, vo), _rel(Tg, To), _rel(pg, po[:-1])
+    print(f"mode {mode}: rel L2 err v {ev:.2e} T {eT:.2e} p {ep:.2e}; krylov iters gpu {stats['krylov_iters_total']} "
+          f"oracle {int(its.sum())}; |v|max {np.abs(vo).max():.3e}")
+    assert ev <= FIELD_TOL and eT <= FIELD_TOL and ep <= FIELD_TOL
+    assert abs(stats["krylov_iters_total"] - int(its.sum())) <= 0.1 * its.sum() + 10
+
+
+def test_graph_replay_matches_direct_launches():
+    # every replay of the captured graphs against the same kernels launched
+    # directly, with host reads in between; reductions are deterministic, so
+    # the two must agree bit for bit after each batch of steps
+    hsm = _hsm()
+    s = ng.cavity2d(h=0.025, seed=77)
+    dt = 0.1 * s.h ** 2 / 2
+    st = _build(s)
+    v, T = _cavity_init(s)
+    dev = torch.device("cuda")
+    sims = [hsm.Sim(st, torch.tensor(v, device=dev), torch.tensor(T, device=dev), Ra=1e5, Pr=0.71, dt=dt, T_ref=0.5,
+                    launch_mode=lm, krylov_chunk=8) for lm in (0, 1)]
+    for rep in range(4):
+        outs = []
+        for sim in sims:
+            sim.step(3)
+            outs.append([a.cpu().numpy() for a in sim.read()])
+            torch.cuda.synchronize()
+        for a, b in zip(*outs):
+            assert np.array_equal(a, b), f"replay {rep} differs"
+    assert sims[0].stats()["krylov_iters_total"] == sims[1].stats()["krylov_iters_total"]
+
+
+def test_conduction_fixed_point_on_gpu():
+    hsm = _hsm()
+    s = ng.cavity2d(h=0.04, seed=5)
+    st = _build(s)
+    T = (1.0 - s.x[0]).copy()
+    dev = torch.device("cuda")
+    sim = hsm.Sim(st, torch.zeros((2, s.n), dtype=torch.float64, device=dev), torch.tensor(T, device=dev),
+                  Ra=0.0, Pr=0.71, dt=1e-4, T_ref=0.5)
+    sim.step(10)
+    vg, Tg, pg = [a.cpu().numpy() for a in sim.read()]
+    assert np.abs(vg).max() == 0.0 and np.abs(pg).max() == 0.0
+    assert np.abs(Tg - T).max() < 1e-10
+
+
+def test_zero_rayleigh_heat_steps_match_oracle():
+    hsm = _hsm()
+    s = ng.cavity2d(h=0.04, seed=6)
+    st = _build(s)
+    rng = np.random.default_rng(1)
+    T = np.where(s.kind == 1, s.tbc, rng.random(s.n))
+    dev = torch.device("cuda")
+    sim = hsm.Sim(st, torch.zeros((2, s.n), dtype=torch.float64, device=dev), torch.tensor(T, device=dev),
+                  Ra=0.0, Pr=0.71, dt=2e-4, T_ref=0.5)
+    sim.step(10)
+    Tg = sim.read()[1].cpu().numpy()
+    ora = O.to_csr(O.build(s.x, s.kind, s.normal, s.h, 2))
+    To, vo, po = T.copy(), np.zeros((2, s.n)), np.zeros(s.n + 1)
+    O.Sim(ora, s.kind).step(vo, To, po, 10, Ra=0.0, Pr=0.71, dt=2e-4, T_ref=0.5)
+    assert np.abs(Tg - To).max() <= 1e-12 * np.abs(To).max()
+
+
+def test_obstacle_domain_3d_parity_short():
+    hsm = _hsm()
+    s = ng.obstacles3d(h=0.05, n_obst=3, rmin=0.08, rmax=0.15, band=0.1, seed=12)
+    dt = 0.1 * s.h ** 2 / 2
+    prm = dict(Ra=1e4, Pr=0.71, dt=dt, T_ref=0.5)
+    st = _build(s)
+    v = np.zeros((3, s.n))
+    T = np.where(s.kind == 1, s.tbc, 0.0)
+    dev = torch.device("cuda")
+    sim = hsm.Sim(st, torch.tensor(v, device=dev), torch.tensor(T, device=dev), **prm)
+    sim.step(10)
+    vg, Tg, pg = [a.cpu().numpy() for a in sim.read()]
+    ora = O.to_csr(O.build(s.x, s.kind, s.normal, s.h, 2))
+    vo, To, po = v.copy(), T.copy(), np.zeros(s.n + 1)
+    O.Sim(ora, s.kind).step(vo, To, po, 10, **prm)
+    ev, eT, ep = _rel(vg, vo), _rel(Tg, To), _rel(pg, po[:-1])
+    print(f"3D: rel L2 err v {ev:.2e} T {eT:.2e} p {ep:.2e}")
+    assert ev <= FIELD_TOL and eT <= FIELD_TOL and ep <= FIELD_TOL
+
+
+def test_not_converged_is_reported():
+    hsm = _hsm()
+    s = ng.cavity2d(h=0.04, seed=8)
+    st = _build(s)
+    v, T = _cavity_init(s)
+    T = np.where(s.kind == 1, T, 0.5 + 0.3 * np.sin(5 * s.x[0]) * np.cos(3 * s.x[1]))
+    dev = torch.device("cuda")
+    sim = hsm.Sim(st, torch.tensor(v, device=dev), torch.tensor(T, device=dev), Ra=1e5, Pr=0.71, dt=1e-4, T_ref=0.5,
+                  krylov_maxiter=2, krylov_chunk=2)
+    with pytest.raises(hsm.HsmError) as e:
+        sim.step(1)
+    assert e.value.code == hsm.E_NOT_CONVERGED
+    assert sim.stats()["status"] == hsm.E_NOT_CONVERGED
+
+
+def test_unstable_time_step_trips_the_nonfinite_guard():
+    hsm = _hsm()
+    s = ng.cavity2d(h=0.04, seed=9)
+    st = _build(s)
+    v, T = _cavity_init(s)
+    dev = torch.device("cuda")
+    # 100x the paper's stable time step: the explicit scheme blows up
+    sim = hsm.Sim(st, torch.tensor(v, device=dev), torch.tensor(T, device=dev), Ra=1e5, Pr=0.71,
+                  dt=100 * 0.1 * s.h ** 2 / 2, T_ref=0.5, krylov_maxiter=300)
+    with pytest.raises(hsm.HsmError) as e:
+        for _ in range(200):
+            sim.step(1)
+    assert e.value.code in (hsm.E_NONFINITE, hsm.E_NOT_CONVERGED)
+
+
+def test_large_2d_heat_sampled_parity():
+    # full 20-obstacle node set, Ra = 0 (velocity stays exactly 0): one step of
+    # T' = T + dt Lap T, with the Neumann walls, checked at sampled nodes
+    hsm = _hsm()
+    s = ng.obstacles2d()
+    st = _build(s)
+    rng = np.random.default_rng(2)
+    T = np.where(s.kind == 1, s.tbc, np.sin(7 * s.x[0]) * np.cos(5 * s.x[1]))
+    dt = 0.1 * s.h ** 2 / 2
+    dev = torch.device("cuda")
+    sim = hsm.Sim(st, torch.zeros((2, s.n), dtype=torch.float64, device=dev), torch.tensor(T, device=dev),
+                  Ra=0.0, Pr=0.71, dt=dt, T_ref=0.5)
+    sim.step(1)
+    vg, Tg, _ = [a.cpu().numpy() for a in sim.read()]
+    assert np.abs(vg).max() == 0.0
+    interior = np.where(s.kind == 0)[0]
+    neu = np.where(s.kind == 2)[0]
+    q = np.sort(np.concatenate([rng.choice(interior, 100, replace=False), rng.choice(neu, 10, replace=False)]))
+    ora = O.build(s.x, s.kind, s.normal, s.h, 2, queries=q)
+
+    def heat(i, stn):
+        wd = stn["width"]
+        return T[i] + dt * float(stn["w"][2, :wd] @ T[stn["idx"][:wd]])
+
+    for k, i in enumerate(q):
+        wd = ora["width"][k]
+        row = dict(width=wd, w=ora["w"][k], idx=ora["idx"][k])
+        if s.kind[i] == 0:
+            ref = heat(i, row)
+        else:
+            nb = ora["idx"][k, 1:wd]
+            sub = O.build(s.x, s.kind, s.normal, s.h, 2, queries=nb)
+            Tn = np.array([heat(j, dict(width=sub["width"][a], w=sub["w"][a], idx=sub["idx"][a]))
+                           for a, j in enumerate(nb)])
+            ref = -float(ora["wn"][k, 1:wd] @ Tn) / ora["wn"][k, 0]
+        assert abs(Tg[i] - ref) <= 1e-12 * max(1.0, abs(ref)), (i, Tg[i], ref)
+
+
+def test_large_2d_steps_properties():
+    # full-size hybrid and all-scattered runs: converged solves, zero-mean
+    # pressure, finite fields, bit-identical reruns
+    hsm = _hsm()
+    s = ng.obstacles2d()
+    dt = 0.1 * s.h ** 2 / 2
+    T = np.where(s.kind == 1, s.tbc, 0.0)
+    dev = torch.device("cuda")
+    for mode in (0, 1):
+        st = _build(s, 2, mode)
+        res = []
+        for rep in range(2):
+            sim = hsm.Sim(st, torch.zeros((2, s.n), dtype=torch.float64, device=dev), torch.tensor(T, device=dev),
+                          Ra=1e5, Pr=0.71, dt=dt, T_ref=0.5, krylov_tol=1e-10)
+            sim.step(3)
+            stats = sim.stats()
+            assert stats["status"] == 0
+            vg, Tg, pg = [a.cpu().numpy() for a in sim.read()]
+            assert np.isfinite(vg).all() and np.isfinite(Tg).all() and np.isfinite(pg).all()
+            assert abs(pg.sum()) <= 1e-8 * np.abs(pg).sum() + 1e-300
+            res.append((vg, Tg, pg))
+            print(f"mode {mode}: krylov iters {stats['krylov_iters_total']} relres {stats['last_relres']:.2e} "
+                  f"node-applies {stats['node_applies']}")
+        for a, b in zip(*res):
+            assert np.array_equal(a, b)
