@@ -168,6 +168,8 @@ typedef struct {
   int32_t field_dtype;     /* HSM_F64, or HSM_F32_COMP for FP32 fields with compensated applies */
   int32_t krylov_chunk;    /* iterations per device-side batch between convergence checks (0 = default) */
   int32_t launch_mode;     /* 0: replay captured HIP graphs, 1: launch kernels directly (same kernels) */
+  int32_t profile;         /* 1: time every kernel of each step and the first Krylov iteration of each batch with HIP events */
+  int32_t pad;
 } hsm_sim_params;
 
 typedef struct {
@@ -209,7 +211,32 @@ hsm_status hsm_sim_get_stats(hsm_sim *sim, hsm_sim_stats *out);
 /* Copy v [d][N], T [N], p [N] (caller numbering, FP64) out; NULL skips a field. */
 hsm_status hsm_sim_read(hsm_sim *sim, double *v, double *T, double *p, void *stream);
 
+/* Kernels timed in profile mode, in this order. */
+enum { HSM_K_PREDICT = 0, HSM_K_RHS = 1, HSM_K_BICG_PV = 2, HSM_K_BICG_ST = 3, HSM_K_BICG_XR = 4,
+       HSM_K_CORRECT_HEAT = 5, HSM_K_NEUMANN = 6, HSM_K_COUNT = 7 };
+
+/*
+ * hsm_sim_kernel_times -- in profile mode, the mean device duration (ms) of
+ * each kernel above over every timed launch so far, and the launch counts
+ * (both arrays [HSM_K_COUNT], host).  Synchronises.  HSM_E_INVALID unless the
+ * simulation was created with profile = 1.
+ */
+hsm_status hsm_sim_kernel_times(hsm_sim *sim, double *host_mean_ms, int64_t *host_count);
+
+/* The per-step pressure-operator bytes and node counts behind the timings:
+ * host_info[0] = N, [1] = total stencil entries (nnz), [2] = interior nodes,
+ * [3] = Neumann-wall nodes. */
+hsm_status hsm_sim_sizes(hsm_sim *sim, int64_t *host_info);
+
 void hsm_sim_destroy(hsm_sim *sim);
+
+/*
+ * hsm_stream_copy -- plain streaming copy of `bytes` (a multiple of 16) from
+ * src to dst on `stream`, 16 bytes per thread per step.  A measurement aid:
+ * it calibrates achievable HBM bandwidth and the hardware byte counters
+ * against a kernel whose traffic is known exactly.
+ */
+hsm_status hsm_stream_copy(const void *src, void *dst, int64_t bytes, void *stream);
 void hsm_stencils_destroy(hsm_stencils *st);
 
 const char *hsm_last_error(void);

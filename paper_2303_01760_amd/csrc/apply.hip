@@ -111,6 +111,23 @@ __global__ __launch_bounds__(kBS) void k_apply(ApplyArgs a) {
   }
 }
 
+// Four independent 16-byte loads in flight per thread, nontemporal (streamed
+// data is not reused), grid-stride over the buffer.
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256) void k_stream_copy(const v4i *__restrict__ src, v4i *__restrict__ dst, int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; i + 3 * stride < n; i += 4 * stride) {
+    v4i v[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] = __builtin_nontemporal_load(src + i + k * stride);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) __builtin_nontemporal_store(v[k], dst + i + k * stride);
+  }
+  for (; i < n; i += stride) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
+}
+
 __global__ void k_to_f32(const double *src, float *dst, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) dst[i] = (float)src[i];
@@ -201,3 +218,20 @@ hsm_status apply_impl(const hsm_stencils *st, uint32_t op_mask, int32_t dtype, c
 }
 
 }  // namespace hsm
+
+extern "C" hsm_status hsm_stream_copy(const void *src, void *dst, int64_t bytes, void *stream) {
+  using namespace hsm;
+  if (!src || !dst || bytes < 0 || (bytes % 16) != 0) {
+    set_error(HSM_E_INVALID, "hsm_stream_copy needs non-NULL buffers and a byte count that is a multiple of 16");
+    return HSM_E_INVALID;
+  }
+  const int64_t n = bytes / 16;
+  if (n == 0) return HSM_OK;
+  // 256 CUs x 8 blocks of 256 threads resident; grid-stride beyond
+  int64_t blocks = (n + 1023) / 1024;
+  if (blocks > 256 * 8) blocks = 256 * 8;
+  hipLaunchKernelGGL(k_stream_copy, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, (const v4i *)src,
+                     (v4i *)dst, n);
+  HSM_HIP(hipGetLastError());
+  return HSM_OK;
+}

@@ -42,7 +42,8 @@ class StencilsInfoC(ctypes.Structure):
 class SimParamsC(ctypes.Structure):
     _fields_ = [("Ra", ctypes.c_double), ("Pr", ctypes.c_double), ("dt", ctypes.c_double),
                 ("T_ref", ctypes.c_double), ("krylov_tol", ctypes.c_double), ("krylov_maxiter", ctypes.c_int32),
-                ("field_dtype", ctypes.c_int32), ("krylov_chunk", ctypes.c_int32), ("launch_mode", ctypes.c_int32)]
+                ("field_dtype", ctypes.c_int32), ("krylov_chunk", ctypes.c_int32), ("launch_mode", ctypes.c_int32),
+                ("profile", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
 class SimStatsC(ctypes.Structure):
@@ -57,7 +58,8 @@ _lib = None
 SYMBOLS = ["hsm_build_stencils", "hsm_stencils_get_info", "hsm_stencils_export", "hsm_permute",
            "hsm_apply_operator", "hsm_apply_node_count", "hsm_sim_create", "hsm_step", "hsm_sim_get_stats",
            "hsm_sim_read", "hsm_sim_destroy", "hsm_stencils_destroy", "hsm_last_error", "hsm_last_error_node",
-           "hsm_version"]
+           "hsm_version", "hsm_sim_kernel_times", "hsm_sim_sizes", "hsm_stream_copy"]
+KERNELS = ["predict", "rhs", "bicg_pv", "bicg_st", "bicg_xr", "correct_heat", "neumann"]
 
 
 def lib():
@@ -96,6 +98,12 @@ def lib():
         L.hsm_last_error.argtypes = []
         L.hsm_last_error_node.restype = ctypes.c_int64
         L.hsm_last_error_node.argtypes = []
+        L.hsm_sim_kernel_times.restype = st
+        L.hsm_sim_kernel_times.argtypes = [_p, _p, _p]
+        L.hsm_sim_sizes.restype = st
+        L.hsm_sim_sizes.argtypes = [_p, _p]
+        L.hsm_stream_copy.restype = st
+        L.hsm_stream_copy.argtypes = [_p, _p, ctypes.c_int64, _p]
         L.hsm_version.restype = ctypes.c_char_p
         L.hsm_version.argtypes = []
         _lib = L
@@ -212,6 +220,13 @@ def build_stencils(x: torch.Tensor, kind: torch.Tensor, normal: torch.Tensor, h,
     return Stencils(h_out.value, d, N)
 
 
+def stream_copy(src: torch.Tensor, dst: torch.Tensor, stream=None):
+    """hsm_stream_copy: plain device copy (measurement aid)."""
+    nbytes = src.numel() * src.element_size()
+    assert dst.numel() * dst.element_size() >= nbytes
+    _check(lib().hsm_stream_copy(_dptr(src), _dptr(dst), nbytes, _stream(stream)))
+
+
 def apply_operator(st: Stencils, op_mask: int, dtype: int, u: torch.Tensor, out: torch.Tensor, stream=None):
     _check(lib().hsm_apply_operator(st.handle, int(op_mask), int(dtype), _dptr(u), _dptr(out), _stream(stream)))
 
@@ -221,9 +236,10 @@ class Sim:
 
     def __init__(self, st: Stencils, v: torch.Tensor, T: torch.Tensor, p=None, *, Ra, Pr, dt, T_ref,
                  krylov_tol=1e-12, krylov_maxiter=20000, field_dtype=F64, krylov_chunk=0, launch_mode=0,
-                 stream=None):
+                 profile=0, stream=None):
         self.st = st
-        prm = SimParamsC(Ra, Pr, dt, T_ref, krylov_tol, krylov_maxiter, field_dtype, krylov_chunk, launch_mode)
+        prm = SimParamsC(Ra, Pr, dt, T_ref, krylov_tol, krylov_maxiter, field_dtype, krylov_chunk, launch_mode,
+                         profile, 0)
         h = _p()
         _check(lib().hsm_sim_create(st.handle, ctypes.byref(prm), _dptr(v, torch.float64), _dptr(T, torch.float64),
                                     None if p is None else _dptr(p, torch.float64), _stream(stream),
@@ -241,6 +257,18 @@ class Sim:
         if rc not in (OK, E_NONFINITE, E_NOT_CONVERGED):
             _check(rc)
         return d
+
+    def kernel_times(self) -> dict:
+        """Mean device ms and launch count of each timed kernel (profile mode)."""
+        ms = np.zeros(len(KERNELS))
+        cnt = np.zeros(len(KERNELS), np.int64)
+        _check(lib().hsm_sim_kernel_times(self._h, ms.ctypes.data, cnt.ctypes.data))
+        return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(KERNELS)}
+
+    def sizes(self) -> dict:
+        info = np.zeros(4, np.int64)
+        _check(lib().hsm_sim_sizes(self._h, info.ctypes.data))
+        return dict(N=int(info[0]), nnz=int(info[1]), n_interior=int(info[2]), n_neumann=int(info[3]))
 
     def read(self, stream=None):
         d, N = self.st.d, self.st.n

@@ -222,7 +222,7 @@ def test_large_2d_steps_properties():
         res = []
         for rep in range(2):
             sim = hsm.Sim(st, torch.zeros((2, s.n), dtype=torch.float64, device=dev), torch.tensor(T, device=dev),
-                          Ra=1e5, Pr=0.71, dt=dt, T_ref=0.5, krylov_tol=1e-10)
+                          Ra=1e5, Pr=0.71, dt=dt, T_ref=0.5, krylov_tol=1e-10, krylov_maxiter=200000)
             sim.step(3)
             stats = sim.stats()
             assert stats["status"] == 0
