@@ -29,23 +29,37 @@ sys.path.insert(0, ROOT)
 
 METRIC = "stencil node-applies/s + weight solves/s, hybrid vs all-scattered, 1 GPU"
 HBM_PEAK_GBS = 8000.0
+KRYLOV_CHUNK = 16      # BiCGSTAB iterations per queued batch
+PMC_COMMAND = ('rocprofv3 --pmc {} --kernel-include-regex "k_bicg_pv|k_bicg_st|k_stream_copy" --output-format csv '
+               '-d <dir> -o run -- python3 bench.py --steps 1 --warmup 0 --time-steps 1 --no-cpu-baseline '
+               '--skip-all-scattered')
 PROFILES = os.path.join(ROOT, "profiles")
-TRAFFIC_FILE = os.path.join(PROFILES, "traffic_bicg_pv_obstacles2d_h0.002.json")
-SIM_SRC = os.path.join(ROOT, "paper_2303_01760_amd", "csrc", "sim.hip")
+TRAFFIC_FILE = os.path.join(PROFILES, "traffic_bicg_iteration_obstacles2d_h0.002.json")
+# device code the traffic record was measured on (the kernels and their shared helpers)
+KERNEL_SRCS = [os.path.join(ROOT, "paper_2303_01760_amd", "csrc", f) for f in ("sim_kernels.h", "hsm_internal.h")]
+
+
+def kernel_source_sha():
+    h = hashlib.sha256()
+    for f in KERNEL_SRCS:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_bytes(sizes_buckets, N, D, kernel):
+def kernel_bytes(sizes_buckets, N, kernel):
     """Algorithmic HBM bytes of one launch (FP64 values, int32 indices; every
     array element read or written once).  sizes_buckets: [(type, width, count)]."""
     nnz = sum(w * c for _, w, c in sizes_buckets)
-    if kernel == "bicg_pv":    # idx + weights; gather s, t, p, v; read x, rh; write x, r, p, v
-        return 12 * nnz + 80 * N
+    if kernel == "bicg_pv":    # idx + weights; gather (s,t), (p,v); read x, rh; write x, (p,v), (r,v)
+        return 12 * nnz + 88 * N
     if kernel == "bicg_st":    # idx + weights; gather r, v; read rh; write s, t
         return 12 * nnz + 40 * N
+    if kernel == "iteration":  # one BiCGSTAB iteration = one launch of each
+        return kernel_bytes(sizes_buckets, N, "bicg_pv") + kernel_bytes(sizes_buckets, N, "bicg_st")
     raise ValueError(kernel)
 
 
@@ -54,16 +68,16 @@ def traffic_record():
     if not os.path.exists(TRAFFIC_FILE):
         return None
     rec = json.load(open(TRAFFIC_FILE))
-    sha = hashlib.sha256(open(SIM_SRC, "rb").read()).hexdigest()
-    if rec.get("sim_source_sha256") != sha:
+    if rec.get("kernel_source_sha256") != kernel_source_sha():
         return None
     return rec
 
 
 def pmc_summary(fetch_csv, write_csv, out_path):
     """Turn two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch)
-    into HBM bytes per launch of k_bicg_pv, scaled by what the same counters
-    read for the plain copy kernel (whose bytes are known exactly)."""
+    into HBM bytes per BiCGSTAB iteration (one launch each of k_bicg_pv and
+    k_bicg_st), scaled by what the same counters read for the plain copy
+    kernel (whose bytes are known exactly)."""
     import csv
     import statistics
 
@@ -73,7 +87,8 @@ def pmc_summary(fetch_csv, write_csv, out_path):
             if row.get("Counter_Name") != counter:
                 continue
             name = row["Kernel_Name"]
-            key = "pv" if "k_bicg_pv" in name else ("copy" if "k_stream_copy" in name else None)
+            key = ("pv" if "k_bicg_pv" in name else "st" if "k_bicg_st" in name
+                   else "copy" if "k_stream_copy" in name else None)
             if key:
                 vals.setdefault(key, []).append(float(row["Counter_Value"]) * 1024.0)
         return vals
@@ -82,17 +97,81 @@ def pmc_summary(fetch_csv, write_csv, out_path):
     copy_bytes = float(1 << 31)            # each copy launch reads and writes 2 GiB
     f_scale = copy_bytes / statistics.median(f["copy"])
     w_scale = copy_bytes / statistics.median(w["copy"])
-    # busy launches only (launches after convergence return at once)
-    fb = sorted(f["pv"])[len(f["pv"]) // 2:]
-    wb = sorted(w["pv"])[len(w["pv"]) // 2:]
-    rec = dict(kernel="k_bicg_pv<2>", workload="2D unit square minus 20 circles, h=0.002, m=2, hybrid",
-               fetch_bytes_per_launch=statistics.median(fb) * f_scale,
-               write_bytes_per_launch=statistics.median(wb) * w_scale,
-               copy_fetch_scale=f_scale, copy_write_scale=w_scale, launches=len(f["pv"]),
-               sim_source_sha256=hashlib.sha256(open(SIM_SRC, "rb").read()).hexdigest())
-    rec["hbm_bytes_per_launch"] = rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
+    # busy launches only (launches queued past convergence return at once): upper half
+    busy = lambda v: statistics.median(sorted(v)[len(v) // 2:])
+    rec = dict(kernel="BiCGSTAB iteration (k_bicg_pv<2> + k_bicg_st<2>)",
+               workload="2D unit square minus 20 circles, h=0.002, m=2, hybrid",
+               fetch_bytes_pv=busy(f["pv"]) * f_scale, write_bytes_pv=busy(w["pv"]) * w_scale,
+               fetch_bytes_st=busy(f["st"]) * f_scale, write_bytes_st=busy(w["st"]) * w_scale,
+               copy_fetch_scale=f_scale, copy_write_scale=w_scale, launches_pv=len(f["pv"]),
+               launches_st=len(f["st"]), kernel_source_sha256=kernel_source_sha(),
+               commands=[PMC_COMMAND.format(c) for c in ("FETCH_SIZE", "WRITE_SIZE")])
+    rec["hbm_bytes_per_iteration"] = sum(rec[k] for k in ("fetch_bytes_pv", "write_bytes_pv",
+                                                          "fetch_bytes_st", "write_bytes_st"))
     json.dump(rec, open(out_path, "w"), indent=1)
     print(json.dumps(rec))
+
+
+def _kname(n):
+    n = n.replace("void ", "").replace("hsm::(anonymous namespace)::", "")
+    return n.split("(")[0]
+
+
+def trace_summary(trace_csv, stats_csv, warmup, steps, chunk, command, out_path):
+    """Summarise a rocprofv3 --kernel-trace run of this script: the overall
+    per-kernel statistics; per-kernel means inside the timed region of the
+    hybrid layout (delimited by the k_bbox launch that opens every stencil
+    build); and, as the stepper's own events measure it, the mean time of one
+    BiCGSTAB iteration: the span between the ends of consecutive k_chunk_end
+    launches (one batch of `chunk` iterations) over the batches in which every
+    k_bicg_pv launch was busy (at least 3 us; launches queued past
+    convergence return at once), divided by `chunk`."""
+    import csv
+    rows = list(csv.DictReader(open(trace_csv)))
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    bbox = [int(r["Start_Timestamp"]) for r in rows if "k_bbox" in r["Kernel_Name"]]
+    end = lambda k: bbox[k] if len(bbox) > k else float("inf")
+    t0, t1 = bbox[warmup], end(warmup + steps)
+    win = [r for r in rows if t0 <= int(r["Start_Timestamp"]) < t1]
+
+    per = {}
+    for r in win:
+        d = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3
+        rec = per.setdefault(_kname(r["Kernel_Name"]), [0, 0.0, 0, 0.0])
+        rec[0] += 1
+        rec[1] += d
+        if d >= 3.0:
+            rec[2] += 1
+            rec[3] += d
+    spans, prev_end, pv = [], None, []
+    for r in win:
+        nm = r["Kernel_Name"]
+        if "k_bicg_pv" in nm:
+            pv.append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3)
+        elif "k_chunk_end" in nm:
+            e = int(r["End_Timestamp"])
+            if prev_end is not None and len(pv) == chunk and min(pv) >= 3.0:
+                spans.append((e - prev_end) * 1e-3 / chunk)
+            prev_end, pv = e, []
+        elif "k_predict" in nm:
+            prev_end, pv = None, []
+
+    lines = [f"# command: {command}", "",
+             "## all launches of the run (kernel_stats.csv)", "",
+             f"{'kernel':56s} {'calls':>8s} {'avg_us':>9s} {'pct':>7s}"]
+    for r in list(csv.DictReader(open(stats_csv)))[:14]:
+        lines.append(f"{_kname(r['Name'])[:56]:56s} {int(r['Calls']):8d} {float(r['AverageNs']) / 1e3:9.2f} "
+                     f"{float(r['Percentage']):6.2f}%")
+    lines += ["", f"## hybrid timed region (stencil builds {warmup + 1}..{warmup + steps})", "",
+              f"{'kernel':56s} {'calls':>8s} {'avg_us':>9s} {'busy':>8s} {'busy_avg_us':>12s}"]
+    for nm, (n, tot, nb, totb) in sorted(per.items(), key=lambda kv: -kv[1][1])[:10]:
+        lines.append(f"{nm[:56]:56s} {n:8d} {tot / n:9.2f} {nb:8d} {(totb / nb if nb else 0.0):12.2f}")
+    it_us = sum(spans) / len(spans) if spans else float("nan")
+    lines += ["", "## one BiCGSTAB iteration (k_bicg_pv + k_bicg_st), hybrid timed region", "",
+              f"full batches of {chunk} iterations: {len(spans)}",
+              f"mean iteration time (chunk_end-to-chunk_end span / {chunk}): {it_us:.2f} us"]
+    open(out_path, "w").write("\n".join(lines) + "\n")
+    print("\n".join(lines))
 
 
 def cpu_baseline(s, m, budget_s=12.0):
@@ -140,9 +219,17 @@ def main():
     ap.add_argument("--skip-all-scattered", action="store_true")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="summarise two rocprofv3 --pmc runs into the traffic record and exit")
+    ap.add_argument("--trace-summary", nargs=3, metavar=("TRACE_CSV", "STATS_CSV", "OUT"),
+                    help="summarise a rocprofv3 --kernel-trace run of this script (same --steps/--warmup) and exit")
+    ap.add_argument("--trace-command", default="rocprofv3 --kernel-trace --stats --output-format csv -d <dir> -o run "
+                                                "-- python3 bench.py")
     args = ap.parse_args()
     if args.pmc_summary:
         pmc_summary(args.pmc_summary[0], args.pmc_summary[1], TRAFFIC_FILE)
+        return 0
+    if args.trace_summary:
+        trace_summary(args.trace_summary[0], args.trace_summary[1], args.warmup, args.steps, KRYLOV_CHUNK,
+                      args.trace_command, args.trace_summary[2])
         return 0
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (pass --gpus 1)", file=sys.stderr)
@@ -194,8 +281,9 @@ def main():
         for f in fields:
             st.apply(st.to_internal(f), ops, hsm.F64, out=out)
         rec["applies"] += 3 * st.node_count(ops)
+        # profile=1: start/stop events around every graph launch on the stepper's stream
         sim = hsm.Sim(st, v0, T0d, Ra=1e5, Pr=0.71, dt=dt, T_ref=0.5, krylov_tol=args.tol, krylov_maxiter=200000,
-                      profile=1)
+                      krylov_chunk=KRYLOV_CHUNK, profile=1)
         sim.step(args.time_steps)
         stats = sim.stats()
         assert stats["status"] == 0, stats
@@ -203,18 +291,22 @@ def main():
         rec["krylov_iters"] += stats["krylov_iters_total"]
         rec["solves"] += s.n
         rec["info"] = info
-        rec["ktimes"] = sim.kernel_times()
+        for k, (ms, n) in sim.phase_times().items():
+            t = rec["ptimes"].setdefault(k, [0.0, 0])
+            t[0] += ms * n
+            t[1] += n
         rec["sizes"] = sim.sizes()
         return st
 
     results = {}
     modes = [("hybrid", hsm.MODE_HYBRID)] + ([] if args.skip_all_scattered else [("all_scattered", hsm.MODE_ALL_SCATTERED)])
+    fresh = lambda: dict(build_s=0.0, build_dev_ms=0.0, solve_dev_ms=0.0, applies=0, krylov_iters=0, solves=0,
+                         ptimes={})
     for name, mode in modes:
-        rec = dict(build_s=0.0, build_dev_ms=0.0, solve_dev_ms=0.0, applies=0, krylov_iters=0, solves=0)
         for _ in range(args.warmup):
-            one_step(mode, dict(rec))
+            one_step(mode, fresh())
         torch.cuda.synchronize()
-        rec = dict(build_s=0.0, build_dev_ms=0.0, solve_dev_ms=0.0, applies=0, krylov_iters=0, solves=0)
+        rec = fresh()
         t0 = time.perf_counter()
         for k in range(args.steps):
             one_step(mode, rec)
@@ -222,6 +314,7 @@ def main():
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         rec["elapsed_s"] = el
+        rec["ptimes"] = {k: (tot / n if n else float("nan"), n) for k, (tot, n) in rec["ptimes"].items()}
         results[name] = rec
         log(f"{name}: {el / args.steps * 1e3:.1f} ms/step, {rec['applies'] / el:.3e} node-applies/s, "
             f"krylov iters/step {rec['krylov_iters'] / args.steps:.0f}")
@@ -229,16 +322,18 @@ def main():
     hy = results["hybrid"]
     info = hy["info"]
     buckets = info["buckets"]
-    kt = hy["ktimes"]
-    dom = max(("bicg_pv", "bicg_st"), key=lambda k: kt[k][0])
-    bytes_launch = kernel_bytes(buckets, s.n, D, dom)
-    mean_ms = kt[dom][0]
-    achieved = bytes_launch / (mean_ms * 1e-3) / 1e9
-    tr = traffic_record() if dom == "bicg_pv" else None
+    pt = hy["ptimes"]
+    # the pressure solve dominates the step; its unit of work is one BiCGSTAB
+    # iteration (one launch each of k_bicg_pv and k_bicg_st)
+    bytes_it = kernel_bytes(buckets, s.n, "iteration")
+    it_ms = pt["krylov_iter"][0]
+    achieved = bytes_it / (it_ms * 1e-3) / 1e9
+    tr = traffic_record()
     roofline = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS,
-                    traffic=(tr["hbm_bytes_per_launch"] if tr else None), kernel="k_bicg_pv<2>" if dom == "bicg_pv"
-                    else "k_bicg_st<2>", bytes_per_launch=bytes_launch, mean_launch_ms=mean_ms,
-                    launches_timed=kt[dom][1], copy_kernel_gbs=copy_gbs)
+                    traffic=(tr["hbm_bytes_per_iteration"] if tr else None),
+                    kernel="BiCGSTAB iteration (k_bicg_pv<2> + k_bicg_st<2>)", bytes_per_launch=bytes_it,
+                    bytes_pv=kernel_bytes(buckets, s.n, "bicg_pv"), bytes_st=kernel_bytes(buckets, s.n, "bicg_st"),
+                    mean_launch_ms=it_ms, iterations_timed=pt["krylov_iter"][1], copy_kernel_gbs=copy_gbs)
     el = hy["elapsed_s"]
     out = dict(metric=METRIC, value=hy["applies"] / el, unit="node-applies/s", n_gpus=1, steps=args.steps,
                warmup=args.warmup, ms_per_step=el / args.steps * 1e3, higher_is_better=True, scaling="weak",
@@ -251,7 +346,7 @@ def main():
                            time_steps_per_step=args.time_steps, krylov_tol=args.tol),
                solves_per_s=hy["solves"] / hy["build_s"], solves_per_s_device=hy["solves"] / (hy["solve_dev_ms"] * 1e-3),
                krylov_iters_per_time_step=hy["krylov_iters"] / (args.steps * args.time_steps),
-               kernel_mean_ms={k: v[0] for k, v in kt.items()},
+               phase_mean_ms={k: v[0] for k, v in pt.items()},
                roofline=roofline)
     if "all_scattered" in results:
         a = results["all_scattered"]
@@ -259,11 +354,10 @@ def main():
                                     krylov_iters_per_time_step=a["krylov_iters"] / (args.steps * args.time_steps),
                                     solves_per_s=a["solves"] / a["build_s"],
                                     solves_per_s_device=a["solves"] / (a["solve_dev_ms"] * 1e-3),
-                                    kernel_mean_ms={k: v[0] for k, v in a["ktimes"].items()})
+                                    phase_mean_ms={k: v[0] for k, v in a["ptimes"].items()})
         out["hybrid_speedup_per_step"] = a["elapsed_s"] / el
         # per-iteration cost ratio of the pressure operator (same node set, same kernels)
-        out["hybrid_speedup_per_krylov_iteration"] = (a["ktimes"]["bicg_pv"][0] + a["ktimes"]["bicg_st"][0]) / \
-            (kt["bicg_pv"][0] + kt["bicg_st"][0])
+        out["hybrid_speedup_per_krylov_iteration"] = a["ptimes"]["krylov_iter"][0] / it_ms
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(s, args.m)

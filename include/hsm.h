@@ -168,7 +168,7 @@ typedef struct {
   int32_t field_dtype;     /* HSM_F64, or HSM_F32_COMP for FP32 fields with compensated applies */
   int32_t krylov_chunk;    /* iterations per device-side batch between convergence checks (0 = default) */
   int32_t launch_mode;     /* 0: replay captured HIP graphs, 1: launch kernels directly (same kernels) */
-  int32_t profile;         /* 1: time every kernel of each step and the first Krylov iteration of each batch with HIP events */
+  int32_t profile;         /* 1: bracket each phase (pre, Krylov batch, post) with HIP events; see hsm_sim_phase_times */
   int32_t pad;
 } hsm_sim_params;
 
@@ -211,17 +211,20 @@ hsm_status hsm_sim_get_stats(hsm_sim *sim, hsm_sim_stats *out);
 /* Copy v [d][N], T [N], p [N] (caller numbering, FP64) out; NULL skips a field. */
 hsm_status hsm_sim_read(hsm_sim *sim, double *v, double *T, double *p, void *stream);
 
-/* Kernels timed in profile mode, in this order. */
-enum { HSM_K_PREDICT = 0, HSM_K_RHS = 1, HSM_K_BICG_PV = 2, HSM_K_BICG_ST = 3, HSM_K_BICG_XR = 4,
-       HSM_K_CORRECT_HEAT = 5, HSM_K_NEUMANN = 6, HSM_K_COUNT = 7 };
+/* Phases timed in profile mode, in this order. */
+enum { HSM_PH_PRE = 0, HSM_PH_KRYLOV_ITER = 1, HSM_PH_POST = 2, HSM_PH_COUNT = 3 };
 
 /*
- * hsm_sim_kernel_times -- in profile mode, the mean device duration (ms) of
- * each kernel above over every timed launch so far, and the launch counts
- * (both arrays [HSM_K_COUNT], host).  Synchronises.  HSM_E_INVALID unless the
- * simulation was created with profile = 1.
+ * hsm_sim_phase_times -- in profile mode, mean device time (ms) of: the
+ * pre-Krylov phase of a step (predictor, pressure right-hand side, initial
+ * residual); one BiCGSTAB iteration (its two kernels), from the batches in
+ * which every iteration did work (batch time / batch size); the post-Krylov
+ * phase (projection, heat, walls).  host_count gets the number of steps,
+ * iterations and steps behind each mean.  Both arrays [HSM_PH_COUNT], host.
+ * Start/stop events bracket each graph launch on the stepper's stream.
+ * Synchronises.  HSM_E_INVALID unless created with profile = 1.
  */
-hsm_status hsm_sim_kernel_times(hsm_sim *sim, double *host_mean_ms, int64_t *host_count);
+hsm_status hsm_sim_phase_times(hsm_sim *sim, double *host_mean_ms, int64_t *host_count);
 
 /* The per-step pressure-operator bytes and node counts behind the timings:
  * host_info[0] = N, [1] = total stencil entries (nnz), [2] = interior nodes,

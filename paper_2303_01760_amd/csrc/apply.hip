@@ -24,6 +24,7 @@ constexpr int kMaxOps = 5;
 
 struct ApplyArgs {
   const BucketTable *tab;
+  BlockMap bm;
   const void *u;
   void *out;
   int64_t N;
@@ -91,7 +92,7 @@ __device__ __forceinline__ void apply_node(const T *__restrict__ u, T *__restric
 
 template <class T, class A>
 __global__ __launch_bounds__(kBS) void k_apply(ApplyArgs a) {
-  const BucketDesc b = select_bucket(a.tab, blockIdx.x);
+  const BucketDesc b = a.tab->b[bucket_index(a.bm, blockIdx.x)];
   const int64_t t = ((int64_t)blockIdx.x - b.block0) * kBS + threadIdx.x;
   if (t >= b.count) return;
   OpSel os;
@@ -202,8 +203,10 @@ hsm_status apply_impl(const hsm_stencils *st, uint32_t op_mask, int32_t dtype, c
     HSM_HIP(hipMemcpyAsync(st->dtab[which].p, &tab, sizeof(BucketTable), hipMemcpyHostToDevice, s));
     HSM_HIP(hipStreamSynchronize(s));
     st->dtab_blocks[which] = tab.nblocks;
+    st->bmap[which] = make_blockmap(tab);
   }
   a.tab = st->dtab[which].as<BucketTable>();
+  a.bm = st->bmap[which];
   a.u = u;
   a.out = out;
   a.N = st->N;

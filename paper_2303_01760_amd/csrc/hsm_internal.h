@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <climits>
+
 #include <string>
 #include <vector>
 
@@ -87,6 +89,14 @@ struct Bucket {
   DBuf w32;            // float  [nops][width][count] (made on first FP32 use)
 };
 
+// First block of each bucket, passed by value: the bucket index of a block
+// follows from statically indexed kernel arguments (scalar registers), so
+// the descriptor load is the only memory access and can start at once.
+struct BlockMap {
+  int64_t block0[kMaxBuckets];
+  int32_t nb, pad;
+};
+
 }  // namespace hsm
 
 struct hsm_stencils;
@@ -107,6 +117,7 @@ struct hsm_stencils {
   mutable bool w32_ready = false;
   mutable hsm::DBuf dtab[2];     // device copies of the apply bucket table (FP64, FP32 weights)
   mutable int64_t dtab_blocks[2] = {-1, -1};
+  mutable hsm::BlockMap bmap[2];
 };
 
 namespace hsm {
@@ -136,6 +147,21 @@ __device__ __forceinline__ BucketDesc select_bucket(const BucketTable *__restric
   for (int k = 1; k < nb; ++k)
     if (block >= tab->b[k].block0) bi = k;
   return tab->b[bi];
+}
+
+__device__ __forceinline__ int bucket_index(const BlockMap &bm, int64_t block) {
+  int bi = 0;
+#pragma unroll
+  for (int k = 1; k < kMaxBuckets; ++k)
+    if (k < bm.nb && block >= bm.block0[k]) bi = k;
+  return bi;
+}
+inline BlockMap make_blockmap(const BucketTable &tab) {
+  BlockMap bm{};
+  bm.nb = tab.nb;
+  for (int k = 0; k < tab.nb; ++k) bm.block0[k] = tab.b[k].block0;
+  for (int k = tab.nb; k < kMaxBuckets; ++k) bm.block0[k] = INT64_MAX;
+  return bm;
 }
 
 // Fills tab for all buckets of st (or only those whose type bit is in type_mask),

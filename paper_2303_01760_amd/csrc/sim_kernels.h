@@ -1,0 +1,622 @@
+// Device code of the time-step driver: the kernels and the device-side
+// Krylov state.  Included once, by sim.hip.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <type_traits>
+
+#include "hsm_internal.h"
+
+namespace hsm {
+namespace {
+
+constexpr int kBS = 256;
+constexpr int kNR = 3;          // partial sums of the right-hand-side kernel
+constexpr int kNA = 3;          // partial sums of the p/v kernel
+constexpr int kNB = 6;          // partial sums of the s/t kernel
+constexpr int kMaxIterChunk = 256;
+
+// Host-visible summary written once per batch of Krylov iterations.
+struct HostFlags {
+  int32_t done, iters, fail, nonfinite;
+  double relres;
+  double pad;
+};
+
+// Krylov state.  Values a kernel computes for iteration k live in slot k & 1,
+// so kernels of iteration k never overwrite what their own blocks still read.
+struct Scalars {
+  double rho[2], alpha[2];
+  double bnorm2, relres;
+  int32_t done, fail, zero_sol, nonfinite;
+  int32_t it_base, iters, early[2];   // early: 1 = |s| converged, 2 = breakdown, 3 = zero right-hand side
+  HostFlags mirror;
+};
+
+struct SimArgs {
+  const BucketTable *tab;          // device table; aux = row-scaled pressure weights [W][count]
+  BlockMap bm;
+  int64_t N;
+  double dt, Ra, Pr, T_ref, tol;
+  int32_t maxiter, chunk;
+  // fields
+  const double *v;    // [D][N]
+  double *vs;         // [D][N]
+  const double *T;    // [N]
+  double *Tn;         // [N]
+  double *vout;       // [D][N]
+  // Krylov vectors, each [N+1] (slot N: the border multiplier / zero-mean row)
+  double *x, *rh;                 // [N+1]
+  double2 *ST, *PVo, *PVn, *RV;   // pairs (s,t), (p,v) previous/this iteration, (r,v); [N+1]
+  double *partR, *partA, *partB;   // block partial sums [nblocks][kN*]
+  Scalars *sc;
+};
+
+template <class F>
+__device__ __forceinline__ void with_width2(int w, F &&f) {
+  switch (w) {
+    case 5: f(std::integral_constant<int, 5>{}); break;
+    case 6: f(std::integral_constant<int, 6>{}); break;
+    case 12: f(std::integral_constant<int, 12>{}); break;
+    case 20: f(std::integral_constant<int, 20>{}); break;
+    case 30: f(std::integral_constant<int, 30>{}); break;
+    default: break;
+  }
+}
+template <class F>
+__device__ __forceinline__ void with_width3(int w, F &&f) {
+  switch (w) {
+    case 7: f(std::integral_constant<int, 7>{}); break;
+    case 8: f(std::integral_constant<int, 8>{}); break;
+    case 20: f(std::integral_constant<int, 20>{}); break;
+    case 30: f(std::integral_constant<int, 30>{}); break;
+    case 40: f(std::integral_constant<int, 40>{}); break;
+    default: break;
+  }
+}
+template <int D, class F>
+__device__ __forceinline__ void with_width(int w, F &&f) {
+  if constexpr (D == 2) with_width2(w, f);
+  else with_width3(w, f);
+}
+
+// bucket fields as plain scalars
+struct BScal {
+  int64_t start, count, block0;
+  int32_t type, width;
+  const int32_t *idx;
+  const double *w;
+  const double *wP;
+};
+
+// Deterministic block sum of NQ values (fixed shuffle tree, then the waves in
+// order); thread 0 writes the block's partials.  No fences or atomics: the
+// consumer is a later kernel.
+template <int NQ>
+__device__ __forceinline__ void block_partials(double (&v)[NQ], double *part) {
+  __shared__ double red[kBS / 64][NQ];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < NQ; ++q)
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v[q] += __shfl_xor(v[q], o, 64);
+  if (lane == 0)
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) red[wv][q] = v[q];
+  __syncthreads();
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      double s = red[0][q];
+#pragma unroll
+      for (int k = 1; k < kBS / 64; ++k) s += red[k][q];
+      part[(int64_t)blockIdx.x * NQ + q] = s;
+    }
+}
+
+// Grid totals of a previous kernel's block partials, reduced by every block
+// in the same fixed order (so every block holds bit-identical totals).
+template <int NQ>
+__device__ __forceinline__ void reduce_prev(const double *__restrict__ part, int64_t nblk, double (&tot)[NQ]) {
+  __shared__ double red[kBS / 64][NQ];
+  __shared__ double res[NQ];
+  // all loads of the first four passes issued before any sum (same order as a plain loop)
+  constexpr int U = 4;
+  double vals[U][NQ];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int64_t b = threadIdx.x + (int64_t)u * kBS;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) vals[u][q] = (b < nblk) ? part[b * NQ + q] : 0.0;
+  }
+  double acc[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    acc[q] = vals[0][q];
+#pragma unroll
+    for (int u = 1; u < U; ++u) acc[q] += vals[u][q];
+  }
+  for (int64_t b = threadIdx.x + (int64_t)U * kBS; b < nblk; b += kBS)
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) acc[q] += part[b * NQ + q];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < NQ; ++q)
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) acc[q] += __shfl_xor(acc[q], o, 64);
+  if (lane == 0)
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) red[wv][q] = acc[q];
+  __syncthreads();
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      double s = red[0][q];
+#pragma unroll
+      for (int k = 1; k < kBS / 64; ++k) s += red[k][q];
+      res[q] = s;
+    }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) tot[q] = res[q];
+}
+
+// ------------------------------------------------------------- predictor --
+template <int D>
+__global__ __launch_bounds__(kBS) void k_predict(SimArgs a) {
+  const BucketDesc bd = a.tab->b[bucket_index(a.bm, blockIdx.x)];
+  const BScal b{bd.start, bd.count, bd.block0, bd.type, bd.width, bd.idx, static_cast<const double *>(bd.w),
+                static_cast<const double *>(bd.aux)};
+  const int64_t t = ((int64_t)blockIdx.x - b.block0) * kBS + threadIdx.x;
+  if (t >= b.count) return;
+  const int64_t N = a.N, i = b.start + t, cnt = b.count;
+  if (b.type == B_DIR || b.type == B_NEU) {
+#pragma unroll
+    for (int c = 0; c < D; ++c) a.vs[c * N + i] = 0.0;
+    return;
+  }
+  const double *__restrict__ w = b.w;
+  const int32_t *__restrict__ idx = b.idx;
+  const double *__restrict__ v = a.v;
+  double *__restrict__ vs = a.vs;
+  const double Ti = a.T[i], Tref = a.T_ref, Ra = a.Ra, Pr = a.Pr, dt = a.dt;
+  with_width<D>(b.width, [&](auto wc) __attribute__((always_inline)) {
+    constexpr int W = decltype(wc)::value;
+    double g[D][D], L[D];
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      L[c] = 0.0;
+#pragma unroll
+      for (int q = 0; q < D; ++q) g[c][q] = 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+      const int32_t nb = idx[(int64_t)j * cnt + t];
+      double wq[D + 1];
+#pragma unroll
+      for (int q = 0; q <= D; ++q) wq[q] = w[((int64_t)q * W + j) * cnt + t];
+#pragma unroll
+      for (int c = 0; c < D; ++c) {
+        const double u = v[c * N + nb];
+#pragma unroll
+        for (int q = 0; q < D; ++q) g[c][q] = fma(wq[q], u, g[c][q]);
+        L[c] = fma(wq[D], u, L[c]);
+      }
+    }
+    double vi[D];
+#pragma unroll
+    for (int q = 0; q < D; ++q) vi[q] = v[q * N + i];
+    const double buoy = (Ra * Pr) * (Ti - Tref);
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      double adv = vi[0] * g[c][0];
+#pragma unroll
+      for (int q = 1; q < D; ++q) adv = fma(vi[q], g[c][q], adv);
+      double f = fma(Pr, L[c], -adv);
+      if (c == D - 1) f += buoy;
+      vs[c * N + i] = fma(dt, f, vi[c]);
+    }
+  });
+}
+
+// ---------------------------------------- pressure rhs + initial residual --
+// b = div(v*)/dt / diag at interior nodes, 0 at walls; r0 = b - A x; rh = r0.
+template <int D>
+__global__ __launch_bounds__(kBS) void k_rhs(SimArgs a) {
+  const BucketDesc bd = a.tab->b[bucket_index(a.bm, blockIdx.x)];
+  const BScal b{bd.start, bd.count, bd.block0, bd.type, bd.width, bd.idx, static_cast<const double *>(bd.w),
+                static_cast<const double *>(bd.aux)};
+  const int64_t t = ((int64_t)blockIdx.x - b.block0) * kBS + threadIdx.x;
+  double part[kNR] = {0.0, 0.0, 0.0};  // b.b, r.r, sum x
+  const int64_t N = a.N;
+  const double lam = a.x[N];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    Scalars *sc = a.sc;
+    sc->done = 0; sc->fail = 0; sc->zero_sol = 0; sc->it_base = 0; sc->iters = 0;
+    sc->early[0] = 0; sc->early[1] = 0;
+  }
+  if (t < b.count) {
+    const int64_t i = b.start + t, cnt = b.count;
+    const double *w = b.w;
+    const double *wP = b.wP;
+    const bool wall = (b.type == B_DIR || b.type == B_NEU);
+    const double *__restrict__ x = a.x;
+    const double *__restrict__ vs = a.vs;
+    const int32_t *__restrict__ idx = b.idx;
+    const double dt = a.dt;
+    double r = 0.0, rhs = 0.0;
+    with_width<D>(b.width, [&](auto wc) __attribute__((always_inline)) {
+      constexpr int W = decltype(wc)::value;
+      double div = 0.0, Ap = 0.0;
+#pragma unroll
+      for (int j = 0; j < W; ++j) {
+        const int32_t nb = idx[(int64_t)j * cnt + t];
+        Ap = fma(wP[(int64_t)j * cnt + t], x[nb], Ap);
+        if (!wall)
+#pragma unroll
+          for (int q = 0; q < D; ++q) div = fma(w[((int64_t)q * W + j) * cnt + t], vs[q * N + nb], div);
+      }
+      if (!wall) rhs = (div / dt) / w[((int64_t)D * W + 0) * cnt + t];
+      r = rhs - (Ap + lam);
+    });
+    a.RV[i] = make_double2(r, 0.0);
+    a.rh[i] = r;
+    part[0] = rhs * rhs;
+    part[1] = r * r;
+    part[2] = x[i];
+  }
+  block_partials<kNR>(part, a.partR);
+}
+
+// ------------------------------------------------------- BiCGSTAB steps --
+// Iteration k (k = it_base + it) in two kernels.
+//   pv(k): from the s/t partials of iteration k-1: omega = (t,s)/(t,t),
+//          r_k = s - omega t, x += alpha p + omega s, rho_k = (rh, r_k),
+//          beta = (rho_k/rho_{k-1}) (alpha/omega); then p_k = r_k + beta (p - omega v)
+//          formed on the fly at every neighbour, and v_k = A p_k.
+//          (k = 0: p_0 = r_0 from the right-hand-side kernel.)
+//   st(k): from the p/v partials: convergence test on |r_k|, alpha = rho_k/(rh, v_k);
+//          then s = r_k - alpha v_k on the fly and t = A s.
+// Vectors gathered together are stored as pairs, one 16-byte load per
+// neighbour: (s, t), (p, v) (two generations) and (r, v).  The border row
+// and column (zero mean, multiplier) are slot N of every vector.
+template <int D>
+__global__ __launch_bounds__(kBS) void k_bicg_pv(SimArgs a, int it) {
+  Scalars *sc = a.sc;
+  const int par = it & 1;
+  // independent loads first (one wait), then the early exit
+  const int done = sc->done, it_base = sc->it_base;
+  const double bnorm2 = sc->bnorm2, alpha_prev = sc->alpha[par ^ 1], rho_prev = sc->rho[par ^ 1];
+  const BucketDesc bd = a.tab->b[bucket_index(a.bm, blockIdx.x)];
+  if (done) return;
+  const int64_t N = a.N, nblk = gridDim.x;
+  const int k = it_base + it;
+  const bool first = (k == 0);
+  const double bn = sqrt(bnorm2);
+  double omega = 0.0, beta = 0.0, alpha_p = 0.0, rho_k = 0.0, rN, pN;
+  int early = 0;
+  const double2 *__restrict__ ST = a.ST;
+  const double2 *__restrict__ PVo = a.PVo;
+  if (first) {
+    double tot[kNR];
+    reduce_prev<kNR>(a.partR, nblk, tot);
+    rN = -tot[2];                               // border row of r0: 0 - sum x
+    rho_k = fma(rN, rN, tot[1]);                // (rh, r0) = |r0|^2
+    pN = rN;
+    if (tot[0] == 0.0) early = 3;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      sc->bnorm2 = tot[0];
+      a.RV[N] = make_double2(rN, 0.0);
+      a.rh[N] = rN;
+      a.PVn[N] = make_double2(pN, 0.0);
+      sc->rho[par] = rho_k;
+      sc->early[par] = early;
+    }
+    if (early) return;
+  } else {
+    double tot[kNB];
+    reduce_prev<kNB>(a.partB, nblk, tot);
+    const double sN = ST[N].x, rhN = a.rh[N];
+    const double2 pvN = PVo[N];
+    const double tN = tot[5];                   // border row of t = A s: sum s
+    const double ts = fma(tN, sN, tot[0]), tt = fma(tN, tN, tot[1]);
+    const double rhs_ = fma(rhN, sN, tot[2]), rht = fma(rhN, tN, tot[3]);
+    const double ss = fma(sN, sN, tot[4]);
+    alpha_p = alpha_prev;
+    const double rho_p = rho_prev;
+    if (sqrt(ss) <= a.tol * bn) early = 1;
+    else if (tt == 0.0) early = 2;
+    else {
+      omega = ts / tt;
+      rho_k = fma(-omega, rht, rhs_);
+      if (rho_k == 0.0 || omega == 0.0) early = 2;
+      else beta = (rho_k / rho_p) * (alpha_p / omega);
+    }
+    rN = fma(-omega, tN, sN);
+    pN = fma(beta, fma(-omega, pvN.y, pvN.x), rN);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      sc->early[par] = early;
+      if (early == 1) {
+        a.x[N] = fma(alpha_p, pvN.x, a.x[N]);
+        sc->relres = sqrt(ss) / bn;
+      } else if (early == 0) {
+        a.x[N] = fma(omega, sN, fma(alpha_p, pvN.x, a.x[N]));
+        a.RV[N] = make_double2(rN, 0.0);
+        a.PVn[N] = make_double2(pN, 0.0);
+        sc->rho[par] = rho_k;
+      }
+    }
+    if (early == 2) return;
+  }
+  const BScal b{bd.start, bd.count, bd.block0, bd.type, bd.width, bd.idx, static_cast<const double *>(bd.w),
+                static_cast<const double *>(bd.aux)};
+  const int64_t t = ((int64_t)blockIdx.x - b.block0) * kBS + threadIdx.x;
+  if (early == 1) {                             // |s| converged: x += alpha p, nothing else
+    if (t < b.count) {
+      const int64_t i = b.start + t;
+      a.x[i] = fma(alpha_p, PVo[i].x, a.x[i]);
+    }
+    return;
+  }
+  double part[kNA] = {0.0, 0.0, 0.0};           // (rh, v), sum p, |r|^2
+  if (t < b.count) {
+    const int64_t i = b.start + t, cnt = b.count;
+    const int32_t *__restrict__ idx = b.idx;
+    const double *__restrict__ wP = b.wP;
+    const double2 *__restrict__ RV = a.RV;
+    double ri, pi;
+    if (first) {
+      ri = RV[i].x;
+      pi = ri;
+    } else {
+      const double2 st = ST[i], pv = PVo[i];
+      a.x[i] = fma(omega, st.x, fma(alpha_p, pv.x, a.x[i]));
+      ri = fma(-omega, st.y, st.x);
+      pi = fma(beta, fma(-omega, pv.y, pv.x), ri);
+    }
+    double acc = 0.0;
+    with_width<D>(b.width, [&](auto wc) __attribute__((always_inline)) {
+      constexpr int W = decltype(wc)::value;
+      if (first) {
+#pragma unroll
+        for (int j = 0; j < W; ++j) acc = fma(wP[(int64_t)j * cnt + t], RV[idx[(int64_t)j * cnt + t]].x, acc);
+      } else {
+#pragma unroll
+        for (int j = 0; j < W; ++j) {
+          const int32_t nb = idx[(int64_t)j * cnt + t];
+          const double2 st = ST[nb], pv = PVo[nb];
+          const double pj = fma(beta, fma(-omega, pv.y, pv.x), fma(-omega, st.y, st.x));
+          acc = fma(wP[(int64_t)j * cnt + t], pj, acc);
+        }
+      }
+    });
+    const double vi = acc + pN;
+    a.PVn[i] = make_double2(pi, vi);
+    a.RV[i] = make_double2(ri, vi);
+    part[0] = a.rh[i] * vi;
+    part[1] = pi;
+    part[2] = ri * ri;
+  }
+  block_partials<kNA>(part, a.partA);
+}
+
+template <int D>
+__global__ __launch_bounds__(kBS) void k_bicg_st(SimArgs a, int it) {
+  Scalars *sc = a.sc;
+  const int par = it & 1;
+  const int done = sc->done, it_base = sc->it_base, early = sc->early[par];
+  const double bnorm2 = sc->bnorm2, rho_k = sc->rho[par];
+  if (done) return;
+  const int64_t N = a.N, nblk = gridDim.x;
+  const int k = it_base + it;
+  if (early) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      sc->done = 1;
+      sc->iters = (early == 3) ? 0 : k;
+      if (early == 2) sc->fail = 1;
+      if (early == 3) { sc->zero_sol = 1; sc->relres = 0.0; }
+    }
+    return;
+  }
+  const BucketDesc bd = a.tab->b[bucket_index(a.bm, blockIdx.x)];
+  double tot[kNA];
+  reduce_prev<kNA>(a.partA, nblk, tot);
+  const double bn = sqrt(bnorm2);
+  const double vN = tot[1];                     // border row of v = A p: sum p
+  const double rN = a.RV[N].x;
+  const double rv = fma(a.rh[N], vN, tot[0]);
+  const double rr = fma(rN, rN, tot[2]);
+  const double relres = sqrt(rr) / bn;
+  int stop = 0;
+  if (sqrt(rr) <= a.tol * bn) stop = 1;
+  else if (k >= a.maxiter) stop = 2;
+  else if (rv == 0.0) stop = 3;
+  const double alpha = stop ? 0.0 : rho_k / rv;
+  const double sN = fma(-alpha, vN, rN);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    sc->relres = relres;
+    if (stop) {
+      sc->done = 1;
+      sc->iters = k;
+      if (stop >= 2) sc->fail = stop == 2 ? 2 : 1;
+    } else {
+      sc->alpha[par] = alpha;
+      a.PVn[N].y = vN;
+      a.RV[N].y = vN;
+      a.ST[N] = make_double2(sN, 0.0);
+    }
+  }
+  if (stop) return;
+  const BScal b{bd.start, bd.count, bd.block0, bd.type, bd.width, bd.idx, static_cast<const double *>(bd.w),
+                static_cast<const double *>(bd.aux)};
+  const int64_t t = ((int64_t)blockIdx.x - b.block0) * kBS + threadIdx.x;
+  double part[kNB] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};   // (t,s), (t,t), (rh,s), (rh,t), (s,s), sum s
+  if (t < b.count) {
+    const int64_t i = b.start + t, cnt = b.count;
+    const int32_t *__restrict__ idx = b.idx;
+    const double *__restrict__ wP = b.wP;
+    const double2 *__restrict__ RV = a.RV;
+    double acc = 0.0;
+    with_width<D>(b.width, [&](auto wc) __attribute__((always_inline)) {
+      constexpr int W = decltype(wc)::value;
+#pragma unroll
+      for (int j = 0; j < W; ++j) {
+        const double2 rv2 = RV[idx[(int64_t)j * cnt + t]];
+        acc = fma(wP[(int64_t)j * cnt + t], fma(-alpha, rv2.y, rv2.x), acc);
+      }
+    });
+    const double2 rvi = RV[i];
+    const double si = fma(-alpha, rvi.y, rvi.x);
+    const double ti = acc + sN;
+    const double rhi = a.rh[i];
+    a.ST[i] = make_double2(si, ti);
+    part[0] = ti * si;
+    part[1] = ti * ti;
+    part[2] = rhi * si;
+    part[3] = rhi * ti;
+    part[4] = si * si;
+    part[5] = si;
+  }
+  block_partials<kNB>(part, a.partB);
+}
+
+// End of a batch of iterations: advance the iteration base and publish a
+// summary for the host.
+__global__ void k_chunk_end(SimArgs a) {
+  if (threadIdx.x != 0) return;
+  Scalars *sc = a.sc;
+  if (!sc->done) sc->it_base += a.chunk;
+  HostFlags &h = sc->mirror;
+  h.done = sc->done;
+  h.iters = sc->done ? sc->iters : sc->it_base;
+  h.fail = sc->fail;
+  h.nonfinite = sc->nonfinite;
+  h.relres = sc->relres;
+  h.pad = 0.0;
+}
+
+// -------------------------------------------- projection + heat transport --
+template <int D>
+__global__ __launch_bounds__(kBS) void k_correct_heat(SimArgs a) {
+  const BucketDesc bd = a.tab->b[bucket_index(a.bm, blockIdx.x)];
+  const BScal b{bd.start, bd.count, bd.block0, bd.type, bd.width, bd.idx, static_cast<const double *>(bd.w),
+                static_cast<const double *>(bd.aux)};
+  const int64_t t = ((int64_t)blockIdx.x - b.block0) * kBS + threadIdx.x;
+  const int64_t N = a.N;
+  const bool zero = a.sc->zero_sol != 0;
+  if (zero && blockIdx.x == 0 && threadIdx.x == 0) a.x[N] = 0.0;
+  if (t >= b.count) return;
+  const int64_t i = b.start + t, cnt = b.count;
+  bool bad = false;
+  if (b.type == B_DIR || b.type == B_NEU) {
+#pragma unroll
+    for (int c = 0; c < D; ++c) a.vout[c * N + i] = 0.0;
+    if (b.type == B_DIR) a.Tn[i] = a.T[i];
+    if (zero) a.x[i] = 0.0;
+    return;
+  }
+  const double *__restrict__ w = b.w;
+  const int32_t *__restrict__ idx = b.idx;
+  const double *__restrict__ px = a.x;
+  const double *__restrict__ T = a.T;
+  const double *__restrict__ vs = a.vs;
+  double *__restrict__ vout = a.vout;
+  double *__restrict__ Tnp = a.Tn;
+  const double dt = a.dt;
+  with_width<D>(b.width, [&](auto wc) __attribute__((always_inline)) {
+    constexpr int W = decltype(wc)::value;
+    double gp[D], gT[D], LT = 0.0;
+#pragma unroll
+    for (int q = 0; q < D; ++q) { gp[q] = 0.0; gT[q] = 0.0; }
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+      const int32_t nb = idx[(int64_t)j * cnt + t];
+      const double pj = zero ? 0.0 : px[nb];
+      const double Tj = T[nb];
+#pragma unroll
+      for (int q = 0; q < D; ++q) {
+        const double wq = w[((int64_t)q * W + j) * cnt + t];
+        gp[q] = fma(wq, pj, gp[q]);
+        gT[q] = fma(wq, Tj, gT[q]);
+      }
+      LT = fma(w[((int64_t)D * W + j) * cnt + t], Tj, LT);
+    }
+    double vn[D];
+#pragma unroll
+    for (int q = 0; q < D; ++q) {
+      vn[q] = fma(-dt, gp[q], vs[q * N + i]);
+      vout[q * N + i] = vn[q];
+      bad = bad || !isfinite(vn[q]);
+    }
+    double adv = vn[0] * gT[0];
+#pragma unroll
+    for (int q = 1; q < D; ++q) adv = fma(vn[q], gT[q], adv);
+    const double Tn = fma(dt, LT - adv, T[i]);
+    Tnp[i] = Tn;
+    bad = bad || !isfinite(Tn);
+  });
+  if (zero) a.x[i] = 0.0;
+  if (bad) atomicOr(&a.sc->nonfinite, 1);
+}
+
+// Neumann walls: the temperature that zeroes the normal derivative, from the
+// new interior values (wall stencils hold the wall node and interior nodes).
+template <int D>
+__global__ __launch_bounds__(kBS) void k_neumann(SimArgs a) {
+  const BucketDesc bd = a.tab->b[bucket_index(a.bm, blockIdx.x)];
+  const BScal b{bd.start, bd.count, bd.block0, bd.type, bd.width, bd.idx, static_cast<const double *>(bd.w),
+                static_cast<const double *>(bd.aux)};
+  const int64_t t = ((int64_t)blockIdx.x - b.block0) * kBS + threadIdx.x;
+  if (t >= b.count || b.type != B_NEU) return;
+  const int64_t N = a.N, i = b.start + t, cnt = b.count;
+  const double *__restrict__ w = b.w;
+  const int32_t *__restrict__ idx = b.idx;
+  double *Tn = a.Tn;
+  Scalars *sc = a.sc;
+  with_width<D>(b.width, [&](auto wc) __attribute__((always_inline)) {
+    constexpr int W = decltype(wc)::value;
+    const double *wn = w + (int64_t)(D + 1) * W * cnt;
+    double acc = 0.0;
+#pragma unroll
+    for (int j = 1; j < W; ++j) acc = fma(wn[(int64_t)j * cnt + t], Tn[idx[(int64_t)j * cnt + t]], acc);
+    const double Tb = -acc / wn[t];
+    Tn[i] = Tb;
+    if (!isfinite(Tb)) atomicOr(&sc->nonfinite, 1);
+  });
+  (void)N;
+}
+
+// pressure-operator rows: Laplacian (interior) or normal derivative (walls), divided by the centre weight
+__global__ void k_scale_rows(const double *w, int64_t cnt, int W, int slot, double *wP) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= cnt) return;
+  const double *src = w + (int64_t)slot * W * cnt;
+  const double dg = src[t];
+  for (int j = 0; j < W; ++j) wP[(int64_t)j * cnt + t] = src[(int64_t)j * cnt + t] / dg;
+}
+
+__global__ void k_fill(double *p, int64_t n, double v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ void k_init_scalars(Scalars *sc) {
+  if (threadIdx.x == 0) {
+    memset(sc, 0, sizeof(Scalars));
+    sc->done = 1;
+  }
+}
+
+template <class T>
+__global__ void k_gather(const T *src, T *dst, const int32_t *map, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[map[i]];
+}
+
+inline unsigned nblk(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+}  // namespace
+}  // namespace hsm

@@ -58,8 +58,8 @@ _lib = None
 SYMBOLS = ["hsm_build_stencils", "hsm_stencils_get_info", "hsm_stencils_export", "hsm_permute",
            "hsm_apply_operator", "hsm_apply_node_count", "hsm_sim_create", "hsm_step", "hsm_sim_get_stats",
            "hsm_sim_read", "hsm_sim_destroy", "hsm_stencils_destroy", "hsm_last_error", "hsm_last_error_node",
-           "hsm_version", "hsm_sim_kernel_times", "hsm_sim_sizes", "hsm_stream_copy"]
-KERNELS = ["predict", "rhs", "bicg_pv", "bicg_st", "bicg_xr", "correct_heat", "neumann"]
+           "hsm_version", "hsm_sim_phase_times", "hsm_sim_sizes", "hsm_stream_copy"]
+PHASES = ["pre", "krylov_iter", "post"]
 
 
 def lib():
@@ -98,8 +98,8 @@ def lib():
         L.hsm_last_error.argtypes = []
         L.hsm_last_error_node.restype = ctypes.c_int64
         L.hsm_last_error_node.argtypes = []
-        L.hsm_sim_kernel_times.restype = st
-        L.hsm_sim_kernel_times.argtypes = [_p, _p, _p]
+        L.hsm_sim_phase_times.restype = st
+        L.hsm_sim_phase_times.argtypes = [_p, _p, _p]
         L.hsm_sim_sizes.restype = st
         L.hsm_sim_sizes.argtypes = [_p, _p]
         L.hsm_stream_copy.restype = st
@@ -258,12 +258,12 @@ class Sim:
             _check(rc)
         return d
 
-    def kernel_times(self) -> dict:
-        """Mean device ms and launch count of each timed kernel (profile mode)."""
-        ms = np.zeros(len(KERNELS))
-        cnt = np.zeros(len(KERNELS), np.int64)
-        _check(lib().hsm_sim_kernel_times(self._h, ms.ctypes.data, cnt.ctypes.data))
-        return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(KERNELS)}
+    def phase_times(self) -> dict:
+        """Mean device ms and sample count of each timed phase (profile mode)."""
+        ms = np.zeros(len(PHASES))
+        cnt = np.zeros(len(PHASES), np.int64)
+        _check(lib().hsm_sim_phase_times(self._h, ms.ctypes.data, cnt.ctypes.data))
+        return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(PHASES)}
 
     def sizes(self) -> dict:
         info = np.zeros(4, np.int64)

@@ -69,8 +69,9 @@ def test_cavity_100_steps_parity(mode):
 
 def test_graph_replay_matches_direct_launches():
     # every replay of the captured graphs against the same kernels launched
-    # directly, with host reads in between; reductions are deterministic, so
-    # the two must agree bit for bit after each batch of steps
+    # directly, and against graph replay with timing events around each graph
+    # launch, with host reads in between; reductions are deterministic, so
+    # all three must agree bit for bit after each batch of steps
     hsm = _hsm()
     s = ng.cavity2d(h=0.025, seed=77)
     dt = 0.1 * s.h ** 2 / 2
@@ -78,16 +79,25 @@ def test_graph_replay_matches_direct_launches():
     v, T = _cavity_init(s)
     dev = torch.device("cuda")
     sims = [hsm.Sim(st, torch.tensor(v, device=dev), torch.tensor(T, device=dev), Ra=1e5, Pr=0.71, dt=dt, T_ref=0.5,
-                    launch_mode=lm, krylov_chunk=8) for lm in (0, 1)]
+                    launch_mode=lm, krylov_chunk=8, profile=pf) for lm, pf in ((0, 0), (1, 0), (0, 1))]
     for rep in range(4):
         outs = []
         for sim in sims:
             sim.step(3)
             outs.append([a.cpu().numpy() for a in sim.read()])
             torch.cuda.synchronize()
-        for a, b in zip(*outs):
-            assert np.array_equal(a, b), f"replay {rep} differs"
-    assert sims[0].stats()["krylov_iters_total"] == sims[1].stats()["krylov_iters_total"]
+        for o in outs[1:]:
+            for a, b in zip(outs[0], o):
+                assert np.array_equal(a, b), f"replay {rep} differs"
+    iters = [sim.stats()["krylov_iters_total"] for sim in sims]
+    assert iters[0] == iters[1] == iters[2]
+    ph = sims[2].phase_times()
+    assert ph["pre"][1] == 12 and ph["post"][1] == 12, ph
+    # only batches in which all 8 iterations did work are timed
+    assert 0 < ph["krylov_iter"][1] <= iters[2] and ph["krylov_iter"][1] % 8 == 0, ph
+    assert all(ms > 0 for ms, _ in ph.values()), ph
+    with pytest.raises(hsm.HsmError):
+        sims[0].phase_times()
 
 
 def test_conduction_fixed_point_on_gpu():
