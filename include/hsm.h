@@ -112,13 +112,15 @@ typedef struct {
  * scaled by the stencil radius, by LU with partial pivoting.
  *
  * Supported: d = 2 with 1 <= m <= 4, d = 3 with 1 <= m <= 3, and
- * n + C(m+d, d) <= 64 (so 2D m=4 n=30 and 3D m=2 n=20 or 30 fit).
+ * n + C(m+d, d) <= 64 (so 2D m=4 n=30 and 3D m=2 n=20 or 30 fit), and at
+ * most HSM_MAX_NODES nodes in total.
  *
  * Synchronises `stream`.  Errors: HSM_E_INVALID (arguments, a domain with
  * fewer than n usable nodes), HSM_E_DUPLICATE_NODE, HSM_E_AMBIGUOUS,
  * HSM_E_SINGULAR (hsm_last_error_node names the node), HSM_E_OOM, HSM_E_HIP.
  * On success *out is a new handle.
  */
+#define HSM_MAX_NODES 268435454LL   /* (N + 1) * 16 bytes stay below 4 GiB */
 hsm_status hsm_build_stencils(const hsm_nodeset *nodes, int32_t mode, void *stream, hsm_stencils **out);
 
 hsm_status hsm_stencils_get_info(const hsm_stencils *st, hsm_stencils_info *out);

@@ -131,7 +131,8 @@ hsm_status hsm_build_stencils(const hsm_nodeset *ns, int32_t mode, void *stream,
     }
   }
   const int64_t N = off[ns->n_domains];
-  if (N >= (int64_t)INT32_MAX) { set_error(HSM_E_INVALID, "too many nodes"); return HSM_E_INVALID; }
+  // kernels address node vectors of up to 16-byte elements with 32-bit byte offsets
+  if (N > HSM_MAX_NODES) { set_error(HSM_E_INVALID, "too many nodes (at most HSM_MAX_NODES)"); return HSM_E_INVALID; }
   if (!check_ptr(ns->x, "x") || !check_ptr(ns->kind, "kind") || !check_ptr(ns->normal, "normal"))
     return HSM_E_INVALID;
   hsm_status rc = build_stencils_impl(ns, mode, (hipStream_t)stream, out);

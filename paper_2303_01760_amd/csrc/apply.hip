@@ -28,9 +28,10 @@ struct ApplyArgs {
   const void *u;
   void *out;
   int64_t N;
-  int nops;
-  int op_store[kMaxOps];   // storage slot of each requested operator, -1 = not stored (write 0)
-  int op_wall_only[kMaxOps];
+  int nops;                  // requested operators = output planes
+  int ld_slot[kMaxOps];      // storage slot of each stored operator that is computed
+  int ld_wall_only[kMaxOps]; // 1: only wall buckets hold it (normal derivative); 0 elsewhere
+  int out_src[kMaxOps];      // output plane o takes computed operator out_src[o]; -1: zero (not stored)
 };
 
 template <class T>
@@ -38,6 +39,7 @@ struct Acc {
   T s;
   __device__ __forceinline__ void init() { s = T(0); }
   __device__ __forceinline__ void add(T w, T u) { s = fma(w, u, s); }
+  __device__ __forceinline__ void settle() { pin(s); }
   __device__ __forceinline__ T get() const { return s; }
 };
 
@@ -54,62 +56,93 @@ struct Dot2 {
     s = t;
     c = c + (pe + se);
   }
+  __device__ __forceinline__ void settle() { pin(s); pin(c); }
   __device__ __forceinline__ float get() const { return s + c; }
 };
 
-// Operator selection of one launch, held in registers.
-struct OpSel {
-  int nops;
-  int slot[kMaxOps];   // storage slot, -1 = operator not stored (writes 0)
-  int wall_only[kMaxOps];
-};
-
-template <class T, class A, int W>
-__device__ __forceinline__ void apply_node(const T *__restrict__ u, T *__restrict__ out, int64_t N, const OpSel &os,
-                                           const BucketDesc &b, int64_t t) {
-  const T *__restrict__ w = static_cast<const T *>(b.w);
-  const int64_t cnt = b.count;
+// One node: NL operators computed from one pass over the stencil (the
+// indices and gathered values are shared), W entries (0: width known only
+// at run time).
+template <class T, class A, int NL, int W>
+__device__ __forceinline__ void apply_node(const ApplyArgs &a, const BucketDesc &b, int64_t t) {
+  const uint32_t cnt = (uint32_t)b.count, t32 = (uint32_t)t;
   const int width = (W > 0) ? W : b.width;
   const bool wall = (b.type == B_DIR || b.type == B_NEU);
-  bool on[kMaxOps];
+  bool live[NL];
+  uint32_t row0[NL];
 #pragma unroll
-  for (int o = 0; o < kMaxOps; ++o) on[o] = o < os.nops && os.slot[o] >= 0 && (!os.wall_only[o] || wall);
-  A acc[kMaxOps];
-#pragma unroll
-  for (int o = 0; o < kMaxOps; ++o) acc[o].init();
-#pragma unroll
-  for (int j = 0; j < width; ++j) {
-    const int32_t nb = b.idx[(int64_t)j * cnt + t];
-    const T uv = u[nb];
-#pragma unroll
-    for (int o = 0; o < kMaxOps; ++o)
-      if (on[o]) acc[o].add(w[((int64_t)os.slot[o] * width + j) * cnt + t], uv);
+  for (int k = 0; k < NL; ++k) {
+    live[k] = !a.ld_wall_only[k] || wall;
+    row0[k] = (uint32_t)((live[k] ? a.ld_slot[k] : 0) * width);   // a present row keeps every load valid
   }
+  A acc[NL];
 #pragma unroll
-  for (int o = 0; o < kMaxOps; ++o)
-    if (o < os.nops) out[(int64_t)o * N + b.start + t] = on[o] ? (T)acc[o].get() : T(0);
+  for (int k = 0; k < NL; ++k) acc[k].init();
+  const Buf ub = plane(static_cast<const T *>(a.u), a.N, 0);
+  const auto wl = [&](int j) __attribute__((always_inline)) {
+    Pack<T, NL> r;
+#pragma unroll
+    for (int k = 0; k < NL; ++k) r.v[k] = ld_soa<T>(b.w, cnt, row0[k] + j, t32);
+    return r;
+  };
+  const auto vl = [&](int32_t nb) __attribute__((always_inline)) { return ld_at<T>(ub, nb); };
+  const auto use = [&](int, const Pack<T, NL> &wv, T uv) __attribute__((always_inline)) {
+#pragma unroll
+    for (int k = 0; k < NL; ++k) acc[k].add(wv.v[k], uv);
+  };
+  if constexpr (W > 0) {
+    gather_chunks<W, 8>(b.idx, cnt, t32, wl, vl, use, [&]() __attribute__((always_inline)) {
+#pragma unroll
+      for (int k = 0; k < NL; ++k) acc[k].settle();
+    });
+  } else {
+    for (int j = 0; j < width; ++j) use(j, wl(j), vl(ld_soa<int32_t>(b.idx, cnt, j, t32)));
+  }
+  T *out = static_cast<T *>(a.out);
+  for (int o = 0; o < a.nops; ++o) {
+    const int src = a.out_src[o];
+    T val = T(0);
+#pragma unroll
+    for (int k = 0; k < NL; ++k)
+      if (src == k && live[k]) val = (T)acc[k].get();
+    out[(int64_t)o * a.N + b.start + t] = val;
+  }
 }
 
-template <class T, class A>
+template <class T, class A, int NL>
 __global__ __launch_bounds__(kBS) void k_apply(ApplyArgs a) {
   const BucketDesc b = a.tab->b[bucket_index(a.bm, blockIdx.x)];
   const int64_t t = ((int64_t)blockIdx.x - b.block0) * kBS + threadIdx.x;
   if (t >= b.count) return;
-  OpSel os;
-  os.nops = a.nops;
-#pragma unroll
-  for (int o = 0; o < kMaxOps; ++o) { os.slot[o] = a.op_store[o]; os.wall_only[o] = a.op_wall_only[o]; }
-  const T *u = static_cast<const T *>(a.u);
-  T *out = static_cast<T *>(a.out);
-  const int64_t N = a.N;
   switch (b.width) {
-    case 5: apply_node<T, A, 5>(u, out, N, os, b, t); break;
-    case 7: apply_node<T, A, 7>(u, out, N, os, b, t); break;
-    case 12: apply_node<T, A, 12>(u, out, N, os, b, t); break;
-    case 20: apply_node<T, A, 20>(u, out, N, os, b, t); break;
-    case 30: apply_node<T, A, 30>(u, out, N, os, b, t); break;
-    default: apply_node<T, A, 0>(u, out, N, os, b, t); break;
+    case 5: apply_node<T, A, NL, 5>(a, b, t); break;
+    case 6: apply_node<T, A, NL, 6>(a, b, t); break;
+    case 7: apply_node<T, A, NL, 7>(a, b, t); break;
+    case 8: apply_node<T, A, NL, 8>(a, b, t); break;
+    case 12: apply_node<T, A, NL, 12>(a, b, t); break;
+    case 20: apply_node<T, A, NL, 20>(a, b, t); break;
+    case 30: apply_node<T, A, NL, 30>(a, b, t); break;
+    case 40: apply_node<T, A, NL, 40>(a, b, t); break;
+    default: apply_node<T, A, NL, 0>(a, b, t); break;
   }
+}
+
+// A launch with nl computed operators.
+template <class T, class A>
+void launch_apply(int nl, dim3 g, dim3 bs, hipStream_t s, const ApplyArgs &a) {
+  switch (nl) {
+    case 1: hipLaunchKernelGGL((k_apply<T, A, 1>), g, bs, 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_apply<T, A, 2>), g, bs, 0, s, a); break;
+    case 3: hipLaunchKernelGGL((k_apply<T, A, 3>), g, bs, 0, s, a); break;
+    case 4: hipLaunchKernelGGL((k_apply<T, A, 4>), g, bs, 0, s, a); break;
+    default: hipLaunchKernelGGL((k_apply<T, A, 5>), g, bs, 0, s, a); break;
+  }
+}
+
+template <class T>
+__global__ void k_zero(T *p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = T(0);
 }
 
 // Four independent 16-byte loads in flight per thread, nontemporal (streamed
@@ -178,6 +211,7 @@ hsm_status apply_impl(const hsm_stencils *st, uint32_t op_mask, int32_t dtype, c
   ApplyArgs a;
   const int d = st->d;
   a.nops = 0;
+  int nl = 0;
   const uint32_t bits[5] = {HSM_OP_DX, HSM_OP_DY, HSM_OP_DZ, HSM_OP_LAP, HSM_OP_DN};
   for (int k = 0; k < 5; ++k) {
     if (!(op_mask & bits[k])) continue;
@@ -185,10 +219,17 @@ hsm_status apply_impl(const hsm_stencils *st, uint32_t op_mask, int32_t dtype, c
     if (k < 3) slot = (k < d) ? k : -1;
     else if (k == 3) slot = d;
     else { slot = d + 1; wall_only = 1; }
-    a.op_store[a.nops] = slot;
-    a.op_wall_only[a.nops] = wall_only;
+    if (slot >= 0) {
+      a.ld_slot[nl] = slot;
+      a.ld_wall_only[nl] = wall_only;
+      a.out_src[a.nops] = nl++;
+    } else {
+      a.out_src[a.nops] = -1;
+    }
     a.nops++;
   }
+  for (int k = nl; k < kMaxOps; ++k) { a.ld_slot[k] = 0; a.ld_wall_only[k] = 0; }
+  for (int o = a.nops; o < kMaxOps; ++o) a.out_src[o] = -1;
   const bool fp32 = dtype != HSM_F64;
   if (fp32) {
     hsm_status rc = ensure_w32(st, s);
@@ -213,9 +254,15 @@ hsm_status apply_impl(const hsm_stencils *st, uint32_t op_mask, int32_t dtype, c
   const int64_t nblocks = st->dtab_blocks[which];
   if (nblocks == 0 || a.nops == 0) return HSM_OK;
   const dim3 g((unsigned)nblocks), b(kBS);
-  if (dtype == HSM_F64) hipLaunchKernelGGL((k_apply<double, Acc<double>>), g, b, 0, s, a);
-  else if (dtype == HSM_F32) hipLaunchKernelGGL((k_apply<float, Acc<float>>), g, b, 0, s, a);
-  else hipLaunchKernelGGL((k_apply<float, Dot2>), g, b, 0, s, a);
+  if (nl == 0) {            // only operators that are not stored (d/dz in 2D): zeros
+    const int64_t n = (int64_t)a.nops * a.N;
+    if (dtype == HSM_F64) hipLaunchKernelGGL(k_zero<double>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                                             static_cast<double *>(out), n);
+    else hipLaunchKernelGGL(k_zero<float>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                            static_cast<float *>(out), n);
+  } else if (dtype == HSM_F64) launch_apply<double, Acc<double>>(nl, g, b, s, a);
+  else if (dtype == HSM_F32) launch_apply<float, Acc<float>>(nl, g, b, s, a);
+  else launch_apply<float, Dot2>(nl, g, b, s, a);
   HSM_HIP(hipGetLastError());
   return HSM_OK;
 }

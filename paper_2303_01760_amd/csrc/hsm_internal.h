@@ -123,6 +123,115 @@ struct hsm_stencils {
 namespace hsm {
 
 // Bucket table handed to kernels by value.
+// Raw buffer loads: a resource (base address and byte size, in scalar
+// registers), a 32-bit per-lane byte offset and a uniform 32-bit byte
+// offset.  A load costs one vector register of address, and loads at uniform
+// strides from one lane offset (the SoA stencil arrays) share it; the
+// compiler also sees plain vector-memory loads it can keep in flight
+// together (pointers read from device memory would otherwise compile to
+// flat loads, which it can only await all at once).  Reads past the stated
+// size return zero.  Each resource spans one row of a stencil array or one
+// node vector, so every offset stays below 4 GiB (the node count is capped
+// on the host).
+struct Buf {
+  __amdgpu_buffer_rsrc_t r;
+};
+constexpr int kBufDword3 = 0x00020000;   // gfx9 raw buffer: 32-bit data format, no swizzle
+__device__ __forceinline__ Buf make_buf(const void *p, uint64_t bytes) {
+  const uint32_t n = bytes > 0xffffffffull ? 0xffffffffu : (uint32_t)bytes;
+  return Buf{__builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)n, kBufDword3)};
+}
+template <class T>
+__device__ __forceinline__ T ld(const Buf &b, uint32_t voff);
+template <>
+__device__ __forceinline__ int32_t ld<int32_t>(const Buf &b, uint32_t voff) {
+  return (int32_t)__builtin_amdgcn_raw_buffer_load_b32(b.r, voff, 0, 0);
+}
+template <>
+__device__ __forceinline__ float ld<float>(const Buf &b, uint32_t voff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(b.r, voff, 0, 0));
+}
+template <>
+__device__ __forceinline__ double ld<double>(const Buf &b, uint32_t voff) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(b.r, voff, 0, 0));
+}
+template <>
+__device__ __forceinline__ double2 ld<double2>(const Buf &b, uint32_t voff) {
+  const auto q = __builtin_amdgcn_raw_buffer_load_b128(b.r, voff, 0, 0);
+  return make_double2(__builtin_bit_cast(double, (uint64_t)q[0] | ((uint64_t)q[1] << 32)),
+                      __builtin_bit_cast(double, (uint64_t)q[2] | ((uint64_t)q[3] << 32)));
+}
+// Row e (uniform) of an SoA array [rows][cnt], element t (per lane).
+template <class T>
+__device__ __forceinline__ T ld_soa(const void *base, uint32_t cnt, uint32_t e, uint32_t t) {
+  const Buf b = make_buf(static_cast<const T *>(base) + (uint64_t)e * cnt, (uint64_t)cnt * sizeof(T));
+  return ld<T>(b, t * (uint32_t)sizeof(T));
+}
+// Element nb (per lane) of a node vector held as a resource.
+template <class T>
+__device__ __forceinline__ T ld_at(const Buf &b, int32_t nb) {
+  return ld<T>(b, (uint32_t)nb * (uint32_t)sizeof(T));
+}
+// Plane c (uniform) of a [planes][n] array as a resource.
+template <class T>
+__device__ __forceinline__ Buf plane(const T *base, int64_t n, int c) {
+  return make_buf(base + (int64_t)c * n, (uint64_t)n * sizeof(T));
+}
+
+// A fixed-size bundle of values loaded together.
+template <class T, int K>
+struct Pack {
+  T v[K];
+};
+
+// Largest divisor of W that is at most K.
+constexpr int chunk_of(int W, int K) {
+  for (int c = K < W ? K : W; c > 1; --c)
+    if (W % c == 0) return c;
+  return 1;
+}
+
+// Ties a register value to this point of the program (an empty asm
+// statement that reads and writes it): the arithmetic producing it cannot be
+// sunk below.
+template <class T>
+__device__ __forceinline__ void pin(T &x) {
+  asm volatile("" : "+v"(x));
+}
+
+// Stencil gather of node t over its W entries, in chunks of C entries (the
+// largest divisor of W not above K): a chunk's indices and weights are
+// loaded, then its neighbour values, and only then consumed, in stencil
+// order, by use(j, weights, values); settle() then pins the accumulators.
+// The loads of a chunk are in flight together instead of one neighbour
+// after another, and each chunk's values die with the chunk: the pins keep
+// the accumulation from being sunk to the end, and a scheduling barrier
+// keeps the next chunk's loads from being hoisted (either would hold every
+// chunk's values live at once).  idx: the bucket's [W][cnt] neighbour indices.
+template <int W, int K = 12, class FW, class FV, class FU, class FS>
+__device__ __forceinline__ void gather_chunks(const void *idx, uint32_t cnt, uint32_t t, FW &&wload, FV &&vload,
+                                              FU &&use, FS &&settle) {
+  constexpr int C = chunk_of(W, K);
+#pragma unroll
+  for (int j0 = 0; j0 < W; j0 += C) {
+    int32_t nb[C];
+    decltype(wload(0)) wv[C];
+    decltype(vload(0)) vv[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) nb[c] = ld_soa<int32_t>(idx, cnt, j0 + c, t);
+#pragma unroll
+    for (int c = 0; c < C; ++c) wv[c] = wload(j0 + c);
+#pragma unroll
+    for (int c = 0; c < C; ++c) vv[c] = vload(nb[c]);
+#pragma unroll
+    for (int c = 0; c < C; ++c) use(j0 + c, wv[c], vv[c]);
+    if (j0 + C < W) {
+      settle();
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+}
+
 struct BucketDesc {
   int64_t start, count;
   int32_t type, width;

@@ -84,45 +84,75 @@ __device__ __forceinline__ void with_width(int w, F &&f) {
 }
 
 // bucket fields as plain scalars
+// bucket fields as plain scalars
 struct BScal {
   int64_t start, count, block0;
   int32_t type, width;
-  const int32_t *idx;
-  const double *w;
-  const double *wP;
+  uint32_t cnt;       // count
+  const void *idx;    // [width][cnt] int32
+  const void *w;      // [nops][width][cnt] double
+  const void *wP;     // [width][cnt] double: the pressure-operator rows
 };
+__device__ __forceinline__ BScal bscal(const BucketDesc &bd) {
+  return BScal{bd.start, bd.count, bd.block0, bd.type, bd.width, (uint32_t)bd.count, bd.idx, bd.w, bd.aux};
+}
 
-// Deterministic block sum of NQ values (fixed shuffle tree, then the waves in
-// order); thread 0 writes the block's partials.  No fences or atomics: the
-// consumer is a later kernel.
+// Cross-lane moves by DPP (data-parallel primitives: a VALU operand read
+// from another lane of the same row of 16), on the two halves of a double.
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(uint32_t)u, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(uint32_t)(u >> 32), CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, (uint64_t)(uint32_t)lo | ((uint64_t)(uint32_t)hi << 32));
+}
+__device__ __forceinline__ double read_lane(double v, int l) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)u, l);
+  const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), l);
+  return __builtin_bit_cast(double, (uint64_t)lo | ((uint64_t)hi << 32));
+}
+// Sum over the 64 lanes of a wave, the same value in every lane: swap
+// neighbours, then pairs (quad_perm), mirror within 8 and within 16 lanes
+// (each step adds two equal-sized partial sums, and a + b == b + a, so every
+// lane of a row holds the identical row sum), then the four row sums in a
+// fixed order.  Fixed order throughout: deterministic.
+__device__ __forceinline__ double wave_sum(double v) {
+  v += dpp_mov<0xB1>(v);    // quad_perm [1,0,3,2]
+  v += dpp_mov<0x4E>(v);    // quad_perm [2,3,0,1]
+  v += dpp_mov<0x141>(v);   // row_half_mirror
+  v += dpp_mov<0x140>(v);   // row_mirror
+  return (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
+}
+
+// Deterministic block sum of NQ values (wave sums, then the waves in order);
+// the first NQ threads write the block's partials.  No fences or atomics:
+// the consumer is a later kernel.
 template <int NQ>
 __device__ __forceinline__ void block_partials(double (&v)[NQ], double *part) {
   __shared__ double red[kBS / 64][NQ];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int wv = threadIdx.x >> 6;
 #pragma unroll
-  for (int q = 0; q < NQ; ++q)
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v[q] += __shfl_xor(v[q], o, 64);
-  if (lane == 0)
+  for (int q = 0; q < NQ; ++q) v[q] = wave_sum(v[q]);
+  if ((threadIdx.x & 63) == 0)
 #pragma unroll
     for (int q = 0; q < NQ; ++q) red[wv][q] = v[q];
   __syncthreads();
-  if (threadIdx.x == 0)
+  if (threadIdx.x < NQ) {
+    const int q = threadIdx.x;
+    double s = red[0][q];
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      double s = red[0][q];
-#pragma unroll
-      for (int k = 1; k < kBS / 64; ++k) s += red[k][q];
-      part[(int64_t)blockIdx.x * NQ + q] = s;
-    }
+    for (int k = 1; k < kBS / 64; ++k) s += red[k][q];
+    part[(int64_t)blockIdx.x * NQ + q] = s;
+  }
 }
 
 // Grid totals of a previous kernel's block partials, reduced by every block
-// in the same fixed order (so every block holds bit-identical totals).
+// (and every thread of it) in the same fixed order, so all hold bit-identical
+// totals.
 template <int NQ>
 __device__ __forceinline__ void reduce_prev(const double *__restrict__ part, int64_t nblk, double (&tot)[NQ]) {
   __shared__ double red[kBS / 64][NQ];
-  __shared__ double res[NQ];
   // all loads of the first four passes issued before any sum (same order as a plain loop)
   constexpr int U = 4;
   double vals[U][NQ];
@@ -142,34 +172,27 @@ __device__ __forceinline__ void reduce_prev(const double *__restrict__ part, int
   for (int64_t b = threadIdx.x + (int64_t)U * kBS; b < nblk; b += kBS)
 #pragma unroll
     for (int q = 0; q < NQ; ++q) acc[q] += part[b * NQ + q];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int wv = threadIdx.x >> 6;
 #pragma unroll
-  for (int q = 0; q < NQ; ++q)
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) acc[q] += __shfl_xor(acc[q], o, 64);
-  if (lane == 0)
+  for (int q = 0; q < NQ; ++q) acc[q] = wave_sum(acc[q]);
+  if ((threadIdx.x & 63) == 0)
 #pragma unroll
     for (int q = 0; q < NQ; ++q) red[wv][q] = acc[q];
   __syncthreads();
-  if (threadIdx.x == 0)
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      double s = red[0][q];
+  for (int q = 0; q < NQ; ++q) {
+    double s = red[0][q];
 #pragma unroll
-      for (int k = 1; k < kBS / 64; ++k) s += red[k][q];
-      res[q] = s;
-    }
-  __syncthreads();
-#pragma unroll
-  for (int q = 0; q < NQ; ++q) tot[q] = res[q];
+    for (int k = 1; k < kBS / 64; ++k) s += red[k][q];
+    tot[q] = s;
+  }
 }
 
 // ------------------------------------------------------------- predictor --
 template <int D>
 __global__ __launch_bounds__(kBS) void k_predict(SimArgs a) {
   const BucketDesc bd = a.tab->b[bucket_index(a.bm, blockIdx.x)];
-  const BScal b{bd.start, bd.count, bd.block0, bd.type, bd.width, bd.idx, static_cast<const double *>(bd.w),
-                static_cast<const double *>(bd.aux)};
+  const BScal b = bscal(bd);
   const int64_t t = ((int64_t)blockIdx.x - b.block0) * kBS + threadIdx.x;
   if (t >= b.count) return;
   const int64_t N = a.N, i = b.start + t, cnt = b.count;
@@ -178,8 +201,10 @@ __global__ __launch_bounds__(kBS) void k_predict(SimArgs a) {
     for (int c = 0; c < D; ++c) a.vs[c * N + i] = 0.0;
     return;
   }
-  const double *__restrict__ w = b.w;
-  const int32_t *__restrict__ idx = b.idx;
+  const uint32_t cnt32 = b.cnt, t32 = (uint32_t)t;
+  Buf vb[D];
+#pragma unroll
+  for (int c = 0; c < D; ++c) vb[c] = plane(a.v, N, c);
   const double *__restrict__ v = a.v;
   double *__restrict__ vs = a.vs;
   const double Ti = a.T[i], Tref = a.T_ref, Ra = a.Ra, Pr = a.Pr, dt = a.dt;
@@ -192,20 +217,36 @@ __global__ __launch_bounds__(kBS) void k_predict(SimArgs a) {
 #pragma unroll
       for (int q = 0; q < D; ++q) g[c][q] = 0.0;
     }
+    gather_chunks<W>(
+        b.idx, cnt32, t32,
+        [&](int j) __attribute__((always_inline)) {
+          Pack<double, D + 1> r;
 #pragma unroll
-    for (int j = 0; j < W; ++j) {
-      const int32_t nb = idx[(int64_t)j * cnt + t];
-      double wq[D + 1];
+          for (int q = 0; q <= D; ++q) r.v[q] = ld_soa<double>(b.w, cnt32, q * W + j, t32);
+          return r;
+        },
+        [&](int32_t nb) __attribute__((always_inline)) {
+          Pack<double, D> r;
 #pragma unroll
-      for (int q = 0; q <= D; ++q) wq[q] = w[((int64_t)q * W + j) * cnt + t];
+          for (int c = 0; c < D; ++c) r.v[c] = ld_at<double>(vb[c], nb);
+          return r;
+        },
+        [&](int, const Pack<double, D + 1> &wq, const Pack<double, D> &u) __attribute__((always_inline)) {
 #pragma unroll
-      for (int c = 0; c < D; ++c) {
-        const double u = v[c * N + nb];
+          for (int c = 0; c < D; ++c) {
 #pragma unroll
-        for (int q = 0; q < D; ++q) g[c][q] = fma(wq[q], u, g[c][q]);
-        L[c] = fma(wq[D], u, L[c]);
-      }
-    }
+            for (int q = 0; q < D; ++q) g[c][q] = fma(wq.v[q], u.v[c], g[c][q]);
+            L[c] = fma(wq.v[D], u.v[c], L[c]);
+          }
+        },
+        [&]() __attribute__((always_inline)) {
+#pragma unroll
+          for (int c = 0; c < D; ++c) {
+            pin(L[c]);
+#pragma unroll
+            for (int q = 0; q < D; ++q) pin(g[c][q]);
+          }
+        });
     double vi[D];
 #pragma unroll
     for (int q = 0; q < D; ++q) vi[q] = v[q * N + i];
@@ -227,8 +268,7 @@ __global__ __launch_bounds__(kBS) void k_predict(SimArgs a) {
 template <int D>
 __global__ __launch_bounds__(kBS) void k_rhs(SimArgs a) {
   const BucketDesc bd = a.tab->b[bucket_index(a.bm, blockIdx.x)];
-  const BScal b{bd.start, bd.count, bd.block0, bd.type, bd.width, bd.idx, static_cast<const double *>(bd.w),
-                static_cast<const double *>(bd.aux)};
+  const BScal b = bscal(bd);
   const int64_t t = ((int64_t)blockIdx.x - b.block0) * kBS + threadIdx.x;
   double part[kNR] = {0.0, 0.0, 0.0};  // b.b, r.r, sum x
   const int64_t N = a.N;
@@ -239,27 +279,43 @@ __global__ __launch_bounds__(kBS) void k_rhs(SimArgs a) {
     sc->early[0] = 0; sc->early[1] = 0;
   }
   if (t < b.count) {
-    const int64_t i = b.start + t, cnt = b.count;
-    const double *w = b.w;
-    const double *wP = b.wP;
+    const int64_t i = b.start + t;
+    const uint32_t cnt32 = b.cnt, t32 = (uint32_t)t;
     const bool wall = (b.type == B_DIR || b.type == B_NEU);
     const double *__restrict__ x = a.x;
-    const double *__restrict__ vs = a.vs;
-    const int32_t *__restrict__ idx = b.idx;
+    const Buf xb = plane(a.x, N + 1, 0);
+    Buf vsb[D];
+#pragma unroll
+    for (int q = 0; q < D; ++q) vsb[q] = plane(a.vs, N, q);
     const double dt = a.dt;
     double r = 0.0, rhs = 0.0;
     with_width<D>(b.width, [&](auto wc) __attribute__((always_inline)) {
       constexpr int W = decltype(wc)::value;
       double div = 0.0, Ap = 0.0;
+      gather_chunks<W>(
+          b.idx, cnt32, t32,
+          [&](int j) __attribute__((always_inline)) {
+            Pack<double, D + 1> r;
+            r.v[0] = ld_soa<double>(b.wP, cnt32, j, t32);
 #pragma unroll
-      for (int j = 0; j < W; ++j) {
-        const int32_t nb = idx[(int64_t)j * cnt + t];
-        Ap = fma(wP[(int64_t)j * cnt + t], x[nb], Ap);
-        if (!wall)
+            for (int q = 0; q < D; ++q) r.v[1 + q] = ld_soa<double>(b.w, cnt32, q * W + j, t32);   // unused at walls
+            return r;
+          },
+          [&](int32_t nb) __attribute__((always_inline)) {
+            Pack<double, D + 1> r;
+            r.v[0] = ld_at<double>(xb, nb);
 #pragma unroll
-          for (int q = 0; q < D; ++q) div = fma(w[((int64_t)q * W + j) * cnt + t], vs[q * N + nb], div);
-      }
-      if (!wall) rhs = (div / dt) / w[((int64_t)D * W + 0) * cnt + t];
+            for (int q = 0; q < D; ++q) r.v[1 + q] = ld_at<double>(vsb[q], nb);
+            return r;
+          },
+          [&](int, const Pack<double, D + 1> &wq, const Pack<double, D + 1> &u) __attribute__((always_inline)) {
+            Ap = fma(wq.v[0], u.v[0], Ap);
+            if (!wall)
+#pragma unroll
+              for (int q = 0; q < D; ++q) div = fma(wq.v[1 + q], u.v[1 + q], div);
+          },
+          [&]() __attribute__((always_inline)) { pin(Ap); pin(div); });
+      if (!wall) rhs = (div / dt) / ld_soa<double>(b.w, cnt32, D * W, t32);
       r = rhs - (Ap + lam);
     });
     a.RV[i] = make_double2(r, 0.0);
@@ -351,8 +407,7 @@ __global__ __launch_bounds__(kBS) void k_bicg_pv(SimArgs a, int it) {
     }
     if (early == 2) return;
   }
-  const BScal b{bd.start, bd.count, bd.block0, bd.type, bd.width, bd.idx, static_cast<const double *>(bd.w),
-                static_cast<const double *>(bd.aux)};
+  const BScal b = bscal(bd);
   const int64_t t = ((int64_t)blockIdx.x - b.block0) * kBS + threadIdx.x;
   if (early == 1) {                             // |s| converged: x += alpha p, nothing else
     if (t < b.count) {
@@ -363,9 +418,9 @@ __global__ __launch_bounds__(kBS) void k_bicg_pv(SimArgs a, int it) {
   }
   double part[kNA] = {0.0, 0.0, 0.0};           // (rh, v), sum p, |r|^2
   if (t < b.count) {
-    const int64_t i = b.start + t, cnt = b.count;
-    const int32_t *__restrict__ idx = b.idx;
-    const double *__restrict__ wP = b.wP;
+    const int64_t i = b.start + t;
+    const uint32_t cnt32 = b.cnt, t32 = (uint32_t)t;
+    const Buf RVb = plane(a.RV, N + 1, 0), STb = plane(ST, N + 1, 0), PVb = plane(PVo, N + 1, 0);
     const double2 *__restrict__ RV = a.RV;
     double ri, pi;
     if (first) {
@@ -380,17 +435,23 @@ __global__ __launch_bounds__(kBS) void k_bicg_pv(SimArgs a, int it) {
     double acc = 0.0;
     with_width<D>(b.width, [&](auto wc) __attribute__((always_inline)) {
       constexpr int W = decltype(wc)::value;
+      const auto wl = [&](int j) __attribute__((always_inline)) { return ld_soa<double>(b.wP, cnt32, j, t32); };
       if (first) {
-#pragma unroll
-        for (int j = 0; j < W; ++j) acc = fma(wP[(int64_t)j * cnt + t], RV[idx[(int64_t)j * cnt + t]].x, acc);
+        gather_chunks<W>(
+            b.idx, cnt32, t32, wl, [&](int32_t nb) __attribute__((always_inline)) { return ld_at<double>(RVb, 2 * nb); },
+            [&](int, double wj, double rj) __attribute__((always_inline)) { acc = fma(wj, rj, acc); },
+            [&]() __attribute__((always_inline)) { pin(acc); });
       } else {
-#pragma unroll
-        for (int j = 0; j < W; ++j) {
-          const int32_t nb = idx[(int64_t)j * cnt + t];
-          const double2 st = ST[nb], pv = PVo[nb];
-          const double pj = fma(beta, fma(-omega, pv.y, pv.x), fma(-omega, st.y, st.x));
-          acc = fma(wP[(int64_t)j * cnt + t], pj, acc);
-        }
+        gather_chunks<W>(
+            b.idx, cnt32, t32, wl,
+            [&](int32_t nb) __attribute__((always_inline)) {
+              return Pack<double2, 2>{{ld_at<double2>(STb, nb), ld_at<double2>(PVb, nb)}};
+            },
+            [&](int, double wj, const Pack<double2, 2> &g) __attribute__((always_inline)) {
+              const double pj = fma(beta, fma(-omega, g.v[1].y, g.v[1].x), fma(-omega, g.v[0].y, g.v[0].x));
+              acc = fma(wj, pj, acc);
+            },
+            [&]() __attribute__((always_inline)) { pin(acc); });
       }
     });
     const double vi = acc + pN;
@@ -450,23 +511,24 @@ __global__ __launch_bounds__(kBS) void k_bicg_st(SimArgs a, int it) {
     }
   }
   if (stop) return;
-  const BScal b{bd.start, bd.count, bd.block0, bd.type, bd.width, bd.idx, static_cast<const double *>(bd.w),
-                static_cast<const double *>(bd.aux)};
+  const BScal b = bscal(bd);
   const int64_t t = ((int64_t)blockIdx.x - b.block0) * kBS + threadIdx.x;
   double part[kNB] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};   // (t,s), (t,t), (rh,s), (rh,t), (s,s), sum s
   if (t < b.count) {
-    const int64_t i = b.start + t, cnt = b.count;
-    const int32_t *__restrict__ idx = b.idx;
-    const double *__restrict__ wP = b.wP;
+    const int64_t i = b.start + t;
+    const uint32_t cnt32 = b.cnt, t32 = (uint32_t)t;
+    const Buf RVb = plane(a.RV, N + 1, 0);
     const double2 *__restrict__ RV = a.RV;
     double acc = 0.0;
     with_width<D>(b.width, [&](auto wc) __attribute__((always_inline)) {
       constexpr int W = decltype(wc)::value;
-#pragma unroll
-      for (int j = 0; j < W; ++j) {
-        const double2 rv2 = RV[idx[(int64_t)j * cnt + t]];
-        acc = fma(wP[(int64_t)j * cnt + t], fma(-alpha, rv2.y, rv2.x), acc);
-      }
+      gather_chunks<W>(
+          b.idx, cnt32, t32, [&](int j) __attribute__((always_inline)) { return ld_soa<double>(b.wP, cnt32, j, t32); },
+          [&](int32_t nb) __attribute__((always_inline)) { return ld_at<double2>(RVb, nb); },
+          [&](int, double wj, const double2 &rv2) __attribute__((always_inline)) {
+            acc = fma(wj, fma(-alpha, rv2.y, rv2.x), acc);
+          },
+          [&]() __attribute__((always_inline)) { pin(acc); });
     });
     const double2 rvi = RV[i];
     const double si = fma(-alpha, rvi.y, rvi.x);
@@ -502,8 +564,7 @@ __global__ void k_chunk_end(SimArgs a) {
 template <int D>
 __global__ __launch_bounds__(kBS) void k_correct_heat(SimArgs a) {
   const BucketDesc bd = a.tab->b[bucket_index(a.bm, blockIdx.x)];
-  const BScal b{bd.start, bd.count, bd.block0, bd.type, bd.width, bd.idx, static_cast<const double *>(bd.w),
-                static_cast<const double *>(bd.aux)};
+  const BScal b = bscal(bd);
   const int64_t t = ((int64_t)blockIdx.x - b.block0) * kBS + threadIdx.x;
   const int64_t N = a.N;
   const bool zero = a.sc->zero_sol != 0;
@@ -518,9 +579,8 @@ __global__ __launch_bounds__(kBS) void k_correct_heat(SimArgs a) {
     if (zero) a.x[i] = 0.0;
     return;
   }
-  const double *__restrict__ w = b.w;
-  const int32_t *__restrict__ idx = b.idx;
-  const double *__restrict__ px = a.x;
+  const uint32_t cnt32 = b.cnt, t32 = (uint32_t)t;
+  const Buf xb = plane(a.x, N + 1, 0), Tb = plane(a.T, N, 0);
   const double *__restrict__ T = a.T;
   const double *__restrict__ vs = a.vs;
   double *__restrict__ vout = a.vout;
@@ -531,19 +591,31 @@ __global__ __launch_bounds__(kBS) void k_correct_heat(SimArgs a) {
     double gp[D], gT[D], LT = 0.0;
 #pragma unroll
     for (int q = 0; q < D; ++q) { gp[q] = 0.0; gT[q] = 0.0; }
+    gather_chunks<W>(
+        b.idx, cnt32, t32,
+        [&](int j) __attribute__((always_inline)) {
+          Pack<double, D + 1> r;
 #pragma unroll
-    for (int j = 0; j < W; ++j) {
-      const int32_t nb = idx[(int64_t)j * cnt + t];
-      const double pj = zero ? 0.0 : px[nb];
-      const double Tj = T[nb];
+          for (int q = 0; q <= D; ++q) r.v[q] = ld_soa<double>(b.w, cnt32, q * W + j, t32);
+          return r;
+        },
+        [&](int32_t nb) __attribute__((always_inline)) {
+          const double pj = ld_at<double>(xb, nb);
+          return Pack<double, 2>{{zero ? 0.0 : pj, ld_at<double>(Tb, nb)}};
+        },
+        [&](int, const Pack<double, D + 1> &wq, const Pack<double, 2> &u) __attribute__((always_inline)) {
 #pragma unroll
-      for (int q = 0; q < D; ++q) {
-        const double wq = w[((int64_t)q * W + j) * cnt + t];
-        gp[q] = fma(wq, pj, gp[q]);
-        gT[q] = fma(wq, Tj, gT[q]);
-      }
-      LT = fma(w[((int64_t)D * W + j) * cnt + t], Tj, LT);
-    }
+          for (int q = 0; q < D; ++q) {
+            gp[q] = fma(wq.v[q], u.v[0], gp[q]);
+            gT[q] = fma(wq.v[q], u.v[1], gT[q]);
+          }
+          LT = fma(wq.v[D], u.v[1], LT);
+        },
+        [&]() __attribute__((always_inline)) {
+          pin(LT);
+#pragma unroll
+          for (int q = 0; q < D; ++q) { pin(gp[q]); pin(gT[q]); }
+        });
     double vn[D];
 #pragma unroll
     for (int q = 0; q < D; ++q) {
@@ -567,22 +639,26 @@ __global__ __launch_bounds__(kBS) void k_correct_heat(SimArgs a) {
 template <int D>
 __global__ __launch_bounds__(kBS) void k_neumann(SimArgs a) {
   const BucketDesc bd = a.tab->b[bucket_index(a.bm, blockIdx.x)];
-  const BScal b{bd.start, bd.count, bd.block0, bd.type, bd.width, bd.idx, static_cast<const double *>(bd.w),
-                static_cast<const double *>(bd.aux)};
+  const BScal b = bscal(bd);
   const int64_t t = ((int64_t)blockIdx.x - b.block0) * kBS + threadIdx.x;
   if (t >= b.count || b.type != B_NEU) return;
-  const int64_t N = a.N, i = b.start + t, cnt = b.count;
-  const double *__restrict__ w = b.w;
-  const int32_t *__restrict__ idx = b.idx;
+  const int64_t N = a.N, i = b.start + t;
+  const uint32_t cnt32 = b.cnt, t32 = (uint32_t)t;
+  const Buf Tnb = plane(a.Tn, N, 0);
   double *Tn = a.Tn;
   Scalars *sc = a.sc;
   with_width<D>(b.width, [&](auto wc) __attribute__((always_inline)) {
     constexpr int W = decltype(wc)::value;
-    const double *wn = w + (int64_t)(D + 1) * W * cnt;
     double acc = 0.0;
-#pragma unroll
-    for (int j = 1; j < W; ++j) acc = fma(wn[(int64_t)j * cnt + t], Tn[idx[(int64_t)j * cnt + t]], acc);
-    const double Tb = -acc / wn[t];
+    gather_chunks<W>(
+        b.idx, cnt32, t32,
+        [&](int j) __attribute__((always_inline)) { return ld_soa<double>(b.w, cnt32, (D + 1) * W + j, t32); },
+        [&](int32_t nb) __attribute__((always_inline)) { return ld_at<double>(Tnb, nb); },
+        [&](int j, double wj, double Tj) __attribute__((always_inline)) {
+          if (j > 0) acc = fma(wj, Tj, acc);         // the wall node's own entry is the unknown
+        },
+        [&]() __attribute__((always_inline)) { pin(acc); });
+    const double Tb = -acc / ld_soa<double>(b.w, cnt32, (D + 1) * W, t32);
     Tn[i] = Tb;
     if (!isfinite(Tb)) atomicOr(&sc->nonfinite, 1);
   });
