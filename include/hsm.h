@@ -167,7 +167,7 @@ typedef struct {
   double Ra, Pr, dt, T_ref;
   double krylov_tol;       /* relative residual of the pressure solve, e.g. 1e-12 */
   int32_t krylov_maxiter;  /* iteration cap per step */
-  int32_t field_dtype;     /* HSM_F64, or HSM_F32_COMP for FP32 fields with compensated applies */
+  int32_t field_dtype;     /* HSM_F64, or HSM_F32_COMP: see below */
   int32_t krylov_chunk;    /* iterations per device-side batch between convergence checks (0 = default) */
   int32_t launch_mode;     /* 0: replay captured HIP graphs, 1: launch kernels directly (same kernels) */
   int32_t profile;         /* 1: bracket each phase (pre, Krylov batch, post) with HIP events; see hsm_sim_phase_times */
@@ -182,6 +182,16 @@ typedef struct {
   double last_relres;            /* relative residual reached in the last step */
   int64_t node_applies;          /* (operator, field, node) triples evaluated so far */
 } hsm_sim_stats;
+
+/*
+ * Field forms.  HSM_F64: every field, weight and sum in FP64.  HSM_F32_COMP:
+ * v, v*, T stored in FP32 and the field operators (advection, diffusion,
+ * divergence, heat, Neumann walls) apply FP32 weights with compensated FP32
+ * dot products (Dot2), pointwise updates in FP64 before the FP32 store; the
+ * pressure problem (its operator, Krylov vectors, reductions and p itself)
+ * stays FP64, and so does the pressure gradient's accumulation.  The caller's
+ * arrays are FP64 in both forms (converted on create and read).
+ */
 
 /*
  * hsm_sim_create -- a simulation state on a stencil set.  v [d][N], T [N] and

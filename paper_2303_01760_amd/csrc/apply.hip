@@ -34,32 +34,6 @@ struct ApplyArgs {
   int out_src[kMaxOps];      // output plane o takes computed operator out_src[o]; -1: zero (not stored)
 };
 
-template <class T>
-struct Acc {
-  T s;
-  __device__ __forceinline__ void init() { s = T(0); }
-  __device__ __forceinline__ void add(T w, T u) { s = fma(w, u, s); }
-  __device__ __forceinline__ void settle() { pin(s); }
-  __device__ __forceinline__ T get() const { return s; }
-};
-
-// Dot2 accumulator in FP32
-struct Dot2 {
-  float s, c;
-  __device__ __forceinline__ void init() { s = 0.f; c = 0.f; }
-  __device__ __forceinline__ void add(float w, float u) {
-    const float p = w * u;
-    const float pe = fmaf(w, u, -p);          // TwoProduct error
-    const float t = s + p;                     // TwoSum(s, p)
-    const float z = t - s;
-    const float se = (s - (t - z)) + (p - z);
-    s = t;
-    c = c + (pe + se);
-  }
-  __device__ __forceinline__ void settle() { pin(s); pin(c); }
-  __device__ __forceinline__ float get() const { return s + c; }
-};
-
 // One node: NL operators computed from one pass over the stencil (the
 // indices and gathered values are shared), W entries (0: width known only
 // at run time).

@@ -178,10 +178,70 @@ __device__ __forceinline__ Buf plane(const T *base, int64_t n, int c) {
   return make_buf(base + (int64_t)c * n, (uint64_t)n * sizeof(T));
 }
 
+// Ties a register value to this point of the program (an empty asm
+// statement that reads and writes it): the arithmetic producing it cannot be
+// sunk below.
+template <class T>
+__device__ __forceinline__ void pin(T &x) {
+  asm volatile("" : "+v"(x));
+}
+
+// Dot-product accumulators.  FMA in the working precision, or FP32 with
+// compensated products and sums (Ogita, Rump, Oishi 2005, "Dot2":
+// TwoProduct by FMA, Knuth's TwoSum), which evaluates an FP32 dot product as
+// if in twice the working precision.  Sources are built with
+// -ffp-contract=off, so the error-free transformations stay as written.
+template <class T>
+struct Acc {
+  T s;
+  __device__ __forceinline__ void init() { s = T(0); }
+  __device__ __forceinline__ void add(T w, T u) { s = fma(w, u, s); }
+  __device__ __forceinline__ void settle() { pin(s); }
+  __device__ __forceinline__ T get() const { return s; }
+  __device__ __forceinline__ double get_d() const { return (double)s; }
+};
+struct Dot2 {
+  float s, c;
+  __device__ __forceinline__ void init() { s = 0.f; c = 0.f; }
+  __device__ __forceinline__ void add(float w, float u) {
+    const float p = w * u;
+    const float pe = fmaf(w, u, -p);          // TwoProduct error
+    const float t = s + p;                     // TwoSum(s, p)
+    const float z = t - s;
+    const float se = (s - (t - z)) + (p - z);
+    s = t;
+    c = c + (pe + se);
+  }
+  __device__ __forceinline__ void settle() { pin(s); pin(c); }
+  __device__ __forceinline__ float get() const { return s + c; }
+  __device__ __forceinline__ double get_d() const { return (double)s + (double)c; }
+};
+// The accumulator of field applies for a field storage type: FP64 FMA, or
+// Dot2 for FP32 fields.
+template <class FT>
+struct FieldAccT;
+template <>
+struct FieldAccT<double> {
+  using type = Acc<double>;
+};
+template <>
+struct FieldAccT<float> {
+  using type = Dot2;
+};
+template <class FT>
+using FieldAcc = typename FieldAccT<FT>::type;
+
 // A fixed-size bundle of values loaded together.
 template <class T, int K>
 struct Pack {
   T v[K];
+};
+
+// Two bundles of different types loaded together.
+template <class TA, int KA, class TB, int KB>
+struct Pack2 {
+  Pack<TA, KA> a;
+  Pack<TB, KB> b;
 };
 
 // Largest divisor of W that is at most K.
@@ -189,14 +249,6 @@ constexpr int chunk_of(int W, int K) {
   for (int c = K < W ? K : W; c > 1; --c)
     if (W % c == 0) return c;
   return 1;
-}
-
-// Ties a register value to this point of the program (an empty asm
-// statement that reads and writes it): the arithmetic producing it cannot be
-// sunk below.
-template <class T>
-__device__ __forceinline__ void pin(T &x) {
-  asm volatile("" : "+v"(x));
 }
 
 // Stencil gather of node t over its W entries, in chunks of C entries (the

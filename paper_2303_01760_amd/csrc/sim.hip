@@ -56,6 +56,7 @@ struct hsm_sim {
   BucketTable tab_all{};
   DBuf dtab;
   int64_t nblk_nodes = 0;
+  bool f32 = false;           // FP32 field form (HSM_F32_COMP)
 
   ~hsm_sim() {
     if (s) (void)hipStreamSynchronize(s);
@@ -86,11 +87,11 @@ SimArgs make_args(hsm_sim *m, int par, int kpar) {
   a.dt = m->prm.dt; a.Ra = m->prm.Ra; a.Pr = m->prm.Pr; a.T_ref = m->prm.T_ref; a.tol = m->prm.krylov_tol;
   a.maxiter = m->prm.krylov_maxiter;
   a.chunk = m->chunk;
-  a.v = m->v.as<double>();
-  a.vs = m->vs.as<double>();
-  a.T = m->T[par].as<double>();
-  a.Tn = m->T[par ^ 1].as<double>();
-  a.vout = m->v.as<double>();
+  a.v = m->v.p;
+  a.vs = m->vs.p;
+  a.T = m->T[par].p;
+  a.Tn = m->T[par ^ 1].p;
+  a.vout = m->v.p;
   a.x = m->x; a.rh = m->rh;
   a.ST = m->ST; a.RV = m->RV;
   a.PVo = m->PV[kpar]; a.PVn = m->PV[kpar ^ 1];
@@ -106,8 +107,13 @@ template <int D>
 hsm_status enqueue_pre(hsm_sim *m, int par, hipStream_t s) {
   SimArgs a = make_args(m, par, 0);
   const dim3 g((unsigned)m->tab_all.nblocks), b(kBS);
-  hipLaunchKernelGGL(k_predict<D>, g, b, 0, s, a);
-  hipLaunchKernelGGL(k_rhs<D>, g, b, 0, s, a);
+  if (m->f32) {
+    hipLaunchKernelGGL((k_predict<D, float>), g, b, 0, s, a);
+    hipLaunchKernelGGL((k_rhs<D, float>), g, b, 0, s, a);
+  } else {
+    hipLaunchKernelGGL((k_predict<D, double>), g, b, 0, s, a);
+    hipLaunchKernelGGL((k_rhs<D, double>), g, b, 0, s, a);
+  }
   HSM_HIP(hipGetLastError());
   return HSM_OK;
 }
@@ -137,8 +143,13 @@ template <int D>
 hsm_status enqueue_post(hsm_sim *m, int par, hipStream_t s) {
   SimArgs a = make_args(m, par, 0);
   const dim3 g((unsigned)m->tab_all.nblocks), b(kBS);
-  hipLaunchKernelGGL(k_correct_heat<D>, g, b, 0, s, a);
-  hipLaunchKernelGGL(k_neumann<D>, g, b, 0, s, a);
+  if (m->f32) {
+    hipLaunchKernelGGL((k_correct_heat<D, float>), g, b, 0, s, a);
+    hipLaunchKernelGGL((k_neumann<D, float>), g, b, 0, s, a);
+  } else {
+    hipLaunchKernelGGL((k_correct_heat<D, double>), g, b, 0, s, a);
+    hipLaunchKernelGGL((k_neumann<D, double>), g, b, 0, s, a);
+  }
   HSM_HIP(hipGetLastError());
   return HSM_OK;
 }
@@ -288,7 +299,10 @@ hsm_status hsm_sim_create(const hsm_stencils *st, const hsm_sim_params *prm, con
     set_error(HSM_E_INVALID, "bad simulation parameters");
     return HSM_E_INVALID;
   }
-  if (prm->field_dtype != HSM_F64) { set_error(HSM_E_INVALID, "field_dtype must be HSM_F64"); return HSM_E_INVALID; }
+  if (prm->field_dtype != HSM_F64 && prm->field_dtype != HSM_F32_COMP) {
+    set_error(HSM_E_INVALID, "field_dtype must be HSM_F64 or HSM_F32_COMP");
+    return HSM_E_INVALID;
+  }
   if (st->N < 1) { set_error(HSM_E_INVALID, "empty stencil set"); return HSM_E_INVALID; }
   if (prm->profile != 0 && prm->profile != 1) { set_error(HSM_E_INVALID, "profile must be 0 or 1"); return HSM_E_INVALID; }
   if (prm->launch_mode != 0 && prm->launch_mode != 1) { set_error(HSM_E_INVALID, "launch_mode must be 0 or 1"); return HSM_E_INVALID; }
@@ -303,10 +317,12 @@ hsm_status hsm_sim_create(const hsm_stencils *st, const hsm_sim_params *prm, con
   const int64_t N = st->N, d = st->d;
   hipStream_t us = (hipStream_t)stream;
   hsm_status rc;
-  if ((rc = m->v.alloc(sizeof(double) * d * N)) || (rc = m->vs.alloc(sizeof(double) * d * N)) ||
-      (rc = m->T[0].alloc(sizeof(double) * N)) || (rc = m->T[1].alloc(sizeof(double) * N)) ||
-      (rc = m->sc.alloc(sizeof(Scalars))))
+  m->f32 = prm->field_dtype == HSM_F32_COMP;
+  const size_t fsz = m->f32 ? sizeof(float) : sizeof(double);
+  if ((rc = m->v.alloc(fsz * d * N)) || (rc = m->vs.alloc(fsz * d * N)) || (rc = m->T[0].alloc(fsz * N)) ||
+      (rc = m->T[1].alloc(fsz * N)) || (rc = m->sc.alloc(sizeof(Scalars))))
     return rc;
+  if (m->f32 && (rc = ensure_w32(st, us))) return rc;
   for (auto &b : m->vec)
     if ((rc = b.alloc(sizeof(double) * (N + 1)))) return rc;
   for (auto &b : m->pairs)
@@ -314,7 +330,7 @@ hsm_status hsm_sim_create(const hsm_stencils *st, const hsm_sim_params *prm, con
   m->x = m->vec[0].as<double>(); m->rh = m->vec[1].as<double>();
   m->ST = m->pairs[0].as<double2>(); m->PV[0] = m->pairs[1].as<double2>(); m->PV[1] = m->pairs[2].as<double2>();
   m->RV = m->pairs[3].as<double2>();
-  make_table(st, m->tab_all, kBS, 0xFu, false);
+  make_table(st, m->tab_all, kBS, 0xFu, m->f32);   // field weights in the field storage type
   if ((rc = m->partR.alloc(sizeof(double) * kNR * (m->tab_all.nblocks + 1))) ||
       (rc = m->partA.alloc(sizeof(double) * kNA * (m->tab_all.nblocks + 1))) ||
       (rc = m->partB.alloc(sizeof(double) * kNB * (m->tab_all.nblocks + 1))))
@@ -334,14 +350,23 @@ hsm_status hsm_sim_create(const hsm_stencils *st, const hsm_sim_params *prm, con
   if ((rc = m->dtab.alloc(sizeof(BucketTable)))) return rc;
   HSM_HIP(hipMemcpyAsync(m->dtab.p, &m->tab_all, sizeof(BucketTable), hipMemcpyHostToDevice, us));
   const int32_t *perm = st->perm.as<int32_t>();
-  for (int c = 0; c < d; ++c)
-    hipLaunchKernelGGL(k_gather<double>, dim3(nblk(N, 256)), dim3(256), 0, us, v + c * N, m->v.as<double>() + c * N,
-                       perm, N);
-  hipLaunchKernelGGL(k_gather<double>, dim3(nblk(N, 256)), dim3(256), 0, us, T, m->T[0].as<double>(), perm, N);
+  for (int c = 0; c < d; ++c) {
+    if (m->f32)
+      hipLaunchKernelGGL((k_gather<double, float>), dim3(nblk(N, 256)), dim3(256), 0, us, v + c * N,
+                         m->v.as<float>() + c * N, perm, N);
+    else
+      hipLaunchKernelGGL((k_gather<double, double>), dim3(nblk(N, 256)), dim3(256), 0, us, v + c * N,
+                         m->v.as<double>() + c * N, perm, N);
+  }
+  if (m->f32)
+    hipLaunchKernelGGL((k_gather<double, float>), dim3(nblk(N, 256)), dim3(256), 0, us, T, m->T[0].as<float>(), perm, N);
+  else
+    hipLaunchKernelGGL((k_gather<double, double>), dim3(nblk(N, 256)), dim3(256), 0, us, T, m->T[0].as<double>(), perm,
+                       N);
   for (auto &b : m->vec) hipLaunchKernelGGL(k_fill, dim3(nblk(N + 1, 256)), dim3(256), 0, us, b.as<double>(), N + 1, 0.0);
   for (auto &b : m->pairs)
     hipLaunchKernelGGL(k_fill, dim3(nblk(2 * (N + 1), 256)), dim3(256), 0, us, b.as<double>(), 2 * (N + 1), 0.0);
-  if (p) hipLaunchKernelGGL(k_gather<double>, dim3(nblk(N, 256)), dim3(256), 0, us, p, m->x, perm, N);
+  if (p) hipLaunchKernelGGL((k_gather<double, double>), dim3(nblk(N, 256)), dim3(256), 0, us, p, m->x, perm, N);
   hipLaunchKernelGGL(k_init_scalars, dim3(1), dim3(64), 0, us, m->sc.as<Scalars>());
   HSM_HIP(hipGetLastError());
   HSM_HIP(hipStreamSynchronize(us));
@@ -391,12 +416,17 @@ hsm_status hsm_sim_read(hsm_sim *m, double *v, double *T, double *p, void *strea
   HSM_HIP(hipStreamWaitEvent(us, m->ev_out, 0));
   const int64_t N = m->N;
   const int32_t *ip = m->st->iperm.as<int32_t>();
+  const dim3 g(nblk(N, 256)), b(256);
   if (v)
-    for (int c = 0; c < m->d; ++c)
-      hipLaunchKernelGGL(k_gather<double>, dim3(nblk(N, 256)), dim3(256), 0, us, m->v.as<double>() + c * N, v + c * N,
-                         ip, N);
-  if (T) hipLaunchKernelGGL(k_gather<double>, dim3(nblk(N, 256)), dim3(256), 0, us, m->T[m->parity].as<double>(), T, ip, N);
-  if (p) hipLaunchKernelGGL(k_gather<double>, dim3(nblk(N, 256)), dim3(256), 0, us, (const double *)m->x, p, ip, N);
+    for (int c = 0; c < m->d; ++c) {
+      if (m->f32) hipLaunchKernelGGL((k_gather<float, double>), g, b, 0, us, m->v.as<float>() + c * N, v + c * N, ip, N);
+      else hipLaunchKernelGGL((k_gather<double, double>), g, b, 0, us, m->v.as<double>() + c * N, v + c * N, ip, N);
+    }
+  if (T) {
+    if (m->f32) hipLaunchKernelGGL((k_gather<float, double>), g, b, 0, us, m->T[m->parity].as<float>(), T, ip, N);
+    else hipLaunchKernelGGL((k_gather<double, double>), g, b, 0, us, m->T[m->parity].as<double>(), T, ip, N);
+  }
+  if (p) hipLaunchKernelGGL((k_gather<double, double>), g, b, 0, us, (const double *)m->x, p, ip, N);
   HSM_HIP(hipGetLastError());
   return HSM_OK;
 }

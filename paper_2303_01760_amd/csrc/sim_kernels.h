@@ -37,17 +37,18 @@ struct Scalars {
 };
 
 struct SimArgs {
-  const BucketTable *tab;          // device table; aux = row-scaled pressure weights [W][count]
+  const BucketTable *tab;          // device table; w in the field storage type, aux = row-scaled
+                                   // FP64 pressure weights [W][count]
   BlockMap bm;
   int64_t N;
   double dt, Ra, Pr, T_ref, tol;
   int32_t maxiter, chunk;
-  // fields
-  const double *v;    // [D][N]
-  double *vs;         // [D][N]
-  const double *T;    // [N]
-  double *Tn;         // [N]
-  double *vout;       // [D][N]
+  // fields, in the field storage type (double, or float in the FP32 form)
+  const void *v;      // [D][N]
+  void *vs;           // [D][N]
+  const void *T;      // [N]
+  void *Tn;           // [N]
+  void *vout;         // [D][N]
   // Krylov vectors, each [N+1] (slot N: the border multiplier / zero-mean row)
   double *x, *rh;                 // [N+1]
   double2 *ST, *PVo, *PVn, *RV;   // pairs (s,t), (p,v) previous/this iteration, (r,v); [N+1]
@@ -189,83 +190,89 @@ __device__ __forceinline__ void reduce_prev(const double *__restrict__ part, int
 }
 
 // ------------------------------------------------------------- predictor --
-template <int D>
+// v* = v + dt (-(v.grad) v + Pr lap v - Ra Pr g (T - T_ref)) at interior nodes
+// (Eq. (2) with the pressure term left out: Chorin's splitting, Section 3);
+// 0 at walls.  FT: field and weight storage (double, or float with Dot2
+// applies); the pointwise update is in FP64.
+template <int D, class FT>
 __global__ __launch_bounds__(kBS) void k_predict(SimArgs a) {
   const BucketDesc bd = a.tab->b[bucket_index(a.bm, blockIdx.x)];
   const BScal b = bscal(bd);
   const int64_t t = ((int64_t)blockIdx.x - b.block0) * kBS + threadIdx.x;
   if (t >= b.count) return;
-  const int64_t N = a.N, i = b.start + t, cnt = b.count;
+  const int64_t N = a.N, i = b.start + t;
+  FT *__restrict__ vs = static_cast<FT *>(a.vs);
   if (b.type == B_DIR || b.type == B_NEU) {
 #pragma unroll
-    for (int c = 0; c < D; ++c) a.vs[c * N + i] = 0.0;
+    for (int c = 0; c < D; ++c) vs[c * N + i] = FT(0);
     return;
   }
+  const FT *__restrict__ v = static_cast<const FT *>(a.v);
   const uint32_t cnt32 = b.cnt, t32 = (uint32_t)t;
   Buf vb[D];
 #pragma unroll
-  for (int c = 0; c < D; ++c) vb[c] = plane(a.v, N, c);
-  const double *__restrict__ v = a.v;
-  double *__restrict__ vs = a.vs;
-  const double Ti = a.T[i], Tref = a.T_ref, Ra = a.Ra, Pr = a.Pr, dt = a.dt;
+  for (int c = 0; c < D; ++c) vb[c] = plane(v, N, c);
+  const double Ti = (double)static_cast<const FT *>(a.T)[i], Tref = a.T_ref, Ra = a.Ra, Pr = a.Pr, dt = a.dt;
+  using AccT = FieldAcc<FT>;
   with_width<D>(b.width, [&](auto wc) __attribute__((always_inline)) {
     constexpr int W = decltype(wc)::value;
-    double g[D][D], L[D];
+    AccT g[D][D], L[D];
 #pragma unroll
     for (int c = 0; c < D; ++c) {
-      L[c] = 0.0;
+      L[c].init();
 #pragma unroll
-      for (int q = 0; q < D; ++q) g[c][q] = 0.0;
+      for (int q = 0; q < D; ++q) g[c][q].init();
     }
     gather_chunks<W>(
         b.idx, cnt32, t32,
         [&](int j) __attribute__((always_inline)) {
-          Pack<double, D + 1> r;
+          Pack<FT, D + 1> r;
 #pragma unroll
-          for (int q = 0; q <= D; ++q) r.v[q] = ld_soa<double>(b.w, cnt32, q * W + j, t32);
+          for (int q = 0; q <= D; ++q) r.v[q] = ld_soa<FT>(b.w, cnt32, q * W + j, t32);
           return r;
         },
         [&](int32_t nb) __attribute__((always_inline)) {
-          Pack<double, D> r;
+          Pack<FT, D> r;
 #pragma unroll
-          for (int c = 0; c < D; ++c) r.v[c] = ld_at<double>(vb[c], nb);
+          for (int c = 0; c < D; ++c) r.v[c] = ld_at<FT>(vb[c], nb);
           return r;
         },
-        [&](int, const Pack<double, D + 1> &wq, const Pack<double, D> &u) __attribute__((always_inline)) {
+        [&](int, const Pack<FT, D + 1> &wq, const Pack<FT, D> &u) __attribute__((always_inline)) {
 #pragma unroll
           for (int c = 0; c < D; ++c) {
 #pragma unroll
-            for (int q = 0; q < D; ++q) g[c][q] = fma(wq.v[q], u.v[c], g[c][q]);
-            L[c] = fma(wq.v[D], u.v[c], L[c]);
+            for (int q = 0; q < D; ++q) g[c][q].add(wq.v[q], u.v[c]);
+            L[c].add(wq.v[D], u.v[c]);
           }
         },
         [&]() __attribute__((always_inline)) {
 #pragma unroll
           for (int c = 0; c < D; ++c) {
-            pin(L[c]);
+            L[c].settle();
 #pragma unroll
-            for (int q = 0; q < D; ++q) pin(g[c][q]);
+            for (int q = 0; q < D; ++q) g[c][q].settle();
           }
         });
     double vi[D];
 #pragma unroll
-    for (int q = 0; q < D; ++q) vi[q] = v[q * N + i];
+    for (int q = 0; q < D; ++q) vi[q] = (double)v[q * N + i];
     const double buoy = (Ra * Pr) * (Ti - Tref);
 #pragma unroll
     for (int c = 0; c < D; ++c) {
-      double adv = vi[0] * g[c][0];
+      double adv = vi[0] * g[c][0].get_d();
 #pragma unroll
-      for (int q = 1; q < D; ++q) adv = fma(vi[q], g[c][q], adv);
-      double f = fma(Pr, L[c], -adv);
+      for (int q = 1; q < D; ++q) adv = fma(vi[q], g[c][q].get_d(), adv);
+      double f = fma(Pr, L[c].get_d(), -adv);
       if (c == D - 1) f += buoy;
-      vs[c * N + i] = fma(dt, f, vi[c]);
+      vs[c * N + i] = (FT)fma(dt, f, vi[c]);
     }
   });
 }
 
 // ---------------------------------------- pressure rhs + initial residual --
 // b = div(v*)/dt / diag at interior nodes, 0 at walls; r0 = b - A x; rh = r0.
-template <int D>
+// The divergence is a field apply (FT); the pressure operator is FP64.
+template <int D, class FT>
 __global__ __launch_bounds__(kBS) void k_rhs(SimArgs a) {
   const BucketDesc bd = a.tab->b[bucket_index(a.bm, blockIdx.x)];
   const BScal b = bscal(bd);
@@ -286,36 +293,42 @@ __global__ __launch_bounds__(kBS) void k_rhs(SimArgs a) {
     const Buf xb = plane(a.x, N + 1, 0);
     Buf vsb[D];
 #pragma unroll
-    for (int q = 0; q < D; ++q) vsb[q] = plane(a.vs, N, q);
+    for (int q = 0; q < D; ++q) vsb[q] = plane(static_cast<const FT *>(a.vs), N, q);
     const double dt = a.dt;
     double r = 0.0, rhs = 0.0;
+    using AccT = FieldAcc<FT>;
     with_width<D>(b.width, [&](auto wc) __attribute__((always_inline)) {
       constexpr int W = decltype(wc)::value;
-      double div = 0.0, Ap = 0.0;
+      double Ap = 0.0;
+      AccT div;
+      div.init();
       gather_chunks<W>(
           b.idx, cnt32, t32,
           [&](int j) __attribute__((always_inline)) {
-            Pack<double, D + 1> r;
-            r.v[0] = ld_soa<double>(b.wP, cnt32, j, t32);
+            Pack<double, 1> wp;
+            wp.v[0] = ld_soa<double>(b.wP, cnt32, j, t32);
+            Pack<FT, D> wd;
 #pragma unroll
-            for (int q = 0; q < D; ++q) r.v[1 + q] = ld_soa<double>(b.w, cnt32, q * W + j, t32);   // unused at walls
-            return r;
+            for (int q = 0; q < D; ++q) wd.v[q] = ld_soa<FT>(b.w, cnt32, q * W + j, t32);   // unused at walls
+            return Pack2<double, 1, FT, D>{wp, wd};
           },
           [&](int32_t nb) __attribute__((always_inline)) {
-            Pack<double, D + 1> r;
-            r.v[0] = ld_at<double>(xb, nb);
+            Pack<double, 1> xp;
+            xp.v[0] = ld_at<double>(xb, nb);
+            Pack<FT, D> u;
 #pragma unroll
-            for (int q = 0; q < D; ++q) r.v[1 + q] = ld_at<double>(vsb[q], nb);
-            return r;
+            for (int q = 0; q < D; ++q) u.v[q] = ld_at<FT>(vsb[q], nb);
+            return Pack2<double, 1, FT, D>{xp, u};
           },
-          [&](int, const Pack<double, D + 1> &wq, const Pack<double, D + 1> &u) __attribute__((always_inline)) {
-            Ap = fma(wq.v[0], u.v[0], Ap);
-            if (!wall)
+          [&](int, const Pack2<double, 1, FT, D> &wq, const Pack2<double, 1, FT, D> &u)
+              __attribute__((always_inline)) {
+                Ap = fma(wq.a.v[0], u.a.v[0], Ap);
+                if (!wall)
 #pragma unroll
-              for (int q = 0; q < D; ++q) div = fma(wq.v[1 + q], u.v[1 + q], div);
-          },
-          [&]() __attribute__((always_inline)) { pin(Ap); pin(div); });
-      if (!wall) rhs = (div / dt) / ld_soa<double>(b.w, cnt32, D * W, t32);
+                  for (int q = 0; q < D; ++q) div.add(wq.b.v[q], u.b.v[q]);
+              },
+          [&]() __attribute__((always_inline)) { pin(Ap); div.settle(); });
+      if (!wall) rhs = (div.get_d() / dt) / (double)ld_soa<FT>(b.w, cnt32, D * W, t32);
       r = rhs - (Ap + lam);
     });
     a.RV[i] = make_double2(r, 0.0);
@@ -561,7 +574,10 @@ __global__ void k_chunk_end(SimArgs a) {
 }
 
 // -------------------------------------------- projection + heat transport --
-template <int D>
+// v = v* - dt grad p at interior nodes (0 at walls); T' = T + dt (lap T -
+// v.grad T) with the new velocity (Eq. (4)); Dirichlet walls keep T.  The
+// pressure gradient reads FP64 p with FT weights, accumulated in FP64.
+template <int D, class FT>
 __global__ __launch_bounds__(kBS) void k_correct_heat(SimArgs a) {
   const BucketDesc bd = a.tab->b[bucket_index(a.bm, blockIdx.x)];
   const BScal b = bscal(bd);
@@ -570,64 +586,72 @@ __global__ __launch_bounds__(kBS) void k_correct_heat(SimArgs a) {
   const bool zero = a.sc->zero_sol != 0;
   if (zero && blockIdx.x == 0 && threadIdx.x == 0) a.x[N] = 0.0;
   if (t >= b.count) return;
-  const int64_t i = b.start + t, cnt = b.count;
+  const int64_t i = b.start + t;
+  const FT *__restrict__ T = static_cast<const FT *>(a.T);
+  FT *__restrict__ vout = static_cast<FT *>(a.vout);
+  FT *__restrict__ Tnp = static_cast<FT *>(a.Tn);
   bool bad = false;
   if (b.type == B_DIR || b.type == B_NEU) {
 #pragma unroll
-    for (int c = 0; c < D; ++c) a.vout[c * N + i] = 0.0;
-    if (b.type == B_DIR) a.Tn[i] = a.T[i];
+    for (int c = 0; c < D; ++c) vout[c * N + i] = FT(0);
+    if (b.type == B_DIR) Tnp[i] = T[i];
     if (zero) a.x[i] = 0.0;
     return;
   }
   const uint32_t cnt32 = b.cnt, t32 = (uint32_t)t;
-  const Buf xb = plane(a.x, N + 1, 0), Tb = plane(a.T, N, 0);
-  const double *__restrict__ T = a.T;
-  const double *__restrict__ vs = a.vs;
-  double *__restrict__ vout = a.vout;
-  double *__restrict__ Tnp = a.Tn;
+  const Buf xb = plane(a.x, N + 1, 0), Tb = plane(T, N, 0);
+  const FT *__restrict__ vs = static_cast<const FT *>(a.vs);
   const double dt = a.dt;
+  using AccT = FieldAcc<FT>;
   with_width<D>(b.width, [&](auto wc) __attribute__((always_inline)) {
     constexpr int W = decltype(wc)::value;
-    double gp[D], gT[D], LT = 0.0;
+    double gp[D];
+    AccT gT[D], LT;
+    LT.init();
 #pragma unroll
-    for (int q = 0; q < D; ++q) { gp[q] = 0.0; gT[q] = 0.0; }
+    for (int q = 0; q < D; ++q) { gp[q] = 0.0; gT[q].init(); }
     gather_chunks<W>(
         b.idx, cnt32, t32,
         [&](int j) __attribute__((always_inline)) {
-          Pack<double, D + 1> r;
+          Pack<FT, D + 1> r;
 #pragma unroll
-          for (int q = 0; q <= D; ++q) r.v[q] = ld_soa<double>(b.w, cnt32, q * W + j, t32);
+          for (int q = 0; q <= D; ++q) r.v[q] = ld_soa<FT>(b.w, cnt32, q * W + j, t32);
           return r;
         },
         [&](int32_t nb) __attribute__((always_inline)) {
           const double pj = ld_at<double>(xb, nb);
-          return Pack<double, 2>{{zero ? 0.0 : pj, ld_at<double>(Tb, nb)}};
+          Pack2<double, 1, FT, 1> r;
+          r.a.v[0] = zero ? 0.0 : pj;
+          r.b.v[0] = ld_at<FT>(Tb, nb);
+          return r;
         },
-        [&](int, const Pack<double, D + 1> &wq, const Pack<double, 2> &u) __attribute__((always_inline)) {
+        [&](int, const Pack<FT, D + 1> &wq, const Pack2<double, 1, FT, 1> &u) __attribute__((always_inline)) {
 #pragma unroll
           for (int q = 0; q < D; ++q) {
-            gp[q] = fma(wq.v[q], u.v[0], gp[q]);
-            gT[q] = fma(wq.v[q], u.v[1], gT[q]);
+            gp[q] = fma((double)wq.v[q], u.a.v[0], gp[q]);
+            gT[q].add(wq.v[q], u.b.v[0]);
           }
-          LT = fma(wq.v[D], u.v[1], LT);
+          LT.add(wq.v[D], u.b.v[0]);
         },
         [&]() __attribute__((always_inline)) {
-          pin(LT);
+          LT.settle();
 #pragma unroll
-          for (int q = 0; q < D; ++q) { pin(gp[q]); pin(gT[q]); }
+          for (int q = 0; q < D; ++q) { pin(gp[q]); gT[q].settle(); }
         });
     double vn[D];
 #pragma unroll
     for (int q = 0; q < D; ++q) {
-      vn[q] = fma(-dt, gp[q], vs[q * N + i]);
-      vout[q * N + i] = vn[q];
+      vn[q] = fma(-dt, gp[q], (double)vs[q * N + i]);
+      const FT st = (FT)vn[q];
+      vout[q * N + i] = st;
+      vn[q] = (double)st;                    // the stored velocity advects T
       bad = bad || !isfinite(vn[q]);
     }
-    double adv = vn[0] * gT[0];
+    double adv = vn[0] * gT[0].get_d();
 #pragma unroll
-    for (int q = 1; q < D; ++q) adv = fma(vn[q], gT[q], adv);
-    const double Tn = fma(dt, LT - adv, T[i]);
-    Tnp[i] = Tn;
+    for (int q = 1; q < D; ++q) adv = fma(vn[q], gT[q].get_d(), adv);
+    const double Tn = fma(dt, LT.get_d() - adv, (double)T[i]);
+    Tnp[i] = (FT)Tn;
     bad = bad || !isfinite(Tn);
   });
   if (zero) a.x[i] = 0.0;
@@ -636,7 +660,7 @@ __global__ __launch_bounds__(kBS) void k_correct_heat(SimArgs a) {
 
 // Neumann walls: the temperature that zeroes the normal derivative, from the
 // new interior values (wall stencils hold the wall node and interior nodes).
-template <int D>
+template <int D, class FT>
 __global__ __launch_bounds__(kBS) void k_neumann(SimArgs a) {
   const BucketDesc bd = a.tab->b[bucket_index(a.bm, blockIdx.x)];
   const BScal b = bscal(bd);
@@ -644,25 +668,26 @@ __global__ __launch_bounds__(kBS) void k_neumann(SimArgs a) {
   if (t >= b.count || b.type != B_NEU) return;
   const int64_t N = a.N, i = b.start + t;
   const uint32_t cnt32 = b.cnt, t32 = (uint32_t)t;
-  const Buf Tnb = plane(a.Tn, N, 0);
-  double *Tn = a.Tn;
+  FT *Tn = static_cast<FT *>(a.Tn);
+  const Buf Tnb = plane(Tn, N, 0);
   Scalars *sc = a.sc;
+  using AccT = FieldAcc<FT>;
   with_width<D>(b.width, [&](auto wc) __attribute__((always_inline)) {
     constexpr int W = decltype(wc)::value;
-    double acc = 0.0;
+    AccT acc;
+    acc.init();
     gather_chunks<W>(
         b.idx, cnt32, t32,
-        [&](int j) __attribute__((always_inline)) { return ld_soa<double>(b.w, cnt32, (D + 1) * W + j, t32); },
-        [&](int32_t nb) __attribute__((always_inline)) { return ld_at<double>(Tnb, nb); },
-        [&](int j, double wj, double Tj) __attribute__((always_inline)) {
-          if (j > 0) acc = fma(wj, Tj, acc);         // the wall node's own entry is the unknown
+        [&](int j) __attribute__((always_inline)) { return ld_soa<FT>(b.w, cnt32, (D + 1) * W + j, t32); },
+        [&](int32_t nb) __attribute__((always_inline)) { return ld_at<FT>(Tnb, nb); },
+        [&](int j, FT wj, FT Tj) __attribute__((always_inline)) {
+          if (j > 0) acc.add(wj, Tj);                  // the wall node's own entry is the unknown
         },
-        [&]() __attribute__((always_inline)) { pin(acc); });
-    const double Tb = -acc / ld_soa<double>(b.w, cnt32, (D + 1) * W, t32);
-    Tn[i] = Tb;
+        [&]() __attribute__((always_inline)) { acc.settle(); });
+    const double Tb = -acc.get_d() / (double)ld_soa<FT>(b.w, cnt32, (D + 1) * W, t32);
+    Tn[i] = (FT)Tb;
     if (!isfinite(Tb)) atomicOr(&sc->nonfinite, 1);
   });
-  (void)N;
 }
 
 // pressure-operator rows: Laplacian (interior) or normal derivative (walls), divided by the centre weight
@@ -686,10 +711,10 @@ __global__ void k_init_scalars(Scalars *sc) {
   }
 }
 
-template <class T>
-__global__ void k_gather(const T *src, T *dst, const int32_t *map, int64_t n) {
+template <class S, class T>
+__global__ void k_gather(const S *src, T *dst, const int32_t *map, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) dst[i] = src[map[i]];
+  if (i < n) dst[i] = (T)src[map[i]];
 }
 
 inline unsigned nblk(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
