@@ -206,17 +206,36 @@ def cpu_baseline(s, m, budget_s=12.0):
                 solves_per_s=len(q) / t_build, build_s=t_build)
 
 
+WORKLOADS = {
+    # name: (node-set generator, scattered degree m, Ra, description)
+    "c2": (lambda ng: ng.obstacles2d(h=0.002), 2, 1e5,
+           "2D unit square minus 20 seeded circles (radii 0.02-0.08), h=0.002, scattered band 0.05"),
+    "c4": (lambda ng: ng.obstacles3d(h=0.01), 2, 1e5,
+           "3D unit cube minus 8 seeded spheres (radii 0.05-0.15), h=0.01, scattered band 0.05"),
+    "c5": (lambda ng: ng.obstacles2d(h=0.001), 4, 1e6,
+           "2D unit square minus 20 seeded circles (radii 0.02-0.08), h=0.001, scattered band 0.05"),
+}
+
+
+def apply_bytes(buckets, N, nops, fsize):
+    """Algorithmic bytes of one fused apply of nops operators to one field:
+    int32 indices and every weight read once, the field read once, nops outputs written."""
+    nnz = sum(w * c for _, w, c in buckets)
+    return 4 * nnz + nops * fsize * nnz + fsize * N + nops * fsize * N
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--time-steps", type=int, default=5, help="explicit time steps per benchmark step")
-    ap.add_argument("--m", type=int, default=2)
-    ap.add_argument("--h", type=float, default=0.002)
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="c2")
+    ap.add_argument("--m", type=int, default=0, help="scattered polynomial degree (0: the workload's)")
     ap.add_argument("--tol", type=float, default=1e-10, help="relative residual of each pressure solve")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-all-scattered", action="store_true")
+    ap.add_argument("--skip-fp32-form", action="store_true")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="summarise two rocprofv3 --pmc runs into the traffic record and exit")
     ap.add_argument("--trace-summary", nargs=3, metavar=("TRACE_CSV", "STATS_CSV", "OUT"),
@@ -240,8 +259,10 @@ def main():
     from paper_2303_01760_amd import hsm
     from paper_2303_01760_amd import nodegen as ng
 
+    gen, m_default, Ra, wdesc = WORKLOADS[args.workload]
+    m = args.m or m_default
     dev = torch.device("cuda:0")
-    s = ng.obstacles2d(h=args.h)
+    s = gen(ng)
     D = s.d
     x = torch.tensor(s.x, device=dev)
     kind = torch.tensor(s.kind, device=dev)
@@ -252,7 +273,8 @@ def main():
     T0d = torch.tensor(T0, device=dev)
     fields = [torch.tensor(np.sin(3 * s.x[0]), device=dev), torch.tensor(np.cos(2 * s.x[1]), device=dev), T0d]
     ops = hsm.OP_DX | hsm.OP_DY | hsm.OP_LAP
-    log(f"node set: N={s.n}, h={s.h}, m={args.m}, dt={dt:.3e}")
+    nops = 3
+    log(f"node set ({args.workload}): N={s.n}, d={D}, h={s.h}, m={m}, dt={dt:.3e}")
 
     # achievable HBM bandwidth: plain copy of 2 GiB (also the byte-counter calibration kernel)
     src = torch.empty(1 << 28, dtype=torch.float64, device=dev).fill_(1.0)
@@ -270,9 +292,9 @@ def main():
     del src, dst
     log(f"stream copy: {copy_gbs:.0f} GB/s")
 
-    def one_step(mode, rec):
+    def one_step(mode, rec, field_dtype=hsm.F64, keep=False):
         t0 = time.perf_counter()
-        st = hsm.build_stencils(x, kind, nrm, s.h, args.m, mode=mode)
+        st = hsm.build_stencils(x, kind, nrm, s.h, m, mode=mode)
         rec["build_s"] += time.perf_counter() - t0
         info = st.info()
         rec["build_dev_ms"] += info["build_ms"][0] + info["build_ms"][1] + info["build_ms"][2]
@@ -282,8 +304,8 @@ def main():
             st.apply(st.to_internal(f), ops, hsm.F64, out=out)
         rec["applies"] += 3 * st.node_count(ops)
         # profile=1: start/stop events around every graph launch on the stepper's stream
-        sim = hsm.Sim(st, v0, T0d, Ra=1e5, Pr=0.71, dt=dt, T_ref=0.5, krylov_tol=args.tol, krylov_maxiter=200000,
-                      krylov_chunk=KRYLOV_CHUNK, profile=1)
+        sim = hsm.Sim(st, v0, T0d, Ra=Ra, Pr=0.71, dt=dt, T_ref=0.5, krylov_tol=args.tol, krylov_maxiter=200000,
+                      krylov_chunk=KRYLOV_CHUNK, profile=1, field_dtype=field_dtype)
         sim.step(args.time_steps)
         stats = sim.stats()
         assert stats["status"] == 0, stats
@@ -296,12 +318,31 @@ def main():
             t[0] += ms * n
             t[1] += n
         rec["sizes"] = sim.sizes()
+        if keep:
+            rec["final"] = [a.cpu().numpy() for a in sim.read()]
         return st
 
-    results = {}
-    modes = [("hybrid", hsm.MODE_HYBRID)] + ([] if args.skip_all_scattered else [("all_scattered", hsm.MODE_ALL_SCATTERED)])
+    def apply_timing(st, dtype, reps=20):
+        """Mean device time of one fused 3-operator apply to one field (events on the launch stream)."""
+        u = st.to_internal(fields[0])
+        if dtype != hsm.F64:
+            u = u.float()
+        out = torch.empty((3, s.n), dtype=u.dtype, device=dev)
+        for _ in range(3):
+            st.apply(u, ops, dtype, out=out)
+        torch.cuda.synchronize()
+        a0, a1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a0.record()
+        for _ in range(reps):
+            st.apply(u, ops, dtype, out=out)
+        a1.record()
+        torch.cuda.synchronize()
+        return a0.elapsed_time(a1) / reps
+
     fresh = lambda: dict(build_s=0.0, build_dev_ms=0.0, solve_dev_ms=0.0, applies=0, krylov_iters=0, solves=0,
                          ptimes={})
+    results = {}
+    modes = [("hybrid", hsm.MODE_HYBRID)] + ([] if args.skip_all_scattered else [("all_scattered", hsm.MODE_ALL_SCATTERED)])
     for name, mode in modes:
         for _ in range(args.warmup):
             one_step(mode, fresh())
@@ -309,15 +350,45 @@ def main():
         rec = fresh()
         t0 = time.perf_counter()
         for k in range(args.steps):
-            one_step(mode, rec)
+            st_last = one_step(mode, rec, keep=(k == args.steps - 1))
             log(f"{name}: step {k + 1}/{args.steps} done")
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         rec["elapsed_s"] = el
         rec["ptimes"] = {k: (tot / n if n else float("nan"), n) for k, (tot, n) in rec["ptimes"].items()}
+        # fused apply of d/dx, d/dy and the Laplacian to one field, FP64 and FP32 + Dot2
+        bk = rec["info"]["buckets"]
+        am = {}
+        for lbl, dtp, fs in (("f64", hsm.F64, 8), ("f32_dot2", hsm.F32_COMP, 4)):
+            ms = apply_timing(st_last, dtp)
+            by = apply_bytes(bk, s.n, nops, fs)
+            am[lbl] = dict(mean_launch_ms=ms, bytes_per_launch=by, achieved_gbs=by / (ms * 1e-3) / 1e9,
+                           frac=by / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                           node_applies_per_s=nops * s.n / (ms * 1e-3))
+        rec["apply"] = am
+        del st_last
         results[name] = rec
         log(f"{name}: {el / args.steps * 1e3:.1f} ms/step, {rec['applies'] / el:.3e} node-applies/s, "
             f"krylov iters/step {rec['krylov_iters'] / args.steps:.0f}")
+
+    fp32 = None
+    if not args.skip_fp32_form:
+        rec = fresh()
+        t0 = time.perf_counter()
+        one_step(hsm.MODE_HYBRID, rec, field_dtype=hsm.F32_COMP, keep=True)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        ref = results["hybrid"]["final"]
+        err = {}
+        for nm, a, b in zip(("v", "T", "p"), rec["final"], ref):
+            if nm == "p":
+                a, b = a - a.mean(), b - b.mean()
+            err[nm] = dict(rel_l2=float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)),
+                           max_rel=float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)))
+        fp32 = dict(ms_per_step=el * 1e3, value=rec["applies"] / el,
+                    phase_mean_ms={k: (tot / n if n else float("nan")) for k, (tot, n) in rec["ptimes"].items()},
+                    error_vs_fp64_gpu_after_time_steps=err, time_steps=args.time_steps)
+        log(f"fp32 form: {el * 1e3:.1f} ms/step; error vs FP64: {err}")
 
     hy = results["hybrid"]
     info = hy["info"]
@@ -328,25 +399,26 @@ def main():
     bytes_it = kernel_bytes(buckets, s.n, "iteration")
     it_ms = pt["krylov_iter"][0]
     achieved = bytes_it / (it_ms * 1e-3) / 1e9
-    tr = traffic_record()
+    tr = traffic_record() if args.workload == "c2" else None
     roofline = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS,
                     traffic=(tr["hbm_bytes_per_iteration"] if tr else None),
-                    kernel="BiCGSTAB iteration (k_bicg_pv<2> + k_bicg_st<2>)", bytes_per_launch=bytes_it,
+                    kernel=f"BiCGSTAB iteration (k_bicg_pv<{D}> + k_bicg_st<{D}>)", bytes_per_launch=bytes_it,
                     bytes_pv=kernel_bytes(buckets, s.n, "bicg_pv"), bytes_st=kernel_bytes(buckets, s.n, "bicg_st"),
                     mean_launch_ms=it_ms, iterations_timed=pt["krylov_iter"][1], copy_kernel_gbs=copy_gbs)
     el = hy["elapsed_s"]
+    n_s = 2 * int(round(np.prod([m + k for k in range(1, D + 1)]) / np.prod(range(1, D + 1))))
     out = dict(metric=METRIC, value=hy["applies"] / el, unit="node-applies/s", n_gpus=1, steps=args.steps,
                warmup=args.warmup, ms_per_step=el / args.steps * 1e3, higher_is_better=True, scaling="weak",
                vs_baseline=None, dtype="f64", data="synthetic",
-               config=dict(workload=f"2D unit square minus 20 seeded circles, h={s.h}, band 0.05, m={args.m} "
-                                    f"(n={2 * (args.m + 1) * (args.m + 2) // 2}), hybrid; per step: stencil build + "
-                                    f"3-field apply + {args.time_steps} Boussinesq steps (Ra=1e5, Pr=0.71, "
-                                    f"dt=0.1h^2/2, pressure rel. residual {args.tol})",
-                           nodes=s.n, n_regular=info["n_regular"], n_scattered=info["n_scattered"],
+               config=dict(workload=f"{wdesc}, m={m} (n={n_s}), hybrid; per step: stencil build + 3-field apply + "
+                                    f"{args.time_steps} Boussinesq steps (Ra={Ra:g}, Pr=0.71, dt=0.1h^2/2, pressure "
+                                    f"rel. residual {args.tol})",
+                           name=args.workload, nodes=s.n, n_regular=info["n_regular"], n_scattered=info["n_scattered"],
                            time_steps_per_step=args.time_steps, krylov_tol=args.tol),
                solves_per_s=hy["solves"] / hy["build_s"], solves_per_s_device=hy["solves"] / (hy["solve_dev_ms"] * 1e-3),
                krylov_iters_per_time_step=hy["krylov_iters"] / (args.steps * args.time_steps),
                phase_mean_ms={k: v[0] for k, v in pt.items()},
+               apply=hy["apply"],
                roofline=roofline)
     if "all_scattered" in results:
         a = results["all_scattered"]
@@ -354,13 +426,17 @@ def main():
                                     krylov_iters_per_time_step=a["krylov_iters"] / (args.steps * args.time_steps),
                                     solves_per_s=a["solves"] / a["build_s"],
                                     solves_per_s_device=a["solves"] / (a["solve_dev_ms"] * 1e-3),
-                                    phase_mean_ms={k: v[0] for k, v in a["ptimes"].items()})
+                                    phase_mean_ms={k: v[0] for k, v in a["ptimes"].items()},
+                                    apply=a["apply"])
         out["hybrid_speedup_per_step"] = a["elapsed_s"] / el
         # per-iteration cost ratio of the pressure operator (same node set, same kernels)
         out["hybrid_speedup_per_krylov_iteration"] = a["ptimes"]["krylov_iter"][0] / it_ms
+        out["hybrid_speedup_apply"] = a["apply"]["f64"]["mean_launch_ms"] / hy["apply"]["f64"]["mean_launch_ms"]
+    if fp32:
+        out["fp32_form"] = fp32
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline(s, args.m)
+        out["cpu_baseline"] = cpu_baseline(s, m)
     print(json.dumps(out), flush=True)
     return 0
 

@@ -88,6 +88,7 @@ typedef struct {
   int64_t n_nodes, nnz;                /* nnz = total stencil entries over all nodes */
   int64_t n_regular, n_scattered;      /* by class */
   int64_t n_boundary;
+  int64_t n_wall_fallback;             /* wall nodes solved with monomials of degree m-1 (see below) */
   int32_t bucket_width[16];            /* per width bucket, in internal order */
   int32_t bucket_type[16];             /* 0 regular, 1 scattered interior, 2 Dirichlet wall, 3 Neumann wall */
   int64_t bucket_count[16];
@@ -102,8 +103,12 @@ typedef struct {
  * of its domain nearest to it, ordered by (squared distance, caller index)
  * with squared distance dx*dx + dy*dy (+ dz*dz) rounded step by step in that
  * order; the node itself comes first.  A wall node takes itself and its n-1
- * nearest interior nodes.  Classification (Section 2, Fig. 1): in
- * HSM_MODE_HYBRID an interior node is regular if, for each axis a and sign s,
+ * nearest interior nodes; if that local system is singular (the interior
+ * nodes leave the degree-m monomial block rank-deficient, e.g. all but the
+ * wall node on two lattice planes), the wall node uses monomials of degree
+ * m-1 on the same stencil (walls need first derivatives only; m >= 2).
+ * Classification (Section 2, Fig. 1): in HSM_MODE_HYBRID an interior node is
+ * regular if, for each axis a and sign s,
  * exactly one node lies within 1e-6 h_r (max-norm) of x + s h_r e_a; its
  * stencil is then [i, -x, +x, -y, +y (, -z, +z)] with MON weights.  All other
  * nodes (every node in HSM_MODE_ALL_SCATTERED) get RBF-FD weights.  Wall
@@ -246,8 +251,9 @@ hsm_status hsm_sim_sizes(hsm_sim *sim, int64_t *host_info);
 void hsm_sim_destroy(hsm_sim *sim);
 
 /*
- * hsm_stream_copy -- plain streaming copy of `bytes` (a multiple of 16) from
- * src to dst on `stream`, 16 bytes per thread per step.  A measurement aid:
+ * hsm_stream_copy -- plain streaming copy of `bytes` (a multiple of 16, at
+ * most 64 GiB) from src to dst on `stream`, one 16-byte element per thread.
+ * A measurement aid:
  * it calibrates achievable HBM bandwidth and the hardware byte counters
  * against a kernel whose traffic is known exactly.
  */

@@ -398,6 +398,14 @@ int ora_build(int d, int64_t N, const double *x, const uint8_t *kind, const doub
     for (int t = 0; t < wdt; ++t)
       for (int a = 0; a < d; ++a) xs[t * d + a] = x[a * N + nb[t]];
     rc = (c == 0) ? ora_mon(d, xs, wl) : ora_rbffd(d, m_dom[dm], wdt, xs, wl);
+    if (rc == ORA_E_SINGULAR && c != 0 && kind[i] != 0 && m_dom[dm] >= 2) {
+      /* A wall node's stencil of interior nodes can leave the degree-m
+       * monomial block rank-deficient (for instance when all but the wall
+       * node lie on two lattice planes, so x^2 and x agree on the stencil).
+       * Walls only need first derivatives (the normal derivative), so the
+       * node then takes PHS plus monomials of degree m-1 on the same nodes. */
+      rc = ora_rbffd(d, m_dom[dm] - 1, wdt, xs, wl);
+    }
     if (rc) { if (bad_node) *bad_node = i; break; }
     cls[q] = c;
     width[q] = wdt;

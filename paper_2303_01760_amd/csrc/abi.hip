@@ -147,6 +147,7 @@ hsm_status hsm_stencils_get_info(const hsm_stencils *st, hsm_stencils_info *o) {
   o->n_buckets = (int32_t)st->buckets.size();
   o->n_nodes = st->N; o->nnz = st->nnz; o->n_regular = st->n_regular; o->n_scattered = st->n_scattered;
   o->n_boundary = st->n_boundary;
+  o->n_wall_fallback = st->n_wall_fallback;
   for (size_t k = 0; k < st->buckets.size() && k < 16; ++k) {
     o->bucket_width[k] = st->buckets[k].width;
     o->bucket_type[k] = st->buckets[k].type;

@@ -183,7 +183,7 @@ __global__ __launch_bounds__(128) void k_knn(KnnArgs a) {
   const int32_t i = a.cell_nodes[t];
   const int dm = find_domain(i, a.off, a.nd);
   const GridDesc g = a.grids[dm];
-  const bool bnd = a.kind[i] != 0;
+  const bool bnd = a.kind[i] != 0;             // a wall node draws from interior nodes only
   double xi[D];
 #pragma unroll
   for (int q = 0; q < D; ++q) xi[q] = a.x[q * N + i];
@@ -627,11 +627,33 @@ hsm_status build_stencils_impl(const hsm_nodeset *ns, int32_t mode, hipStream_t 
   HSM_HIP(hipStreamSynchronize(s));
   HSM_HIP(hipEventRecord(ev[2], s));
   if (!(hs.bits & ((1u << BE_DUPLICATE) | (1u << BE_SMALL_DOMAIN) | (1u << BE_AMBIGUOUS) | (1u << BE_NONFINITE)))) {
+    // wall nodes whose degree-m system is singular are listed, not failed
+    DBuf d_retry;
+    if ((rc = d_retry.alloc(sizeof(int32_t) * (st->n_boundary + 1)))) return rc;
+    int32_t *retry = d_retry.as<int32_t>();
+    HSM_HIP(hipMemsetAsync(retry, 0, sizeof(int32_t), s));
+    auto is_wall = [](const Bucket &B) { return B.type == B_DIR || B.type == B_NEU; };
     for (const Bucket &B : st->buckets) {
-      if ((rc = solve_bucket(st, B, st->x.as<double>(), st->normal.as<double>(), d_status.as<DevStatus>(), s)))
+      if ((rc = solve_bucket(st, B, st->x.as<double>(), st->normal.as<double>(), d_status.as<DevStatus>(), s,
+                             is_wall(B) ? retry + 1 : nullptr, retry)))
         return rc;
     }
+    int32_t nretry = 0;
+    HSM_HIP(hipMemcpyAsync(&nretry, retry, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HSM_HIP(hipMemcpyAsync(&hs, d_status.p, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
+    HSM_HIP(hipStreamSynchronize(s));
+    if (nretry > 0 && !hs.bits) {
+      // the fallback: those wall nodes take degree m-1 on the same stencil
+      // (walls need first derivatives only); failures now latch
+      for (const Bucket &B : st->buckets) {
+        if (!is_wall(B)) continue;
+        if ((rc = solve_bucket_list(st, B, st->x.as<double>(), st->normal.as<double>(), d_status.as<DevStatus>(), s,
+                                    retry + 1, nretry)))
+          return rc;
+      }
+      HSM_HIP(hipMemcpyAsync(&hs, d_status.p, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
+    }
+    st->n_wall_fallback = nretry;
   }
   HSM_HIP(hipEventRecord(ev[3], s));
   HSM_HIP(hipStreamSynchronize(s));

@@ -105,6 +105,7 @@ namespace hsm { struct BucketTable; }
 struct hsm_stencils {
   int32_t d = 0, mode = 0, n_domains = 0;
   int64_t N = 0, nnz = 0, n_regular = 0, n_scattered = 0, n_boundary = 0;
+  int64_t n_wall_fallback = 0;   // wall nodes solved with monomials of degree m-1
   std::vector<hsm::Bucket> buckets;
   hsm::DBuf perm;        // int32 [N] internal -> caller
   hsm::DBuf iperm;       // int32 [N] caller -> internal
@@ -336,7 +337,11 @@ hsm_status scan_i32_to_i64(const int32_t *in, int64_t *out, int64_t n, hipStream
 // ------------------------------------------------------------- builders ---
 hsm_status build_stencils_impl(const hsm_nodeset *ns, int32_t mode, hipStream_t s, hsm_stencils **out);
 hsm_status solve_bucket(const hsm_stencils *st, const Bucket &b, const double *x_int,
-                        const double *normal_int, DevStatus *status, hipStream_t s);
+                        const double *normal_int, DevStatus *status, hipStream_t s, int32_t *retry = nullptr,
+                        int32_t *nretry = nullptr);
+hsm_status solve_bucket_list(const hsm_stencils *st, const Bucket &b, const double *x_int,
+                             const double *normal_int, DevStatus *status, hipStream_t s, const int32_t *list,
+                             int64_t nlist);
 hsm_status apply_impl(const hsm_stencils *st, uint32_t op_mask, int32_t dtype, const void *u, void *out,
                       hipStream_t s);
 hsm_status ensure_w32(const hsm_stencils *st, hipStream_t s);

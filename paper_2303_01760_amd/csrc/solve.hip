@@ -71,6 +71,9 @@ struct SolveArgs {
   int wall;               // also write normal-derivative weights
   const int32_t *perm;
   DevStatus *status;
+  int32_t *retry;         // non-NULL: list singular nodes here (internal numbering) instead of failing
+  int32_t *nretry;        // length of that list
+  const int32_t *list;    // non-NULL: block b solves internal node list[b] (if it is in this bucket)
 };
 
 template <int D, int M, int NS>
@@ -81,7 +84,12 @@ __global__ __launch_bounds__(64) void k_rbffd(SolveArgs a) {
   constexpr int R = D + 1;
   static_assert(S <= 64, "one system row per lane");
   const int lane = threadIdx.x;
-  const int64_t t = blockIdx.x;
+  int64_t t = blockIdx.x;
+  if (a.list) {
+    const int64_t g = a.list[blockIdx.x];
+    if (g < a.start || g >= a.start + a.count) return;
+    t = g - a.start;
+  }
   const int64_t cnt = a.count, N = a.N;
   __shared__ double sy[NS][D];
   __shared__ double smono[NS][Q];
@@ -204,7 +212,10 @@ __global__ __launch_bounds__(64) void k_rbffd(SolveArgs a) {
     }
   }
   if (singular) {
-    if (lane == 0) latch(a.status, BE_SINGULAR, a.perm[a.start + t]);
+    if (lane == 0) {
+      if (a.retry) a.retry[atomicAdd(a.nretry, 1)] = (int32_t)(a.start + t);
+      else latch(a.status, BE_SINGULAR, a.perm[a.start + t]);
+    }
     return;
   }
   // back substitution, last column first
@@ -374,8 +385,9 @@ __global__ __launch_bounds__(128) void k_mon(SolveArgs a) {
 }
 
 template <int D, int M, int NS>
-void launch_rbffd(const SolveArgs &a, hipStream_t s) {
-  hipLaunchKernelGGL((k_rbffd<D, M, NS>), dim3((unsigned)a.count), dim3(64), 0, s, a);
+void launch_rbffd(const SolveArgs &a, hipStream_t s, int64_t nlist = -1) {
+  const int64_t g = nlist >= 0 ? nlist : a.count;
+  hipLaunchKernelGGL((k_rbffd<D, M, NS>), dim3((unsigned)g), dim3(64), 0, s, a);
 }
 
 }  // namespace
@@ -388,12 +400,13 @@ bool rbffd_supported(int d, int m, int n) {
 }
 
 hsm_status solve_bucket(const hsm_stencils *st, const Bucket &b, const double *x_int, const double *normal_int,
-                        DevStatus *status, hipStream_t s) {
+                        DevStatus *status, hipStream_t s, int32_t *retry, int32_t *nretry) {
   if (b.count == 0) return HSM_OK;
   SolveArgs a;
   a.x = x_int; a.normal = normal_int; a.N = st->N; a.idx = b.idx.as<int32_t>(); a.count = b.count;
   a.start = b.start; a.w = b.w.as<double>(); a.wall = (b.type == B_DIR || b.type == B_NEU);
   a.perm = st->perm.as<int32_t>(); a.status = status;
+  a.retry = retry; a.nretry = nretry; a.list = nullptr;
   const int d = st->d;
   if (b.type == B_REG) {
     const unsigned g = (unsigned)((b.count + 127) / 128);
@@ -413,6 +426,33 @@ hsm_status solve_bucket(const hsm_stencils *st, const Bucket &b, const double *x
       set_error(HSM_E_INVALID, "no local-solve kernel for this (d, m, n)");
       return HSM_E_INVALID;
     }
+  }
+  HSM_HIP(hipGetLastError());
+  return HSM_OK;
+}
+
+// The wall fallback: the listed nodes of a wall bucket (internal numbering;
+// nodes of other buckets are skipped) solved with monomials of degree m-1 on
+// their stencil.  Supported where m >= 2.
+hsm_status solve_bucket_list(const hsm_stencils *st, const Bucket &b, const double *x_int, const double *normal_int,
+                             DevStatus *status, hipStream_t s, const int32_t *list, int64_t nlist) {
+  if (b.count == 0 || nlist <= 0) return HSM_OK;
+  SolveArgs a;
+  a.x = x_int; a.normal = normal_int; a.N = st->N; a.idx = b.idx.as<int32_t>(); a.count = b.count;
+  a.start = b.start; a.w = b.w.as<double>(); a.wall = (b.type == B_DIR || b.type == B_NEU);
+  a.perm = st->perm.as<int32_t>(); a.status = status;
+  a.retry = nullptr; a.nretry = nullptr; a.list = list;
+  const int d = st->d, m = b.m, n = b.width;
+  if (d == 2 && m == 2 && n == 12) launch_rbffd<2, 1, 12>(a, s, nlist);
+  else if (d == 2 && m == 3 && n == 20) launch_rbffd<2, 2, 20>(a, s, nlist);
+  else if (d == 2 && m == 4 && n == 30) launch_rbffd<2, 3, 30>(a, s, nlist);
+  else if (d == 3 && m == 2 && n == 20) launch_rbffd<3, 1, 20>(a, s, nlist);
+  else if (d == 3 && m == 2 && n == 30) launch_rbffd<3, 1, 30>(a, s, nlist);
+  else if (d == 3 && m == 3 && n == 40) launch_rbffd<3, 2, 40>(a, s, nlist);
+  else {
+    // no reduced-degree kernel (m = 1): the singular system is an error
+    set_error(HSM_E_SINGULAR, "singular local system at a wall node (no lower-degree fallback for m = 1)");
+    return HSM_E_SINGULAR;
   }
   HSM_HIP(hipGetLastError());
   return HSM_OK;

@@ -35,7 +35,7 @@ class StencilsInfoC(ctypes.Structure):
     _fields_ = [("d", ctypes.c_int32), ("mode", ctypes.c_int32), ("n_domains", ctypes.c_int32),
                 ("n_buckets", ctypes.c_int32), ("n_nodes", ctypes.c_int64), ("nnz", ctypes.c_int64),
                 ("n_regular", ctypes.c_int64), ("n_scattered", ctypes.c_int64), ("n_boundary", ctypes.c_int64),
-                ("bucket_width", ctypes.c_int32 * 16), ("bucket_type", ctypes.c_int32 * 16),
+                ("n_wall_fallback", ctypes.c_int64), ("bucket_width", ctypes.c_int32 * 16), ("bucket_type", ctypes.c_int32 * 16),
                 ("bucket_count", ctypes.c_int64 * 16), ("build_ms", ctypes.c_double * 4)]
 
 
@@ -152,6 +152,7 @@ class Stencils:
         nb = o.n_buckets
         return dict(d=o.d, mode=o.mode, n_domains=o.n_domains, n_nodes=o.n_nodes, nnz=o.nnz,
                     n_regular=o.n_regular, n_scattered=o.n_scattered, n_boundary=o.n_boundary,
+                    n_wall_fallback=o.n_wall_fallback,
                     buckets=[(o.bucket_type[k], o.bucket_width[k], o.bucket_count[k]) for k in range(nb)],
                     build_ms=list(o.build_ms))
 

@@ -136,6 +136,35 @@ def test_large_2d_sampled_parity():
         print(f"m={m}: N={s.n} regular={info['n_regular']} scattered={info['n_scattered']} build_ms={info['build_ms']}")
 
 
+def test_3d_wall_fallback_sampled_parity():
+    # 3D h=0.02: some wall nodes have a rank-deficient degree-2 system on
+    # their interior-only stencil and fall back to degree 1 (same stencil)
+    hsm = _hsm()
+    s = ng.obstacles3d(h=0.02)
+    x, kind, nrm = _dev(s)
+    st = hsm.build_stencils(x, kind, nrm, s.h, 2)
+    info = st.info()
+    assert info["n_wall_fallback"] >= 3, info["n_wall_fallback"]
+    ex = st.export()
+    rng = np.random.default_rng(23)
+    q = np.sort(np.concatenate([[467, 468, 515, 516, 517, 518], rng.choice(s.n, 150, replace=False),
+                                rng.choice(np.where(s.kind != 0)[0], 50, replace=False)]))
+    q = np.unique(q)
+    ora = O.build(s.x, s.kind, s.normal, s.h, 2, queries=q)
+    assert np.array_equal(ex["cls"][q], ora["cls"])
+    for k, i in enumerate(q):
+        a, b = ex["off"][i], ex["off"][i + 1]
+        wdt = ora["width"][k]
+        assert b - a == wdt
+        assert np.array_equal(ex["idx"][a:b], ora["idx"][k, :wdt])
+        for op in range(4):
+            ref = ora["w"][k, op, :wdt]
+            assert np.abs(ex["w"][op, a:b] - ref).max() <= WTOL * np.abs(ref).max()
+        ref = ora["wn"][k, :wdt]
+        assert np.abs(ex["w"][4, a:b] - ref).max() <= WTOL * max(np.abs(ref).max(), 1e-300)
+    print(f"3D h=0.02: N={s.n} wall fallbacks {info['n_wall_fallback']}")
+
+
 def test_duplicate_node_reports_lowest_node():
     hsm = _hsm()
     s = ng.cavity2d(h=0.05)

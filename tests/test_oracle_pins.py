@@ -507,3 +507,40 @@ def test_all_scattered_mode():
     csr = O.to_csr(st)
     x, y = s.x
     np.testing.assert_allclose(O.apply(csr, csr["w"][2], x * x + y * y), 4.0, rtol=1e-8)
+
+
+def test_wall_node_with_deficient_stencil_falls_back_to_degree_m_minus_1():
+    # 3D h=0.02 obstacle set: a few wall nodes near a sphere whose scattered
+    # band meets the box wall see interior nodes on only two normal layers
+    # beyond the wall, so x^2 and x agree on their stencil and the degree-2
+    # block is rank-deficient.  Walls need first derivatives only: such a
+    # node takes PHS + monomials of degree 1 on the same stencil.
+    s = ng.obstacles3d(h=0.02)
+    q = np.array([467, 468, 515])
+    assert np.all(s.kind[q] != 0)
+    knn = O.knn(s.x, 20, queries=q, kind=s.kind)
+    for r, i in enumerate(q):
+        y = (s.x[:, knn[r]] - s.x[:, [i]]).T
+        P2 = np.stack([_mono(al, y) for al in O.monomials(3, 2)], axis=1)
+        assert np.linalg.matrix_rank(P2) < P2.shape[1]          # the degree-2 system is singular
+    st = O.build(s.x, s.kind, s.normal, s.h, 2, queries=q)     # and the build still succeeds
+    assert np.array_equal(st["idx"][:, :20], knn)              # on the same interior-only stencil
+    for r, i in enumerate(q):
+        nb = st["idx"][r, :20]
+        y = (s.x[:, nb] - s.x[:, [i]]).T
+        # first derivatives exact on every polynomial of degree <= 1 ...
+        for al in O.monomials(3, 1):
+            vals = _mono(al, y)
+            for a in range(3):
+                want = float(al[a] == 1 and sum(al) == 1)
+                got = float(st["w"][r, a, :20] @ vals)
+                assert abs(got - want) <= 1e-10 * np.abs(st["w"][r, a, :20]).sum() * np.abs(y).max()
+        # ... but not on every quadratic (the degree really dropped): some
+        # second-degree monomial has a non-zero derivative error
+        # (every quadratic monomial has zero derivative at the centre, y = 0)
+        errs = [abs(float(st["w"][r, a, :20] @ _mono(al, y))) for al in O.monomials(3, 2) if sum(al) == 2
+                for a in range(3)]
+        assert max(errs) > 1e-6 * s.h
+        # the normal-derivative weights are n . grad weights
+        wn = sum(s.normal[a, i] * st["w"][r, a, :20] for a in range(3))
+        np.testing.assert_allclose(st["wn"][r, :20], wn, rtol=0, atol=1e-12 * np.abs(wn).max())
