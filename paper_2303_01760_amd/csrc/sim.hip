@@ -18,6 +18,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstddef>
 #include <cstring>
 #include <string>
 #include <memory>
@@ -57,6 +58,7 @@ struct hsm_sim {
   DBuf dtab;
   int64_t nblk_nodes = 0;
   bool f32 = false;           // FP32 field form (HSM_F32_COMP)
+  bool sepred = false;        // grid totals by a separate one-block kernel (large grids)
 
   ~hsm_sim() {
     if (s) (void)hipStreamSynchronize(s);
@@ -87,6 +89,7 @@ SimArgs make_args(hsm_sim *m, int par, int kpar) {
   a.dt = m->prm.dt; a.Ra = m->prm.Ra; a.Pr = m->prm.Pr; a.T_ref = m->prm.T_ref; a.tol = m->prm.krylov_tol;
   a.maxiter = m->prm.krylov_maxiter;
   a.chunk = m->chunk;
+  a.sepred = m->sepred ? 1 : 0;
   a.v = m->v.p;
   a.vs = m->vs.p;
   a.T = m->T[par].p;
@@ -102,6 +105,11 @@ SimArgs make_args(hsm_sim *m, int par, int kpar) {
   return a;
 }
 
+// Device address of a Scalars member (no host dereference of the device pointer).
+inline double *sc_member(Scalars *sc, size_t off) {
+  return reinterpret_cast<double *>(reinterpret_cast<char *>(sc) + off);
+}
+
 // Kernel launches of each phase.
 template <int D>
 hsm_status enqueue_pre(hsm_sim *m, int par, hipStream_t s) {
@@ -114,6 +122,9 @@ hsm_status enqueue_pre(hsm_sim *m, int par, hipStream_t s) {
     hipLaunchKernelGGL((k_predict<D, double>), g, b, 0, s, a);
     hipLaunchKernelGGL((k_rhs<D, double>), g, b, 0, s, a);
   }
+  if (m->sepred)
+    hipLaunchKernelGGL(k_reduce<kNR>, dim3(1), dim3(1024), 0, s, a.partR, m->tab_all.nblocks, a.sc,
+                       sc_member(a.sc, offsetof(Scalars, tot_r)));
   HSM_HIP(hipGetLastError());
   return HSM_OK;
 }
@@ -126,7 +137,13 @@ hsm_status enqueue_krylov(hsm_sim *m, int slot, hipStream_t s, int it0, int it1,
   for (int it = it0; it < it1; ++it) {
     SimArgs a = make_args(m, 0, it & 1);
     hipLaunchKernelGGL(k_bicg_pv<D>, g, b, 0, s, a, it);
+    if (m->sepred)
+      hipLaunchKernelGGL(k_reduce<kNA>, dim3(1), dim3(1024), 0, s, a.partA, m->tab_all.nblocks, a.sc,
+                         sc_member(a.sc, offsetof(Scalars, tot_a)));
     hipLaunchKernelGGL(k_bicg_st<D>, g, b, 0, s, a, it);
+    if (m->sepred)
+      hipLaunchKernelGGL(k_reduce<kNB>, dim3(1), dim3(1024), 0, s, a.partB, m->tab_all.nblocks, a.sc,
+                         sc_member(a.sc, offsetof(Scalars, tot_b)));
   }
   HSM_HIP(hipGetLastError());
   if (flags) {
@@ -306,6 +323,10 @@ hsm_status hsm_sim_create(const hsm_stencils *st, const hsm_sim_params *prm, con
   if (st->N < 1) { set_error(HSM_E_INVALID, "empty stencil set"); return HSM_E_INVALID; }
   if (prm->profile != 0 && prm->profile != 1) { set_error(HSM_E_INVALID, "profile must be 0 or 1"); return HSM_E_INVALID; }
   if (prm->launch_mode != 0 && prm->launch_mode != 1) { set_error(HSM_E_INVALID, "launch_mode must be 0 or 1"); return HSM_E_INVALID; }
+  if (prm->reduce_mode < 0 || prm->reduce_mode > 2) {
+    set_error(HSM_E_INVALID, "reduce_mode must be 0, 1 or 2");
+    return HSM_E_INVALID;
+  }
   if (prm->krylov_chunk < 0 || prm->krylov_chunk > kMaxIterChunk) {
     set_error(HSM_E_INVALID, "krylov_chunk out of range");
     return HSM_E_INVALID;
@@ -331,6 +352,10 @@ hsm_status hsm_sim_create(const hsm_stencils *st, const hsm_sim_params *prm, con
   m->ST = m->pairs[0].as<double2>(); m->PV[0] = m->pairs[1].as<double2>(); m->PV[1] = m->pairs[2].as<double2>();
   m->RV = m->pairs[3].as<double2>();
   make_table(st, m->tab_all, kBS, 0xFu, m->f32);   // field weights in the field storage type
+  // grid totals: in every block's prologue for small grids; by a separate
+  // one-block kernel once every block reading every partial costs more than
+  // that launch (measured crossover near a thousand blocks)
+  m->sepred = prm->reduce_mode == 2 || (prm->reduce_mode == 0 && m->tab_all.nblocks > kSepReduceBlocks);
   if ((rc = m->partR.alloc(sizeof(double) * kNR * (m->tab_all.nblocks + 1))) ||
       (rc = m->partA.alloc(sizeof(double) * kNA * (m->tab_all.nblocks + 1))) ||
       (rc = m->partB.alloc(sizeof(double) * kNB * (m->tab_all.nblocks + 1))))

@@ -18,6 +18,7 @@ constexpr int kNR = 3;          // partial sums of the right-hand-side kernel
 constexpr int kNA = 3;          // partial sums of the p/v kernel
 constexpr int kNB = 6;          // partial sums of the s/t kernel
 constexpr int kMaxIterChunk = 256;
+constexpr int64_t kSepReduceBlocks = 1024;   // above this grid size, totals come from k_reduce
 
 // Host-visible summary written once per batch of Krylov iterations.
 struct HostFlags {
@@ -31,6 +32,7 @@ struct HostFlags {
 struct Scalars {
   double rho[2], alpha[2];
   double bnorm2, relres;
+  double tot_r[kNR], tot_a[kNA], tot_b[kNB];   // grid totals from the separate reduction kernel
   int32_t done, fail, zero_sol, nonfinite;
   int32_t it_base, iters, early[2];   // early: 1 = |s| converged, 2 = breakdown, 3 = zero right-hand side
   HostFlags mirror;
@@ -43,6 +45,7 @@ struct SimArgs {
   int64_t N;
   double dt, Ra, Pr, T_ref, tol;
   int32_t maxiter, chunk;
+  int32_t sepred;      // 1: grid totals come from k_reduce (large grids), 0: each block reduces the partials
   // fields, in the field storage type (double, or float in the FP32 form)
   const void *v;      // [D][N]
   void *vs;           // [D][N]
@@ -186,6 +189,48 @@ __device__ __forceinline__ void reduce_prev(const double *__restrict__ part, int
 #pragma unroll
     for (int k = 1; k < kBS / 64; ++k) s += red[k][q];
     tot[q] = s;
+  }
+}
+
+// Grid totals of the previous kernel's partials: reduced in this block's
+// prologue, or (large grids, where every block reading every partial would
+// cost more than a launch) read from what k_reduce wrote.
+template <int NQ>
+__device__ __forceinline__ void grid_totals(const SimArgs &a, const double *part, const double *sep,
+                                            double (&tot)[NQ]) {
+  if (a.sepred) {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) tot[q] = sep[q];
+  } else {
+    reduce_prev<NQ>(part, gridDim.x, tot);
+  }
+}
+
+// One block: the grid totals of a kernel's block partials, in a fixed order
+// (each thread sums a strided set of rows, then wave sums, then the waves in
+// order); nothing to do once the solve has stopped.
+template <int NQ>
+__global__ __launch_bounds__(1024) void k_reduce(const double *__restrict__ part, int64_t nblk, const Scalars *sc,
+                                                 double *out) {
+  if (sc->done) return;
+  __shared__ double red[16][NQ];
+  double acc[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
+  for (int64_t b = threadIdx.x; b < nblk; b += 1024)
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) acc[q] += part[b * NQ + q];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) acc[q] = wave_sum(acc[q]);
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) red[threadIdx.x >> 6][q] = acc[q];
+  __syncthreads();
+  if (threadIdx.x < NQ) {
+    double s = red[0][threadIdx.x];
+#pragma unroll
+    for (int k = 1; k < 16; ++k) s += red[k][threadIdx.x];
+    out[threadIdx.x] = s;
   }
 }
 
@@ -361,7 +406,7 @@ __global__ __launch_bounds__(kBS) void k_bicg_pv(SimArgs a, int it) {
   const double bnorm2 = sc->bnorm2, alpha_prev = sc->alpha[par ^ 1], rho_prev = sc->rho[par ^ 1];
   const BucketDesc bd = a.tab->b[bucket_index(a.bm, blockIdx.x)];
   if (done) return;
-  const int64_t N = a.N, nblk = gridDim.x;
+  const int64_t N = a.N;
   const int k = it_base + it;
   const bool first = (k == 0);
   const double bn = sqrt(bnorm2);
@@ -371,7 +416,7 @@ __global__ __launch_bounds__(kBS) void k_bicg_pv(SimArgs a, int it) {
   const double2 *__restrict__ PVo = a.PVo;
   if (first) {
     double tot[kNR];
-    reduce_prev<kNR>(a.partR, nblk, tot);
+    grid_totals<kNR>(a, a.partR, sc->tot_r, tot);
     rN = -tot[2];                               // border row of r0: 0 - sum x
     rho_k = fma(rN, rN, tot[1]);                // (rh, r0) = |r0|^2
     pN = rN;
@@ -387,7 +432,7 @@ __global__ __launch_bounds__(kBS) void k_bicg_pv(SimArgs a, int it) {
     if (early) return;
   } else {
     double tot[kNB];
-    reduce_prev<kNB>(a.partB, nblk, tot);
+    grid_totals<kNB>(a, a.partB, sc->tot_b, tot);
     const double sN = ST[N].x, rhN = a.rh[N];
     const double2 pvN = PVo[N];
     const double tN = tot[5];                   // border row of t = A s: sum s
@@ -484,7 +529,7 @@ __global__ __launch_bounds__(kBS) void k_bicg_st(SimArgs a, int it) {
   const int done = sc->done, it_base = sc->it_base, early = sc->early[par];
   const double bnorm2 = sc->bnorm2, rho_k = sc->rho[par];
   if (done) return;
-  const int64_t N = a.N, nblk = gridDim.x;
+  const int64_t N = a.N;
   const int k = it_base + it;
   if (early) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -497,7 +542,7 @@ __global__ __launch_bounds__(kBS) void k_bicg_st(SimArgs a, int it) {
   }
   const BucketDesc bd = a.tab->b[bucket_index(a.bm, blockIdx.x)];
   double tot[kNA];
-  reduce_prev<kNA>(a.partA, nblk, tot);
+  grid_totals<kNA>(a, a.partA, sc->tot_a, tot);
   const double bn = sqrt(bnorm2);
   const double vN = tot[1];                     // border row of v = A p: sum p
   const double rN = a.RV[N].x;

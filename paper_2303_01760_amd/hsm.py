@@ -43,7 +43,7 @@ class SimParamsC(ctypes.Structure):
     _fields_ = [("Ra", ctypes.c_double), ("Pr", ctypes.c_double), ("dt", ctypes.c_double),
                 ("T_ref", ctypes.c_double), ("krylov_tol", ctypes.c_double), ("krylov_maxiter", ctypes.c_int32),
                 ("field_dtype", ctypes.c_int32), ("krylov_chunk", ctypes.c_int32), ("launch_mode", ctypes.c_int32),
-                ("profile", ctypes.c_int32), ("pad", ctypes.c_int32)]
+                ("profile", ctypes.c_int32), ("reduce_mode", ctypes.c_int32)]
 
 
 class SimStatsC(ctypes.Structure):
@@ -237,10 +237,10 @@ class Sim:
 
     def __init__(self, st: Stencils, v: torch.Tensor, T: torch.Tensor, p=None, *, Ra, Pr, dt, T_ref,
                  krylov_tol=1e-12, krylov_maxiter=20000, field_dtype=F64, krylov_chunk=0, launch_mode=0,
-                 profile=0, stream=None):
+                 profile=0, reduce_mode=0, stream=None):
         self.st = st
         prm = SimParamsC(Ra, Pr, dt, T_ref, krylov_tol, krylov_maxiter, field_dtype, krylov_chunk, launch_mode,
-                         profile, 0)
+                         profile, reduce_mode)
         h = _p()
         _check(lib().hsm_sim_create(st.handle, ctypes.byref(prm), _dptr(v, torch.float64), _dptr(T, torch.float64),
                                     None if p is None else _dptr(p, torch.float64), _stream(stream),

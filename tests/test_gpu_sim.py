@@ -67,19 +67,22 @@ def _cavity_oracle(mode):
     return _CAVITY[mode]
 
 
-@pytest.mark.parametrize("mode", [0, 1])
-def test_cavity_100_steps_parity(mode):
+@pytest.mark.parametrize("mode,reduce_mode", [(0, 0), (1, 0), (0, 2)])
+def test_cavity_100_steps_parity(mode, reduce_mode):
+    # reduce_mode 2: Krylov grid totals from the separate one-block kernel
+    # (the large-grid path) instead of every block's prologue
     hsm = _hsm()
     s, prm, v, T, vo, To, po, its = _cavity_oracle(mode)
     st = _build(s, 2, mode)
     dev = torch.device("cuda")
-    sim = hsm.Sim(st, torch.tensor(v, device=dev), torch.tensor(T, device=dev), krylov_tol=1e-12, **prm)
+    sim = hsm.Sim(st, torch.tensor(v, device=dev), torch.tensor(T, device=dev), krylov_tol=1e-12,
+                  reduce_mode=reduce_mode, **prm)
     sim.step(100)
     stats = sim.stats()
     assert stats["status"] == 0 and stats["steps"] == 100
     vg, Tg, pg = [a.cpu().numpy() for a in sim.read()]
     ev, eT, ep = _rel(vg, vo), _rel(Tg, To), _rel(pg, po)
-    print(f"mode {mode}: rel L2 err v {ev:.2e} T {eT:.2e} p {ep:.2e}; krylov iters gpu {stats['krylov_iters_total']} "
+    print(f"mode {mode} reduce {reduce_mode}: rel L2 err v {ev:.2e} T {eT:.2e} p {ep:.2e}; krylov iters gpu {stats['krylov_iters_total']} "
           f"oracle {int(its.sum())}; |v|max {np.abs(vo).max():.3e}")
     assert ev <= FIELD_TOL and eT <= FIELD_TOL and ep <= FIELD_TOL
     assert abs(stats["krylov_iters_total"] - int(its.sum())) <= 0.1 * its.sum() + 10
@@ -124,6 +127,26 @@ def test_fp32_form_graph_replay_matches_direct_launches():
             torch.cuda.synchronize()
         for a, b in zip(*outs):
             assert np.array_equal(a, b), f"replay {rep} differs"
+
+
+def test_separate_reduction_graph_replay_matches_direct_launches():
+    hsm = _hsm()
+    s = ng.cavity2d(h=0.025, seed=77)
+    dt = 0.1 * s.h ** 2 / 2
+    st = _build(s)
+    v, T = _cavity_init(s)
+    dev = torch.device("cuda")
+    sims = [hsm.Sim(st, torch.tensor(v, device=dev), torch.tensor(T, device=dev), Ra=1e5, Pr=0.71, dt=dt, T_ref=0.5,
+                    launch_mode=lm, krylov_chunk=8, reduce_mode=2) for lm in (0, 1)]
+    for rep in range(3):
+        outs = []
+        for sim in sims:
+            sim.step(3)
+            outs.append([a.cpu().numpy() for a in sim.read()])
+            torch.cuda.synchronize()
+        for a, b in zip(*outs):
+            assert np.array_equal(a, b), f"replay {rep} differs"
+    assert sims[0].stats()["krylov_iters_total"] == sims[1].stats()["krylov_iters_total"]
 
 
 def test_graph_replay_matches_direct_launches():
