@@ -365,6 +365,19 @@ def main():
             am[lbl] = dict(mean_launch_ms=ms, bytes_per_launch=by, achieved_gbs=by / (ms * 1e-3) / 1e9,
                            frac=by / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                            node_applies_per_s=nops * s.n / (ms * 1e-3))
+        # FP32 and FP32+Dot2 applies against FP64 applies (one smooth field): against the FP64 apply of
+        # the FP64 field (everything FP32 storage costs), and against the FP64 apply of the same
+        # FP32-rounded field (the weights' rounding and the sums alone)
+        u64 = st_last.to_internal(fields[0])
+        u32 = u64.float()
+        refs = {"vs_fp64_field": st_last.apply(u64, ops, hsm.F64),
+                "vs_fp64_apply_of_fp32_field": st_last.apply(u32.double(), ops, hsm.F64)}
+        for lbl, dtp in (("f32", hsm.F32), ("f32_dot2", hsm.F32_COMP)):
+            got = st_last.apply(u32, ops, dtp).double()
+            for rk, ref in refs.items():
+                am.setdefault("precision", {}).setdefault(lbl, {})[rk] = dict(
+                    rel_l2=float(torch.linalg.vector_norm(got - ref).item() / torch.linalg.vector_norm(ref).item()),
+                    max_rel=float((got - ref).abs().max().item() / ref.abs().max().item()))
         rec["apply"] = am
         del st_last
         results[name] = rec
