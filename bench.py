@@ -214,6 +214,9 @@ WORKLOADS = {
            "3D unit cube minus 8 seeded spheres (radii 0.05-0.15), h=0.01, scattered band 0.05"),
     "c5": (lambda ng: ng.obstacles2d(h=0.001), 4, 1e6,
            "2D unit square minus 20 seeded circles (radii 0.02-0.08), h=0.001, scattered band 0.05"),
+    "c3": (lambda ng: ng.batch2d(), 0, 1e5,
+           "512 independent 2D domains (unit square minus 4 seeded circles each), 1k-50k nodes per domain "
+           "(log-uniform), h per domain from its node count, scattered band max(0.05, 3h), m per domain in {2, 4}"),
 }
 
 
@@ -260,21 +263,26 @@ def main():
     from paper_2303_01760_amd import nodegen as ng
 
     gen, m_default, Ra, wdesc = WORKLOADS[args.workload]
-    m = args.m or m_default
     dev = torch.device("cuda:0")
     s = gen(ng)
     D = s.d
+    multi = isinstance(s, ng.Batch)
+    # per-domain lattice spacing and degree (one domain: scalars)
+    hdom = s.h
+    m = (s.m if multi else (args.m or m_default))
+    dom_off = s.off if multi else None
     x = torch.tensor(s.x, device=dev)
     kind = torch.tensor(s.kind, device=dev)
     nrm = torch.tensor(s.normal, device=dev)
-    dt = 0.1 * s.h ** 2 / 2
+    dt = 0.1 * float(np.min(hdom)) ** 2 / 2
     T0 = np.where(s.kind == 1, s.tbc, 0.0)
     v0 = torch.zeros((D, s.n), dtype=torch.float64, device=dev)
     T0d = torch.tensor(T0, device=dev)
     fields = [torch.tensor(np.sin(3 * s.x[0]), device=dev), torch.tensor(np.cos(2 * s.x[1]), device=dev), T0d]
     ops = hsm.OP_DX | hsm.OP_DY | hsm.OP_LAP
     nops = 3
-    log(f"node set ({args.workload}): N={s.n}, d={D}, h={s.h}, m={m}, dt={dt:.3e}")
+    log(f"node set ({args.workload}): N={s.n}, d={D}, domains={s.n_domains if multi else 1}, "
+        f"h={'per domain' if multi else s.h}, m={'per domain' if multi else m}, dt={dt:.3e}")
 
     # achievable HBM bandwidth: plain copy of 2 GiB (also the byte-counter calibration kernel)
     src = torch.empty(1 << 28, dtype=torch.float64, device=dev).fill_(1.0)
@@ -294,7 +302,7 @@ def main():
 
     def one_step(mode, rec, field_dtype=hsm.F64, keep=False):
         t0 = time.perf_counter()
-        st = hsm.build_stencils(x, kind, nrm, s.h, m, mode=mode)
+        st = hsm.build_stencils(x, kind, nrm, hdom, m, mode=mode, domain_offsets=dom_off)
         rec["build_s"] += time.perf_counter() - t0
         info = st.info()
         rec["build_dev_ms"] += info["build_ms"][0] + info["build_ms"][1] + info["build_ms"][2]
@@ -303,6 +311,10 @@ def main():
         for f in fields:
             st.apply(st.to_internal(f), ops, hsm.F64, out=out)
         rec["applies"] += 3 * st.node_count(ops)
+        rec["solves"] += s.n
+        rec["info"] = info
+        if multi:                 # stepping is one domain per simulation for now
+            return st
         # profile=1: start/stop events around every graph launch on the stepper's stream
         sim = hsm.Sim(st, v0, T0d, Ra=Ra, Pr=0.71, dt=dt, T_ref=0.5, krylov_tol=args.tol, krylov_maxiter=200000,
                       krylov_chunk=KRYLOV_CHUNK, profile=1, field_dtype=field_dtype)
@@ -311,8 +323,6 @@ def main():
         assert stats["status"] == 0, stats
         rec["applies"] += stats["node_applies"]
         rec["krylov_iters"] += stats["krylov_iters_total"]
-        rec["solves"] += s.n
-        rec["info"] = info
         for k, (ms, n) in sim.phase_times().items():
             t = rec["ptimes"].setdefault(k, [0.0, 0])
             t[0] += ms * n
@@ -384,8 +394,9 @@ def main():
         log(f"{name}: {el / args.steps * 1e3:.1f} ms/step, {rec['applies'] / el:.3e} node-applies/s, "
             f"krylov iters/step {rec['krylov_iters'] / args.steps:.0f}")
 
+    stepping = not multi
     fp32 = None
-    if not args.skip_fp32_form:
+    if not args.skip_fp32_form and stepping:
         rec = fresh()
         t0 = time.perf_counter()
         one_step(hsm.MODE_HYBRID, rec, field_dtype=hsm.F32_COMP, keep=True)
@@ -406,50 +417,69 @@ def main():
     hy = results["hybrid"]
     info = hy["info"]
     buckets = info["buckets"]
-    pt = hy["ptimes"]
-    # the pressure solve dominates the step; its unit of work is one BiCGSTAB
-    # iteration (one launch each of k_bicg_pv and k_bicg_st)
-    bytes_it = kernel_bytes(buckets, s.n, "iteration")
-    it_ms = pt["krylov_iter"][0]
-    achieved = bytes_it / (it_ms * 1e-3) / 1e9
-    tr = traffic_record() if args.workload == "c2" else None
-    roofline = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS,
-                    traffic=(tr["hbm_bytes_per_iteration"] if tr else None),
-                    kernel=f"BiCGSTAB iteration (k_bicg_pv<{D}> + k_bicg_st<{D}>)", bytes_per_launch=bytes_it,
-                    bytes_pv=kernel_bytes(buckets, s.n, "bicg_pv"), bytes_st=kernel_bytes(buckets, s.n, "bicg_st"),
-                    mean_launch_ms=it_ms, iterations_timed=pt["krylov_iter"][1], copy_kernel_gbs=copy_gbs)
     el = hy["elapsed_s"]
-    n_s = 2 * int(round(np.prod([m + k for k in range(1, D + 1)]) / np.prod(range(1, D + 1))))
+    if stepping:
+        pt = hy["ptimes"]
+        # the pressure solve dominates the step; its unit of work is one BiCGSTAB
+        # iteration (one launch each of k_bicg_pv and k_bicg_st)
+        bytes_it = kernel_bytes(buckets, s.n, "iteration")
+        it_ms = pt["krylov_iter"][0]
+        achieved = bytes_it / (it_ms * 1e-3) / 1e9
+        tr = traffic_record() if args.workload == "c2" else None
+        roofline = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS,
+                        traffic=(tr["hbm_bytes_per_iteration"] if tr else None),
+                        kernel=f"BiCGSTAB iteration (k_bicg_pv<{D}> + k_bicg_st<{D}>)", bytes_per_launch=bytes_it,
+                        bytes_pv=kernel_bytes(buckets, s.n, "bicg_pv"), bytes_st=kernel_bytes(buckets, s.n, "bicg_st"),
+                        mean_launch_ms=it_ms, iterations_timed=pt["krylov_iter"][1], copy_kernel_gbs=copy_gbs)
+    else:
+        # no time stepping: the dominant kernel is the fused 3-operator apply
+        ap = hy["apply"]["f64"]
+        roofline = dict(bound="hbm", achieved=ap["achieved_gbs"], peak=HBM_PEAK_GBS, unit="GB/s", frac=ap["frac"],
+                        traffic=None, kernel="k_apply<double, Acc<double>, 3>",
+                        bytes_per_launch=ap["bytes_per_launch"], mean_launch_ms=ap["mean_launch_ms"],
+                        copy_kernel_gbs=copy_gbs)
+    if multi:
+        mdesc = f"m per domain ({int((s.m == 2).sum())} domains m=2 n=12, {int((s.m == 4).sum())} m=4 n=30)"
+        per_step = "stencil build + 3-field apply (time stepping of many domains in one launch: not built)"
+    else:
+        n_s = 2 * int(round(np.prod([m + k for k in range(1, D + 1)]) / np.prod(range(1, D + 1))))
+        mdesc = f"m={m} (n={n_s})"
+        per_step = (f"stencil build + 3-field apply + {args.time_steps} Boussinesq steps (Ra={Ra:g}, Pr=0.71, "
+                    f"dt=0.1h^2/2, pressure rel. residual {args.tol})")
     out = dict(metric=METRIC, value=hy["applies"] / el, unit="node-applies/s", n_gpus=1, steps=args.steps,
                warmup=args.warmup, ms_per_step=el / args.steps * 1e3, higher_is_better=True, scaling="weak",
                vs_baseline=None, dtype="f64", data="synthetic",
-               config=dict(workload=f"{wdesc}, m={m} (n={n_s}), hybrid; per step: stencil build + 3-field apply + "
-                                    f"{args.time_steps} Boussinesq steps (Ra={Ra:g}, Pr=0.71, dt=0.1h^2/2, pressure "
-                                    f"rel. residual {args.tol})",
-                           name=args.workload, nodes=s.n, n_regular=info["n_regular"], n_scattered=info["n_scattered"],
-                           time_steps_per_step=args.time_steps, krylov_tol=args.tol),
+               config=dict(workload=f"{wdesc}, {mdesc}, hybrid; per step: {per_step}",
+                           name=args.workload, nodes=s.n, domains=(s.n_domains if multi else 1),
+                           n_regular=info["n_regular"], n_scattered=info["n_scattered"],
+                           time_steps_per_step=(args.time_steps if stepping else 0), krylov_tol=args.tol),
                solves_per_s=hy["solves"] / hy["build_s"], solves_per_s_device=hy["solves"] / (hy["solve_dev_ms"] * 1e-3),
-               krylov_iters_per_time_step=hy["krylov_iters"] / (args.steps * args.time_steps),
-               phase_mean_ms={k: v[0] for k, v in pt.items()},
                apply=hy["apply"],
                roofline=roofline)
+    if stepping:
+        out["krylov_iters_per_time_step"] = hy["krylov_iters"] / (args.steps * args.time_steps)
+        out["phase_mean_ms"] = {k: v[0] for k, v in pt.items()}
     if "all_scattered" in results:
         a = results["all_scattered"]
         out["all_scattered"] = dict(value=a["applies"] / a["elapsed_s"], ms_per_step=a["elapsed_s"] / args.steps * 1e3,
-                                    krylov_iters_per_time_step=a["krylov_iters"] / (args.steps * args.time_steps),
                                     solves_per_s=a["solves"] / a["build_s"],
                                     solves_per_s_device=a["solves"] / (a["solve_dev_ms"] * 1e-3),
-                                    phase_mean_ms={k: v[0] for k, v in a["ptimes"].items()},
                                     apply=a["apply"])
         out["hybrid_speedup_per_step"] = a["elapsed_s"] / el
-        # per-iteration cost ratio of the pressure operator (same node set, same kernels)
-        out["hybrid_speedup_per_krylov_iteration"] = a["ptimes"]["krylov_iter"][0] / it_ms
         out["hybrid_speedup_apply"] = a["apply"]["f64"]["mean_launch_ms"] / hy["apply"]["f64"]["mean_launch_ms"]
+        if stepping:
+            out["all_scattered"]["krylov_iters_per_time_step"] = a["krylov_iters"] / (args.steps * args.time_steps)
+            out["all_scattered"]["phase_mean_ms"] = {k: v[0] for k, v in a["ptimes"].items()}
+            # per-iteration cost ratio of the pressure operator (same node set, same kernels)
+            out["hybrid_speedup_per_krylov_iteration"] = a["ptimes"]["krylov_iter"][0] / it_ms
     if fp32:
         out["fp32_form"] = fp32
     if not args.no_cpu_baseline:
-        log("cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline(s, m)
+        if multi:
+            log("cpu baseline: measured on the single-domain workloads only")
+        else:
+            log("cpu baseline (oracle) ...")
+            out["cpu_baseline"] = cpu_baseline(s, m)
     print(json.dumps(out), flush=True)
     return 0
 

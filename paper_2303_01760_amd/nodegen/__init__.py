@@ -152,3 +152,49 @@ def random_cloud(n: int, d: int = 2, seed: int = 0, h: float = 0.1) -> NodeSet:
     z = np.zeros(n)
     return NodeSet(d=d, h=h, x=x, kind=np.zeros(n, np.uint8), normal=np.zeros((d, n)), tbc=z.copy(),
                    origin=np.full(n, 2, np.int8), group=np.full(n, -1, np.int32), name=f"cloud{d}d_{n}")
+
+
+@dataclass
+class Batch:
+    """Independent domains concatenated: domain k holds nodes [off[k], off[k+1])."""
+    d: int
+    x: np.ndarray                 # float64 [d, N]
+    kind: np.ndarray              # uint8 [N]
+    normal: np.ndarray            # float64 [d, N]
+    tbc: np.ndarray               # float64 [N]
+    off: np.ndarray               # int64 [K+1]
+    h: np.ndarray                 # float64 [K], lattice spacing per domain
+    m: np.ndarray                 # int32 [K], scattered polynomial degree per domain
+    name: str = ""
+
+    @property
+    def n(self) -> int:
+        return int(self.x.shape[1])
+
+    @property
+    def n_domains(self) -> int:
+        return len(self.off) - 1
+
+
+def batch2d(n_domains: int = 512, nmin: int = 1000, nmax: int = 50000, n_obst: int = 4,
+            seed_base: int = SEED_BASE * 10) -> Batch:
+    """Many independent 2D obstacle domains of uneven size: domain k draws, from
+    seed seed_base + k, a node count log-uniform in [nmin, nmax] (which sets its
+    lattice spacing h = 1/round(sqrt(count / 0.8))), a scattered degree m in
+    {2, 4}, and n_obst circles of radius 0.04-0.1 with a band max(0.05, 3h)."""
+    sets, hs, ms = [], [], []
+    for k in range(n_domains):
+        rng = np.random.default_rng(seed_base + k)
+        target = float(np.exp(rng.uniform(np.log(nmin), np.log(nmax))))
+        m = int(rng.choice([2, 4]))
+        h = 1.0 / max(8, int(round(np.sqrt(target / 0.8))))   # the lattice must divide the unit box
+        band = max(0.05, 3.0 * h)
+        s = generate(2, h, obst_band=band, n_obst=n_obst, rmin=0.04, rmax=0.1,
+                     wall_kind=[KIND_NEUMANN] * 4, seed=seed_base + k, name=f"batch_{k}")
+        sets.append(s)
+        hs.append(h)
+        ms.append(m)
+    off = np.cumsum([0] + [s.n for s in sets]).astype(np.int64)
+    return Batch(d=2, x=np.concatenate([s.x for s in sets], axis=1), kind=np.concatenate([s.kind for s in sets]),
+                 normal=np.concatenate([s.normal for s in sets], axis=1), tbc=np.concatenate([s.tbc for s in sets]),
+                 off=off, h=np.asarray(hs), m=np.asarray(ms, np.int32), name=f"batch2d_{n_domains}")
