@@ -440,13 +440,16 @@ void ora_apply(int64_t N, const int64_t *off, const int32_t *idx, const double *
 /* ------------------------------------------------- pressure problem ----- */
 /* The pressure operator: row i holds the Laplacian weights at interior nodes
  * and the normal-derivative weights at boundary nodes (dp/dn = 0 on no-slip
- * walls), each row divided by its centre weight.  The zero-mean condition is
- * added as a border:  [[A, 1], [1^T, 0]] [p; lam] = [b; 0]. */
+ * walls), each row divided by its centre weight.  Each domain k's zero-mean
+ * condition is added as a border row and column (its multiplier lam_k at
+ * unknown N + k):  sum_j a_ij p_j + lam_dom(i) = b_i,  sum_{i in k} p_i = 0.
+ * With one domain: [[A, 1], [1^T, 0]] [p; lam] = [b; 0]. */
 typedef struct {
-  int64_t N;
+  int64_t N, K;
   const int64_t *off;
   const int32_t *idx;
-  double *a; /* scaled row weights, CSR */
+  const int32_t *dom; /* domain of each node */
+  double *a;          /* scaled row weights, CSR */
 } pop_t;
 
 static void pop_matvec(const pop_t *P, const double *v, double *out) {
@@ -454,11 +457,10 @@ static void pop_matvec(const pop_t *P, const double *v, double *out) {
   for (int64_t i = 0; i < N; ++i) {
     double acc = 0.0;
     for (int64_t t = P->off[i]; t < P->off[i + 1]; ++t) acc = acc + P->a[t] * v[P->idx[t]];
-    out[i] = acc + v[N];
+    out[i] = acc + v[N + P->dom[i]];
   }
-  double s = 0.0;
-  for (int64_t i = 0; i < N; ++i) s = s + v[i];
-  out[N] = s;
+  for (int64_t k = 0; k < P->K; ++k) out[N + k] = 0.0;
+  for (int64_t i = 0; i < N; ++i) out[N + P->dom[i]] = out[N + P->dom[i]] + v[i];
 }
 
 static double dot(int64_t n, const double *a, const double *b) {
@@ -468,10 +470,10 @@ static double dot(int64_t n, const double *a, const double *b) {
 }
 
 /* BiCGSTAB (van der Vorst 1992) on the bordered system, from the initial
- * guess in x[0..N], until ||r|| <= tol ||b||.  Returns iterations used, or
+ * guess in x[0..N+K), until ||r|| <= tol ||b||.  Returns iterations used, or
  * -1 if not converged within maxiter / on breakdown. */
 static int bicgstab(const pop_t *P, const double *b, double *x, double tol, int maxiter, double *relres) {
-  const int64_t n = P->N + 1;
+  const int64_t n = P->N + P->K;
   double *r = malloc(sizeof(double) * n), *rh = malloc(sizeof(double) * n);
   double *p = calloc(n, sizeof(double)), *v = calloc(n, sizeof(double));
   double *s = malloc(sizeof(double) * n), *t = malloc(sizeof(double) * n);
@@ -522,19 +524,21 @@ done:
   return it;
 }
 
-/* Dense form of the same bordered pressure system, row-major [(N+1)^2].  For
- * small problems the oracle factorises it once and solves exactly. */
+/* Dense form of the same bordered pressure system, row-major [(N+K)^2], K
+ * domains given by dom_off [K+1].  For small problems the oracle factorises
+ * it once and solves exactly. */
 int ora_pressure_dense(int64_t N, const int64_t *off, const int32_t *idx, const double *wlap,
-                       const double *wn, const uint8_t *kind, double *M) {
-  const int64_t n = N + 1;
+                       const double *wn, const uint8_t *kind, int32_t K, const int64_t *dom_off, double *M) {
+  const int64_t n = N + K;
   memset(M, 0, sizeof(double) * n * n);
-  for (int64_t i = 0; i < N; ++i) {
-    const double *wr = kind[i] ? wn : wlap;
-    double dg = wr[off[i]];
-    for (int64_t t = off[i]; t < off[i + 1]; ++t) M[i * n + idx[t]] += wr[t] / dg;
-    M[i * n + N] = 1.0;
-    M[N * n + i] = 1.0;
-  }
+  for (int64_t k = 0; k < K; ++k)
+    for (int64_t i = dom_off[k]; i < dom_off[k + 1]; ++i) {
+      const double *wr = kind[i] ? wn : wlap;
+      double dg = wr[off[i]];
+      for (int64_t t = off[i]; t < off[i + 1]; ++t) M[i * n + idx[t]] += wr[t] / dg;
+      M[i * n + N + k] = 1.0;
+      M[(N + k) * n + i] = 1.0;
+    }
   return ORA_OK;
 }
 
@@ -546,8 +550,8 @@ typedef struct {
   int32_t solver; /* 0: BiCGSTAB, 1: dense LU of the bordered system */
 } ora_params;
 
-/* State carried between steps by the caller: v [d][N], T [N], p [N+1]
- * (p[N] is the border multiplier).  CSR stencils with weights wop[a] for
+/* State carried between steps by the caller: v [d][N], T [N], p [N+K]
+ * (p[N+k] is domain k's border multiplier).  CSR stencils with weights wop[a] for
  * d/dx_a (a < d) and wop[d] for the Laplacian; wn holds normal-derivative
  * weights (read at boundary nodes only).  dense_lu: optional factorised
  * dense system (from ora_pressure_dense; may be NULL for BiCGSTAB).
@@ -565,7 +569,8 @@ typedef struct {
  * iters_out receives the Krylov iteration count. */
 typedef struct {
   int d;
-  int64_t N;
+  int64_t N, K;
+  int32_t *dom;
   const int64_t *off;
   const int32_t *idx;
   const double *wop[4];
@@ -578,13 +583,17 @@ typedef struct {
 } ora_sim;
 
 void *ora_sim_create(int d, int64_t N, const int64_t *off, const int32_t *idx, const double *const *wop,
-                     const double *wn, const uint8_t *kind, int solver) {
+                     const double *wn, const uint8_t *kind, int32_t K, const int64_t *dom_off, int solver) {
+  if (K < 1 || dom_off[0] != 0 || dom_off[K] != N) return NULL;
   ora_sim *S = calloc(1, sizeof(ora_sim));
   if (!S) return NULL;
-  S->d = d; S->N = N; S->off = off; S->idx = idx; S->wn = wn; S->kind = kind;
+  S->d = d; S->N = N; S->K = K; S->off = off; S->idx = idx; S->wn = wn; S->kind = kind;
+  S->dom = malloc(sizeof(int32_t) * (N > 0 ? N : 1));
+  for (int64_t k = 0; k < K; ++k)
+    for (int64_t i = dom_off[k]; i < dom_off[k + 1]; ++i) S->dom[i] = (int32_t)k;
   for (int a = 0; a <= d; ++a) S->wop[a] = wop[a];
   int64_t nnz = off[N];
-  S->P.N = N; S->P.off = off; S->P.idx = idx;
+  S->P.N = N; S->P.K = K; S->P.off = off; S->P.idx = idx; S->P.dom = S->dom;
   S->P.a = malloc(sizeof(double) * (nnz > 0 ? nnz : 1));
   for (int64_t i = 0; i < N; ++i) {
     const double *wr = kind[i] ? wn : wop[d];
@@ -595,14 +604,14 @@ void *ora_sim_create(int d, int64_t N, const int64_t *off, const int32_t *idx, c
   S->g0 = malloc(sizeof(double) * N);
   S->g1 = malloc(sizeof(double) * N);
   S->g2 = malloc(sizeof(double) * N);
-  S->rhs = malloc(sizeof(double) * (N + 1));
+  S->rhs = malloc(sizeof(double) * (N + K));
   S->Tn = malloc(sizeof(double) * N);
   if (solver == 1) {
-    const int64_t n = N + 1;
+    const int64_t n = N + K;
     S->dense = malloc(sizeof(double) * n * n);
     S->dpiv = malloc(sizeof(int) * n);
     if (!S->dense || !S->dpiv) return S;
-    ora_pressure_dense(N, off, idx, wop[d], wn, kind, S->dense);
+    ora_pressure_dense(N, off, idx, wop[d], wn, kind, K, dom_off, S->dense);
     /* factorise once: same pivoting rule as ora_dense_lu_solve, rows kept in place */
     int *used = calloc(n, sizeof(int));
     for (int64_t k = 0; k < n; ++k) {
@@ -628,13 +637,13 @@ void *ora_sim_create(int d, int64_t N, const int64_t *off, const int32_t *idx, c
 void ora_sim_destroy(void *h) {
   ora_sim *S = (ora_sim *)h;
   if (!S) return;
-  free(S->P.a); free(S->vs); free(S->g0); free(S->g1); free(S->g2); free(S->rhs); free(S->Tn);
+  free(S->P.a); free(S->vs); free(S->g0); free(S->g1); free(S->g2); free(S->rhs); free(S->Tn); free(S->dom);
   free(S->dense); free(S->dpiv);
   free(S);
 }
 
 static void dense_solve(const ora_sim *S, double *b, double *x) {
-  const int64_t n = S->N + 1;
+  const int64_t n = S->N + S->K;
   /* forward: replay the elimination on b in pivot order */
   char *used = calloc(n, 1);
   for (int64_t k = 0; k < n; ++k) {
@@ -681,7 +690,7 @@ void ora_predict(void *h, const ora_params *prm, const double *v, const double *
 }
 
 /* Step 2 (right-hand side of the pressure problem): div(vs) / dt at interior
- * nodes divided by the row's centre weight, 0 at boundary nodes, 0 in the border. */
+ * nodes divided by the row's centre weight, 0 at boundary nodes, 0 in the borders. */
 void ora_pressure_rhs(void *h, const ora_params *prm, const double *vs, double *rhs) {
   ora_sim *S = (ora_sim *)h;
   const int d = S->d;
@@ -696,7 +705,7 @@ void ora_pressure_rhs(void *h, const ora_params *prm, const double *vs, double *
     }
     rhs[i] = (dv / prm->dt) / S->wop[d][S->off[i]];
   }
-  rhs[N] = 0.0;
+  for (int64_t k = 0; k < S->K; ++k) rhs[N + k] = 0.0;
 }
 
 /* Step 3 (projection): v = vs - dt grad p at interior nodes, 0 at boundary nodes. */

@@ -60,9 +60,9 @@ def lib():
                                 _i64, _p, ctypes.c_int, _p, _p, _p, _p, _p, _p]
         L.ora_apply.restype = None
         L.ora_apply.argtypes = [_i64, _p, _p, _p, _p, _p]
-        L.ora_pressure_dense.argtypes = [_i64, _p, _p, _p, _p, _p, _p]
+        L.ora_pressure_dense.argtypes = [_i64, _p, _p, _p, _p, _p, _i32, _p, _p]
         L.ora_sim_create.restype = _p
-        L.ora_sim_create.argtypes = [ctypes.c_int, _i64, _p, _p, _p, _p, _p, ctypes.c_int]
+        L.ora_sim_create.argtypes = [ctypes.c_int, _i64, _p, _p, _p, _p, _p, _i32, _p, ctypes.c_int]
         L.ora_sim_destroy.restype = None
         L.ora_sim_destroy.argtypes = [_p]
         L.ora_sim_step.argtypes = [_p, ctypes.POINTER(OracleParams), ctypes.c_int, _p, _p, _p, _p]
@@ -230,19 +230,22 @@ def apply(csr, wrow, u):
     return out
 
 
-def pressure_dense(csr, kind):
+def pressure_dense(csr, kind, dom_off=None):
+    """The bordered pressure matrix [(N+K)^2]: one border row/column per domain."""
     N = len(csr["off"]) - 1
-    M = np.empty((N + 1, N + 1), np.float64)
+    dom_off = _c(dom_off if dom_off is not None else [0, N], np.int64)
+    K = len(dom_off) - 1
+    M = np.empty((N + K, N + K), np.float64)
     d = csr["d"]
     lib().ora_pressure_dense(N, _ptr(csr["off"]), _ptr(csr["idx"]), _ptr(_c(csr["w"][d], np.float64)),
-                             _ptr(_c(csr["wn"], np.float64)), _ptr(_c(kind, np.uint8)), _ptr(M))
+                             _ptr(_c(csr["wn"], np.float64)), _ptr(_c(kind, np.uint8)), K, _ptr(dom_off), _ptr(M))
     return M
 
 
 class Sim:
     """Explicit Euler Boussinesq stepping with Chorin projection (Section 3)."""
 
-    def __init__(self, csr, kind, solver=0):
+    def __init__(self, csr, kind, solver=0, dom_off=None):
         self.csr = csr
         self.kind = _c(kind, np.uint8)
         d = csr["d"]
@@ -250,15 +253,16 @@ class Sim:
         arr = (ctypes.c_void_p * 4)(*[w.ctypes.data for w in self._w], *([None] * (3 - d)))
         self._wn = _c(csr["wn"], np.float64)
         N = len(csr["off"]) - 1
-        self.N, self.d = N, d
+        self._dom_off = _c(dom_off if dom_off is not None else [0, N], np.int64)
+        self.N, self.d, self.K = N, d, len(self._dom_off) - 1
         self.h = lib().ora_sim_create(d, N, _ptr(csr["off"]), _ptr(csr["idx"]), arr, _ptr(self._wn),
-                                      _ptr(self.kind), int(solver))
+                                      _ptr(self.kind), self.K, _ptr(self._dom_off), int(solver))
         if not self.h:
             raise OracleError(E_INVALID)
 
     def step(self, v, T, p, nsteps, Ra, Pr, dt, T_ref, tol=1e-12, maxiter=20000):
-        """Advance v [d,N], T [N], p [N+1] in place by nsteps; returns Krylov iterations per step."""
-        for a, shape in ((v, (self.d, self.N)), (T, (self.N,)), (p, (self.N + 1,))):
+        """Advance v [d,N], T [N], p [N+K] in place by nsteps; returns Krylov iterations per step."""
+        for a, shape in ((v, (self.d, self.N)), (T, (self.N,)), (p, (self.N + self.K,))):
             assert a.dtype == np.float64 and a.flags.c_contiguous and a.shape == shape
         prm = OracleParams(Ra, Pr, dt, T_ref, tol, maxiter, 0)
         its = np.zeros(nsteps, np.int32)

@@ -544,3 +544,61 @@ def test_wall_node_with_deficient_stencil_falls_back_to_degree_m_minus_1():
         # the normal-derivative weights are n . grad weights
         wn = sum(s.normal[a, i] * st["w"][r, a, :20] for a in range(3))
         np.testing.assert_allclose(st["wn"][r, :20], wn, rtol=0, atol=1e-12 * np.abs(wn).max())
+
+
+def _three_domains():
+    sets = [ng.cavity2d(h=0.0625, seed=31), ng.cavity2d(h=0.05, seed=32),
+            ng.obstacles2d(h=0.05, n_obst=2, rmin=0.08, rmax=0.12, band=0.15, seed=33)]
+    x = np.concatenate([q.x for q in sets], axis=1)
+    kind = np.concatenate([q.kind for q in sets])
+    nrm = np.concatenate([q.normal for q in sets], axis=1)
+    tbc = np.concatenate([q.tbc for q in sets])
+    off = np.cumsum([0] + [q.n for q in sets]).astype(np.int64)
+    return sets, x, kind, nrm, tbc, off
+
+
+def test_multi_domain_pressure_system_has_one_border_per_domain():
+    sets, x, kind, nrm, tbc, off = _three_domains()
+    hs = [q.h for q in sets]
+    csr = O.to_csr(O.build(x, kind, nrm, hs, 2, dom_off=off))
+    M = O.pressure_dense(csr, kind, dom_off=off)
+    N, K = len(kind), len(sets)
+    assert M.shape == (N + K, N + K)
+    for k in range(K):
+        rows = np.arange(off[k], off[k + 1])
+        # the border column of domain k is 1 exactly on its rows, its border row sums its nodes
+        np.testing.assert_array_equal(M[:N, N + k], np.isin(np.arange(N), rows).astype(float))
+        np.testing.assert_array_equal(M[N + k, :N], np.isin(np.arange(N), rows).astype(float))
+        # no coupling between domains
+        others = np.setdiff1d(np.arange(N), rows)
+        assert not M[np.ix_(rows, others)].any()
+    assert not M[N:, N:].any()
+
+
+def test_multi_domain_step_equals_independent_domains():
+    # the domains share nothing: stepping them together (one bordered system
+    # with a border per domain) equals stepping each alone
+    sets, x, kind, nrm, tbc, off = _three_domains()
+    hs = [q.h for q in sets]
+    prm = dict(Ra=1e4, Pr=0.71, dt=0.1 * min(hs) ** 2 / 2, T_ref=0.5)
+    csr = O.to_csr(O.build(x, kind, nrm, hs, 2, dom_off=off))
+    N, K = len(kind), len(sets)
+    T0 = np.where(kind == 1, tbc, 0.5)
+    T0 = np.where(kind == 0, 0.5 + 0.2 * np.sin(4 * x[0]) * np.cos(3 * x[1]), T0)
+    results = {}
+    for solver in (1, 0):
+        v, T, p = np.zeros((2, N)), T0.copy(), np.zeros(N + K)
+        O.Sim(csr, kind, solver=solver, dom_off=off).step(v, T, p, 5, tol=1e-13, maxiter=50000, **prm)
+        results[solver] = (v, T, p)
+    for k, q in enumerate(sets):
+        a, b = off[k], off[k + 1]
+        ck = O.to_csr(O.build(q.x, q.kind, q.normal, q.h, 2))
+        # the same stencils, shifted by the domain offset
+        np.testing.assert_array_equal(csr["idx"][csr["off"][a]:csr["off"][b]] - a, ck["idx"])
+        v, T, p = np.zeros((2, q.n)), T0[a:b].copy(), np.zeros(q.n + 1)
+        O.Sim(ck, q.kind, solver=1).step(v, T, p, 5, **prm)
+        for solver, tol in ((1, 1e-10), (0, 1e-8)):
+            vm, Tm, pm = results[solver]
+            for got, want in ((vm[:, a:b], v), (Tm[a:b], T), (pm[a:b], p[:-1])):
+                assert np.abs(got - want).max() <= tol * max(np.abs(want).max(), 1e-30)
+            assert abs(pm[N + k] - p[-1]) <= tol * max(abs(p[-1]), np.abs(p[:-1]).max())
