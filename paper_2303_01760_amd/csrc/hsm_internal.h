@@ -104,6 +104,7 @@ namespace hsm { struct BucketTable; }
 
 struct hsm_stencils {
   int32_t d = 0, mode = 0, n_domains = 0;
+  std::vector<int64_t> dom_off;   // [n_domains + 1] domain ranges, caller numbering (host)
   int64_t N = 0, nnz = 0, n_regular = 0, n_scattered = 0, n_boundary = 0;
   int64_t n_wall_fallback = 0;   // wall nodes solved with monomials of degree m-1
   std::vector<hsm::Bucket> buckets;

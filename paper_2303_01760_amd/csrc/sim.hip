@@ -54,9 +54,9 @@ struct hsm_sim {
   double k_sum_ms[HSM_PH_COUNT] = {};
   int64_t k_cnt[HSM_PH_COUNT] = {};
   int post_pending = -1;     // parity of a post phase whose events are not read yet
-  BucketTable tab_all{};
-  DBuf dtab;
-  int64_t nblk_nodes = 0;
+  int32_t K = 1;              // domains (border rows)
+  int64_t nblk = 0;           // blocks of every node launch
+  DBuf blk, dom_blk_off, dom_blk;   // block descriptors; per-domain block lists
   bool f32 = false;           // FP32 field form (HSM_F32_COMP)
   bool sepred = false;        // grid totals by a separate one-block kernel (large grids)
 
@@ -83,8 +83,11 @@ namespace {
 SimArgs make_args(hsm_sim *m, int par, int kpar) {
   SimArgs a;
   std::memset(&a, 0, sizeof(a));
-  a.tab = m->dtab.as<BucketTable>();
-  a.bm = make_blockmap(m->tab_all);
+  a.blk = m->blk.as<BlockDesc>();
+  a.nblk = m->nblk;
+  a.K = m->K;
+  a.dom_blk_off = m->dom_blk_off.as<int32_t>();
+  a.dom_blk = m->dom_blk.as<int32_t>();
   a.N = m->N;
   a.dt = m->prm.dt; a.Ra = m->prm.Ra; a.Pr = m->prm.Pr; a.T_ref = m->prm.T_ref; a.tol = m->prm.krylov_tol;
   a.maxiter = m->prm.krylov_maxiter;
@@ -105,16 +108,11 @@ SimArgs make_args(hsm_sim *m, int par, int kpar) {
   return a;
 }
 
-// Device address of a Scalars member (no host dereference of the device pointer).
-inline double *sc_member(Scalars *sc, size_t off) {
-  return reinterpret_cast<double *>(reinterpret_cast<char *>(sc) + off);
-}
-
 // Kernel launches of each phase.
 template <int D>
 hsm_status enqueue_pre(hsm_sim *m, int par, hipStream_t s) {
   SimArgs a = make_args(m, par, 0);
-  const dim3 g((unsigned)m->tab_all.nblocks), b(kBS);
+  const dim3 g((unsigned)m->nblk), b(kBS);
   if (m->f32) {
     hipLaunchKernelGGL((k_predict<D, float>), g, b, 0, s, a);
     hipLaunchKernelGGL((k_rhs<D, float>), g, b, 0, s, a);
@@ -122,9 +120,7 @@ hsm_status enqueue_pre(hsm_sim *m, int par, hipStream_t s) {
     hipLaunchKernelGGL((k_predict<D, double>), g, b, 0, s, a);
     hipLaunchKernelGGL((k_rhs<D, double>), g, b, 0, s, a);
   }
-  if (m->sepred)
-    hipLaunchKernelGGL(k_reduce<kNR>, dim3(1), dim3(1024), 0, s, a.partR, m->tab_all.nblocks, a.sc,
-                       sc_member(a.sc, offsetof(Scalars, tot_r)));
+  if (m->sepred) hipLaunchKernelGGL(k_reduce_r, dim3(1), dim3(kRedThreads), 0, s, a);
   HSM_HIP(hipGetLastError());
   return HSM_OK;
 }
@@ -133,17 +129,13 @@ hsm_status enqueue_pre(hsm_sim *m, int par, hipStream_t s) {
 // iteration number, so a batch may be split across launch paths.
 template <int D>
 hsm_status enqueue_krylov(hsm_sim *m, int slot, hipStream_t s, int it0, int it1, bool flags) {
-  const dim3 g((unsigned)m->tab_all.nblocks), b(kBS);
+  const dim3 g((unsigned)m->nblk), b(kBS);
   for (int it = it0; it < it1; ++it) {
     SimArgs a = make_args(m, 0, it & 1);
     hipLaunchKernelGGL(k_bicg_pv<D>, g, b, 0, s, a, it);
-    if (m->sepred)
-      hipLaunchKernelGGL(k_reduce<kNA>, dim3(1), dim3(1024), 0, s, a.partA, m->tab_all.nblocks, a.sc,
-                         sc_member(a.sc, offsetof(Scalars, tot_a)));
+    if (m->sepred) hipLaunchKernelGGL(k_reduce_a, dim3(1), dim3(kRedThreads), 0, s, a, it);
     hipLaunchKernelGGL(k_bicg_st<D>, g, b, 0, s, a, it);
-    if (m->sepred)
-      hipLaunchKernelGGL(k_reduce<kNB>, dim3(1), dim3(1024), 0, s, a.partB, m->tab_all.nblocks, a.sc,
-                         sc_member(a.sc, offsetof(Scalars, tot_b)));
+    if (m->sepred) hipLaunchKernelGGL(k_reduce_b, dim3(1), dim3(kRedThreads), 0, s, a, it);
   }
   HSM_HIP(hipGetLastError());
   if (flags) {
@@ -159,7 +151,7 @@ hsm_status enqueue_krylov(hsm_sim *m, int slot, hipStream_t s, int it0, int it1,
 template <int D>
 hsm_status enqueue_post(hsm_sim *m, int par, hipStream_t s) {
   SimArgs a = make_args(m, par, 0);
-  const dim3 g((unsigned)m->tab_all.nblocks), b(kBS);
+  const dim3 g((unsigned)m->nblk), b(kBS);
   if (m->f32) {
     hipLaunchKernelGGL((k_correct_heat<D, float>), g, b, 0, s, a);
     hipLaunchKernelGGL((k_neumann<D, float>), g, b, 0, s, a);
@@ -344,36 +336,96 @@ hsm_status hsm_sim_create(const hsm_stencils *st, const hsm_sim_params *prm, con
       (rc = m->T[1].alloc(fsz * N)) || (rc = m->sc.alloc(sizeof(Scalars))))
     return rc;
   if (m->f32 && (rc = ensure_w32(st, us))) return rc;
+  // Krylov vectors: N node rows and one border row per domain
+  m->K = st->n_domains;
+  const int64_t NK = N + m->K;
   for (auto &b : m->vec)
-    if ((rc = b.alloc(sizeof(double) * (N + 1)))) return rc;
+    if ((rc = b.alloc(sizeof(double) * NK))) return rc;
   for (auto &b : m->pairs)
-    if ((rc = b.alloc(sizeof(double2) * (N + 1)))) return rc;
+    if ((rc = b.alloc(sizeof(double2) * NK))) return rc;
   m->x = m->vec[0].as<double>(); m->rh = m->vec[1].as<double>();
   m->ST = m->pairs[0].as<double2>(); m->PV[0] = m->pairs[1].as<double2>(); m->PV[1] = m->pairs[2].as<double2>();
   m->RV = m->pairs[3].as<double2>();
-  make_table(st, m->tab_all, kBS, 0xFu, m->f32);   // field weights in the field storage type
-  // grid totals: in every block's prologue for small grids; by a separate
-  // one-block kernel once every block reading every partial costs more than
-  // that launch (measured crossover near a thousand blocks)
-  m->sepred = prm->reduce_mode == 2 || (prm->reduce_mode == 0 && m->tab_all.nblocks > kSepReduceBlocks);
-  if ((rc = m->partR.alloc(sizeof(double) * kNR * (m->tab_all.nblocks + 1))) ||
-      (rc = m->partA.alloc(sizeof(double) * kNA * (m->tab_all.nblocks + 1))) ||
-      (rc = m->partB.alloc(sizeof(double) * kNB * (m->tab_all.nblocks + 1))))
-    return rc;
-  int k = 0;
-  for (const Bucket &B : st->buckets) {
-    if (B.count == 0) continue;
-    if ((rc = m->wP[k].alloc(sizeof(double) * B.width * B.count))) return rc;
-    const int slot = (B.type == B_DIR || B.type == B_NEU) ? st->d + 1 : st->d;
-    hipLaunchKernelGGL(k_scale_rows, dim3(nblk(B.count, 256)), dim3(256), 0, us, B.w.as<double>(), B.count, B.width,
-                       slot, m->wP[k].as<double>());
-    if (B.type == B_REG || B.type == B_SCAT) m->n_int += B.count;
-    if (B.type == B_NEU) m->n_neu += B.count;
-    m->tab_all.b[k].aux = m->wP[k].p;
-    ++k;
+  // pressure-operator rows, per bucket
+  std::vector<const void *> wp_of(st->buckets.size(), nullptr);
+  {
+    int k = 0;
+    for (size_t kb = 0; kb < st->buckets.size(); ++kb) {
+      const Bucket &B = st->buckets[kb];
+      if (B.count == 0) continue;
+      if ((rc = m->wP[k].alloc(sizeof(double) * B.width * B.count))) return rc;
+      const int slot = (B.type == B_DIR || B.type == B_NEU) ? st->d + 1 : st->d;
+      hipLaunchKernelGGL(k_scale_rows, dim3(nblk(B.count, 256)), dim3(256), 0, us, B.w.as<double>(), B.count,
+                         B.width, slot, m->wP[k].as<double>());
+      if (B.type == B_REG || B.type == B_SCAT) m->n_int += B.count;
+      if (B.type == B_NEU) m->n_neu += B.count;
+      wp_of[kb] = m->wP[k].p;
+      ++k;
+    }
   }
-  if ((rc = m->dtab.alloc(sizeof(BucketTable)))) return rc;
-  HSM_HIP(hipMemcpyAsync(m->dtab.p, &m->tab_all, sizeof(BucketTable), hipMemcpyHostToDevice, us));
+  // blocks: up to kBS consecutive nodes of one bucket and one domain
+  std::vector<int32_t> dom_int;
+  if (m->K > 1) {
+    std::vector<int32_t> hperm(N);
+    HSM_HIP(hipMemcpyAsync(hperm.data(), st->perm.p, sizeof(int32_t) * N, hipMemcpyDeviceToHost, us));
+    HSM_HIP(hipStreamSynchronize(us));
+    dom_int.resize(N);
+    for (int64_t i = 0; i < N; ++i)
+      dom_int[i] = (int32_t)(std::upper_bound(st->dom_off.begin(), st->dom_off.end(), (int64_t)hperm[i]) -
+                             st->dom_off.begin() - 1);
+  }
+  std::vector<BlockDesc> blocks;
+  for (size_t kb = 0; kb < st->buckets.size(); ++kb) {
+    const Bucket &B = st->buckets[kb];
+    for (int64_t j = 0; j < B.count;) {
+      const int32_t dom = m->K > 1 ? dom_int[B.start + j] : 0;
+      int64_t e = j + 1;
+      while (e < B.count && e - j < kBS && (m->K == 1 || dom_int[B.start + e] == dom)) ++e;
+      BlockDesc bd;
+      std::memset(&bd, 0, sizeof(bd));
+      bd.idx = B.idx.p;
+      bd.w = m->f32 ? B.w32.p : B.w.p;             // field weights in the field storage type
+      bd.wP = wp_of[kb];
+      bd.bstart = B.start;
+      bd.first = (int32_t)j;
+      bd.nodes = (int32_t)(e - j);
+      bd.count = (int32_t)B.count;
+      bd.type = B.type;
+      bd.width = B.width;
+      bd.domain = dom;
+      blocks.push_back(bd);
+      j = e;
+    }
+  }
+  m->nblk = (int64_t)blocks.size();
+  std::vector<int32_t> dbo(m->K + 1, 0), dbl(blocks.size());
+  for (const BlockDesc &bd : blocks) dbo[bd.domain + 1] += 1;
+  for (int32_t d2 = 0; d2 < m->K; ++d2) dbo[d2 + 1] += dbo[d2];
+  {
+    std::vector<int32_t> fill(dbo.begin(), dbo.end() - 1);
+    for (size_t b2 = 0; b2 < blocks.size(); ++b2) dbl[fill[blocks[b2].domain]++] = (int32_t)b2;
+  }
+  if ((rc = m->blk.alloc(sizeof(BlockDesc) * (blocks.size() + 1))) ||
+      (rc = m->dom_blk_off.alloc(sizeof(int32_t) * dbo.size())) ||
+      (rc = m->dom_blk.alloc(sizeof(int32_t) * (dbl.size() + 1))))
+    return rc;
+  HSM_HIP(hipMemcpyAsync(m->blk.p, blocks.data(), sizeof(BlockDesc) * blocks.size(), hipMemcpyHostToDevice, us));
+  HSM_HIP(hipMemcpyAsync(m->dom_blk_off.p, dbo.data(), sizeof(int32_t) * dbo.size(), hipMemcpyHostToDevice, us));
+  HSM_HIP(hipMemcpyAsync(m->dom_blk.p, dbl.data(), sizeof(int32_t) * dbl.size(), hipMemcpyHostToDevice, us));
+  HSM_HIP(hipStreamSynchronize(us));      // the host vectors above go out of scope
+  // grid totals: in every block's prologue for one domain on a small grid;
+  // otherwise by the reduction kernels, which also own the border rows (a
+  // block reading every partial costs more than a launch near a thousand
+  // blocks; many domains need per-domain sums)
+  if (m->K > 1 && prm->reduce_mode == 1) {
+    set_error(HSM_E_INVALID, "reduce_mode 1 (in-kernel reduction) needs a single domain");
+    return HSM_E_INVALID;
+  }
+  m->sepred = m->K > 1 || prm->reduce_mode == 2 || (prm->reduce_mode == 0 && m->nblk > kSepReduceBlocks);
+  if ((rc = m->partR.alloc(sizeof(double) * kNR * (m->nblk + 1))) ||
+      (rc = m->partA.alloc(sizeof(double) * kNA * (m->nblk + 1))) ||
+      (rc = m->partB.alloc(sizeof(double) * kNB * (m->nblk + 1))))
+    return rc;
   const int32_t *perm = st->perm.as<int32_t>();
   for (int c = 0; c < d; ++c) {
     if (m->f32)
@@ -388,9 +440,9 @@ hsm_status hsm_sim_create(const hsm_stencils *st, const hsm_sim_params *prm, con
   else
     hipLaunchKernelGGL((k_gather<double, double>), dim3(nblk(N, 256)), dim3(256), 0, us, T, m->T[0].as<double>(), perm,
                        N);
-  for (auto &b : m->vec) hipLaunchKernelGGL(k_fill, dim3(nblk(N + 1, 256)), dim3(256), 0, us, b.as<double>(), N + 1, 0.0);
+  for (auto &b : m->vec) hipLaunchKernelGGL(k_fill, dim3(nblk(NK, 256)), dim3(256), 0, us, b.as<double>(), NK, 0.0);
   for (auto &b : m->pairs)
-    hipLaunchKernelGGL(k_fill, dim3(nblk(2 * (N + 1), 256)), dim3(256), 0, us, b.as<double>(), 2 * (N + 1), 0.0);
+    hipLaunchKernelGGL(k_fill, dim3(nblk(2 * NK, 256)), dim3(256), 0, us, b.as<double>(), 2 * NK, 0.0);
   if (p) hipLaunchKernelGGL((k_gather<double, double>), dim3(nblk(N, 256)), dim3(256), 0, us, p, m->x, perm, N);
   hipLaunchKernelGGL(k_init_scalars, dim3(1), dim3(64), 0, us, m->sc.as<Scalars>());
   HSM_HIP(hipGetLastError());

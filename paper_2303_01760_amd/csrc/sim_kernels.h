@@ -18,7 +18,8 @@ constexpr int kNR = 3;          // partial sums of the right-hand-side kernel
 constexpr int kNA = 3;          // partial sums of the p/v kernel
 constexpr int kNB = 6;          // partial sums of the s/t kernel
 constexpr int kMaxIterChunk = 256;
-constexpr int64_t kSepReduceBlocks = 1024;   // above this grid size, totals come from k_reduce
+constexpr int64_t kSepReduceBlocks = 1024;   // above this grid size, totals come from the reduction kernels
+constexpr int kRedThreads = 1024;            // threads of a reduction kernel (one block)
 
 // Host-visible summary written once per batch of Krylov iterations.
 struct HostFlags {
@@ -30,32 +31,52 @@ struct HostFlags {
 // Krylov state.  Values a kernel computes for iteration k live in slot k & 1,
 // so kernels of iteration k never overwrite what their own blocks still read.
 struct Scalars {
-  double rho[2], alpha[2];
+  double rho[2], alpha[2], omega[2], beta[2];
   double bnorm2, relres;
-  double tot_r[kNR], tot_a[kNA], tot_b[kNB];   // grid totals from the separate reduction kernel
+  double tot_r[kNR], tot_a[kNA], tot_b[kNB];   // grid totals, border rows included (reduction kernels)
   int32_t done, fail, zero_sol, nonfinite;
   int32_t it_base, iters, early[2];   // early: 1 = |s| converged, 2 = breakdown, 3 = zero right-hand side
   HostFlags mirror;
 };
 
+// One block of a stepper launch: up to kBS consecutive nodes of one width
+// bucket, all of one domain (so a block's partial sums are sums over part of
+// one domain).
+struct BlockDesc {
+  const void *idx;     // the bucket's [width][count] int32 neighbour indices (internal numbering)
+  const void *w;       // [nops][width][count] field weights, in the field storage type
+  const void *wP;      // [width][count] FP64 pressure-operator rows (divided by the centre weight)
+  int64_t bstart;      // the bucket's first node (internal numbering)
+  int32_t first;       // this block's first node, counted from bstart
+  int32_t nodes;       // nodes in this block (<= kBS)
+  int32_t count;       // the bucket's node count: the SoA stride
+  int32_t type, width;
+  int32_t domain;      // the border row of this block's nodes is N + domain
+  int32_t pad[2];
+};
+static_assert(sizeof(BlockDesc) == 64, "one 64-byte scalar load per block");
+
 struct SimArgs {
-  const BucketTable *tab;          // device table; w in the field storage type, aux = row-scaled
-                                   // FP64 pressure weights [W][count]
-  BlockMap bm;
+  const BlockDesc *blk;            // [nblk]
+  int64_t nblk;
   int64_t N;
+  int32_t K;                       // domains: Krylov vectors hold N + K entries, slot N + k is domain k's border
+  const int32_t *dom_blk_off;      // [K+1] per-domain ranges of dom_blk
+  const int32_t *dom_blk;          // the blocks of each domain, ascending
   double dt, Ra, Pr, T_ref, tol;
   int32_t maxiter, chunk;
-  int32_t sepred;      // 1: grid totals come from k_reduce (large grids), 0: each block reduces the partials
+  int32_t sepred;      // 1: grid totals (border rows included) come from the reduction kernels;
+                       // 0: one domain, each block reduces the partials and handles the border itself
   // fields, in the field storage type (double, or float in the FP32 form)
   const void *v;      // [D][N]
   void *vs;           // [D][N]
   const void *T;      // [N]
   void *Tn;           // [N]
   void *vout;         // [D][N]
-  // Krylov vectors, each [N+1] (slot N: the border multiplier / zero-mean row)
-  double *x, *rh;                 // [N+1]
-  double2 *ST, *PVo, *PVn, *RV;   // pairs (s,t), (p,v) previous/this iteration, (r,v); [N+1]
-  double *partR, *partA, *partB;   // block partial sums [nblocks][kN*]
+  // Krylov vectors, each [N+K]
+  double *x, *rh;
+  double2 *ST, *PVo, *PVn, *RV;   // pairs (s,t), (p,v) previous/this iteration, (r,v)
+  double *partR, *partA, *partB;   // block partial sums [nblk][kN*]
   Scalars *sc;
 };
 
@@ -85,20 +106,6 @@ template <int D, class F>
 __device__ __forceinline__ void with_width(int w, F &&f) {
   if constexpr (D == 2) with_width2(w, f);
   else with_width3(w, f);
-}
-
-// bucket fields as plain scalars
-// bucket fields as plain scalars
-struct BScal {
-  int64_t start, count, block0;
-  int32_t type, width;
-  uint32_t cnt;       // count
-  const void *idx;    // [width][cnt] int32
-  const void *w;      // [nops][width][cnt] double
-  const void *wP;     // [width][cnt] double: the pressure-operator rows
-};
-__device__ __forceinline__ BScal bscal(const BucketDesc &bd) {
-  return BScal{bd.start, bd.count, bd.block0, bd.type, bd.width, (uint32_t)bd.count, bd.idx, bd.w, bd.aux};
 }
 
 // Cross-lane moves by DPP (data-parallel primitives: a VALU operand read
@@ -192,9 +199,8 @@ __device__ __forceinline__ void reduce_prev(const double *__restrict__ part, int
   }
 }
 
-// Grid totals of the previous kernel's partials: reduced in this block's
-// prologue, or (large grids, where every block reading every partial would
-// cost more than a launch) read from what k_reduce wrote.
+// One-domain small grids: each block reduces the partials in its prologue.
+// Otherwise the reduction kernels below have written the totals.
 template <int NQ>
 __device__ __forceinline__ void grid_totals(const SimArgs &a, const double *part, const double *sep,
                                             double (&tot)[NQ]) {
@@ -206,32 +212,126 @@ __device__ __forceinline__ void grid_totals(const SimArgs &a, const double *part
   }
 }
 
-// One block: the grid totals of a kernel's block partials, in a fixed order
-// (each thread sums a strided set of rows, then wave sums, then the waves in
-// order); nothing to do once the solve has stopped.
-template <int NQ>
-__global__ __launch_bounds__(1024) void k_reduce(const double *__restrict__ part, int64_t nblk, const Scalars *sc,
-                                                 double *out) {
-  if (sc->done) return;
-  __shared__ double red[16][NQ];
+// The reduction kernels (one block of kRedThreads): totals of every block's
+// partials, each thread summing a strided set of rows in order, plus the
+// border rows: thread d (d += kRedThreads) sums column qd over domain d's
+// blocks in order (the domain's share of a sum over nodes), and border(d, sum)
+// updates that border row and returns what it adds to each total.  Then wave
+// sums and the waves in order: deterministic.  Thread 0 gets the totals.
+template <int NQ, class FB, class FF>
+__device__ __forceinline__ void reduce_with_borders(const SimArgs &a, const double *__restrict__ part, int qd,
+                                                    FB &&border, FF &&finish) {
+  __shared__ double red[kRedThreads / 64][NQ];
   double acc[NQ];
 #pragma unroll
   for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
-  for (int64_t b = threadIdx.x; b < nblk; b += 1024)
+  for (int64_t b = threadIdx.x; b < a.nblk; b += kRedThreads)
 #pragma unroll
     for (int q = 0; q < NQ; ++q) acc[q] += part[b * NQ + q];
+  for (int d = threadIdx.x; d < a.K; d += kRedThreads) {
+    double sd = 0.0;
+    for (int j = a.dom_blk_off[d]; j < a.dom_blk_off[d + 1]; ++j) sd += part[(int64_t)a.dom_blk[j] * NQ + qd];
+    const Pack<double, NQ> inc = border(d, sd);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) acc[q] += inc.v[q];
+  }
 #pragma unroll
   for (int q = 0; q < NQ; ++q) acc[q] = wave_sum(acc[q]);
   if ((threadIdx.x & 63) == 0)
 #pragma unroll
     for (int q = 0; q < NQ; ++q) red[threadIdx.x >> 6][q] = acc[q];
   __syncthreads();
-  if (threadIdx.x < NQ) {
-    double s = red[0][threadIdx.x];
+  if (threadIdx.x == 0) {
+    double tot[NQ];
 #pragma unroll
-    for (int k = 1; k < 16; ++k) s += red[k][threadIdx.x];
-    out[threadIdx.x] = s;
+    for (int q = 0; q < NQ; ++q) {
+      double s = red[0][q];
+#pragma unroll
+      for (int k = 1; k < kRedThreads / 64; ++k) s += red[k][q];
+      tot[q] = s;
+    }
+    finish(tot);
   }
+}
+
+// After the right-hand-side kernel: border row of r0 = 0 - sum_{i in d} x_i
+// (the border unknowns of x are the multipliers, whose rows have right-hand
+// side 0); r^ = r0.  Totals: |b|^2, |r0|^2.
+__global__ __launch_bounds__(kRedThreads) void k_reduce_r(SimArgs a) {
+  const int64_t N = a.N;
+  reduce_with_borders<kNR>(
+      a, a.partR, 2,
+      [&](int d, double sx) __attribute__((always_inline)) {
+        const double r = -sx;
+        a.RV[N + d] = make_double2(r, 0.0);
+        a.rh[N + d] = r;
+        return Pack<double, kNR>{{0.0, r * r, 0.0}};
+      },
+      [&](const double *tot) __attribute__((always_inline)) {
+        for (int q = 0; q < kNR; ++q) a.sc->tot_r[q] = tot[q];
+      });
+}
+
+// After k_bicg_pv(it): the border rows of iteration k = it_base + it.
+// r = s - omega t, x += alpha_prev p + omega s, p' = r + beta (p - omega v)
+// (k = 0: r from k_reduce_r, p' = r), v' = sum_{i in d} p'_i; stores
+// (p', v') and (r, v').  Totals for k_bicg_st: (r^, v'), |r|^2.  If the
+// previous |s| converged (early 1): only x += alpha_prev p.
+__global__ __launch_bounds__(kRedThreads) void k_reduce_a(SimArgs a, int it) {
+  Scalars *sc = a.sc;
+  const int par = it & 1;
+  if (sc->done) return;
+  const int e = sc->early[par];
+  if (e >= 2) return;
+  const int64_t N = a.N;
+  const bool first = (sc->it_base + it) == 0;
+  const double alpha_p = sc->alpha[par ^ 1], omega = sc->omega[par], beta = sc->beta[par];
+  if (e == 1) {
+    for (int d = threadIdx.x; d < a.K; d += kRedThreads) a.x[N + d] = fma(alpha_p, a.PVo[N + d].x, a.x[N + d]);
+    return;
+  }
+  reduce_with_borders<kNA>(
+      a, a.partA, 1,
+      [&](int d, double sp) __attribute__((always_inline)) {
+        double r, p;
+        if (first) {
+          r = a.RV[N + d].x;
+          p = r;
+        } else {
+          const double2 st = a.ST[N + d], pv = a.PVo[N + d];
+          a.x[N + d] = fma(omega, st.x, fma(alpha_p, pv.x, a.x[N + d]));
+          r = fma(-omega, st.y, st.x);
+          p = fma(beta, fma(-omega, pv.y, pv.x), r);
+        }
+        a.PVn[N + d] = make_double2(p, sp);
+        a.RV[N + d] = make_double2(r, sp);
+        return Pack<double, kNA>{{a.rh[N + d] * sp, 0.0, r * r}};
+      },
+      [&](const double *tot) __attribute__((always_inline)) {
+        for (int q = 0; q < kNA; ++q) sc->tot_a[q] = tot[q];
+      });
+}
+
+// After k_bicg_st(it): s = r - alpha v, t = sum_{i in d} s_i on the border
+// rows; stores (s, t).  Totals for the next k_bicg_pv: (t,s), (t,t), (r^,s),
+// (r^,t), (s,s).
+__global__ __launch_bounds__(kRedThreads) void k_reduce_b(SimArgs a, int it) {
+  Scalars *sc = a.sc;
+  if (sc->done) return;
+  const int par = it & 1;
+  const int64_t N = a.N;
+  const double alpha = sc->alpha[par];
+  reduce_with_borders<kNB>(
+      a, a.partB, 5,
+      [&](int d, double ssum) __attribute__((always_inline)) {
+        const double2 rv = a.RV[N + d];
+        const double sb = fma(-alpha, rv.y, rv.x), tb = ssum, rhb = a.rh[N + d];
+        a.ST[N + d] = make_double2(sb, tb);
+        return Pack<double, kNB>{{tb * sb, tb * tb, rhb * sb, rhb * tb, sb * sb, 0.0}};
+      },
+      [&](const double *tot) __attribute__((always_inline)) {
+        for (int q = 0; q < kNB; ++q) sc->tot_b[q] = tot[q];
+      });
 }
 
 // ------------------------------------------------------------- predictor --
@@ -241,11 +341,11 @@ __global__ __launch_bounds__(1024) void k_reduce(const double *__restrict__ part
 // applies); the pointwise update is in FP64.
 template <int D, class FT>
 __global__ __launch_bounds__(kBS) void k_predict(SimArgs a) {
-  const BucketDesc bd = a.tab->b[bucket_index(a.bm, blockIdx.x)];
-  const BScal b = bscal(bd);
-  const int64_t t = ((int64_t)blockIdx.x - b.block0) * kBS + threadIdx.x;
-  if (t >= b.count) return;
-  const int64_t N = a.N, i = b.start + t;
+  const BlockDesc b = a.blk[blockIdx.x];
+  const int64_t t = b.first + (int64_t)threadIdx.x;
+  const bool live = (int)threadIdx.x < b.nodes;
+  if (!live) return;
+  const int64_t N = a.N, i = b.bstart + t;
   FT *__restrict__ vs = static_cast<FT *>(a.vs);
   if (b.type == B_DIR || b.type == B_NEU) {
 #pragma unroll
@@ -253,7 +353,7 @@ __global__ __launch_bounds__(kBS) void k_predict(SimArgs a) {
     return;
   }
   const FT *__restrict__ v = static_cast<const FT *>(a.v);
-  const uint32_t cnt32 = b.cnt, t32 = (uint32_t)t;
+  const uint32_t cnt32 = (uint32_t)b.count, t32 = (uint32_t)t;
   Buf vb[D];
 #pragma unroll
   for (int c = 0; c < D; ++c) vb[c] = plane(v, N, c);
@@ -319,20 +419,20 @@ __global__ __launch_bounds__(kBS) void k_predict(SimArgs a) {
 // The divergence is a field apply (FT); the pressure operator is FP64.
 template <int D, class FT>
 __global__ __launch_bounds__(kBS) void k_rhs(SimArgs a) {
-  const BucketDesc bd = a.tab->b[bucket_index(a.bm, blockIdx.x)];
-  const BScal b = bscal(bd);
-  const int64_t t = ((int64_t)blockIdx.x - b.block0) * kBS + threadIdx.x;
+  const BlockDesc b = a.blk[blockIdx.x];
+  const int64_t t = b.first + (int64_t)threadIdx.x;
+  const bool live = (int)threadIdx.x < b.nodes;
   double part[kNR] = {0.0, 0.0, 0.0};  // b.b, r.r, sum x
   const int64_t N = a.N;
-  const double lam = a.x[N];
+  const double lam = a.x[N + b.domain];        // this domain's border multiplier
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     Scalars *sc = a.sc;
     sc->done = 0; sc->fail = 0; sc->zero_sol = 0; sc->it_base = 0; sc->iters = 0;
     sc->early[0] = 0; sc->early[1] = 0;
   }
-  if (t < b.count) {
-    const int64_t i = b.start + t;
-    const uint32_t cnt32 = b.cnt, t32 = (uint32_t)t;
+  if (live) {
+    const int64_t i = b.bstart + t;
+    const uint32_t cnt32 = (uint32_t)b.count, t32 = (uint32_t)t;
     const bool wall = (b.type == B_DIR || b.type == B_NEU);
     const double *__restrict__ x = a.x;
     const Buf xb = plane(a.x, N + 1, 0);
@@ -404,41 +504,59 @@ __global__ __launch_bounds__(kBS) void k_bicg_pv(SimArgs a, int it) {
   // independent loads first (one wait), then the early exit
   const int done = sc->done, it_base = sc->it_base;
   const double bnorm2 = sc->bnorm2, alpha_prev = sc->alpha[par ^ 1], rho_prev = sc->rho[par ^ 1];
-  const BucketDesc bd = a.tab->b[bucket_index(a.bm, blockIdx.x)];
+  const BlockDesc b = a.blk[blockIdx.x];
   if (done) return;
   const int64_t N = a.N;
   const int k = it_base + it;
   const bool first = (k == 0);
   const double bn = sqrt(bnorm2);
-  double omega = 0.0, beta = 0.0, alpha_p = 0.0, rho_k = 0.0, rN, pN;
+  double omega = 0.0, beta = 0.0, alpha_p = 0.0, rho_k = 0.0, pN;
   int early = 0;
   const double2 *__restrict__ ST = a.ST;
   const double2 *__restrict__ PVo = a.PVo;
+  const int64_t NB = N + b.domain;              // this block's border row
   if (first) {
     double tot[kNR];
     grid_totals<kNR>(a, a.partR, sc->tot_r, tot);
-    rN = -tot[2];                               // border row of r0: 0 - sum x
-    rho_k = fma(rN, rN, tot[1]);                // (rh, r0) = |r0|^2
-    pN = rN;
+    double rN = 0.0;
+    if (a.sepred) {
+      rho_k = tot[1];                           // (rh, r0) = |r0|^2, border rows included
+      pN = a.RV[NB].x;                          // p0 = r0 on the border row
+    } else {
+      rN = -tot[2];                             // border row of r0: 0 - sum x
+      rho_k = fma(rN, rN, tot[1]);
+      pN = rN;
+    }
     if (tot[0] == 0.0) early = 3;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       sc->bnorm2 = tot[0];
-      a.RV[N] = make_double2(rN, 0.0);
-      a.rh[N] = rN;
-      a.PVn[N] = make_double2(pN, 0.0);
+      if (!a.sepred) {
+        a.RV[N] = make_double2(rN, 0.0);
+        a.rh[N] = rN;
+        a.PVn[N] = make_double2(pN, 0.0);
+      }
       sc->rho[par] = rho_k;
       sc->early[par] = early;
+      sc->omega[par] = 0.0;
+      sc->beta[par] = 0.0;
     }
     if (early) return;
   } else {
     double tot[kNB];
     grid_totals<kNB>(a, a.partB, sc->tot_b, tot);
-    const double sN = ST[N].x, rhN = a.rh[N];
-    const double2 pvN = PVo[N];
-    const double tN = tot[5];                   // border row of t = A s: sum s
-    const double ts = fma(tN, sN, tot[0]), tt = fma(tN, tN, tot[1]);
-    const double rhs_ = fma(rhN, sN, tot[2]), rht = fma(rhN, tN, tot[3]);
-    const double ss = fma(sN, sN, tot[4]);
+    double ts, tt, rhs_, rht, ss, sN = 0.0, tN = 0.0;
+    double2 pvN = make_double2(0.0, 0.0);
+    if (a.sepred) {                             // border rows already in the totals
+      ts = tot[0]; tt = tot[1]; rhs_ = tot[2]; rht = tot[3]; ss = tot[4];
+    } else {
+      sN = ST[N].x;
+      pvN = PVo[N];
+      const double rhN = a.rh[N];
+      tN = tot[5];                              // border row of t = A s: sum s
+      ts = fma(tN, sN, tot[0]); tt = fma(tN, tN, tot[1]);
+      rhs_ = fma(rhN, sN, tot[2]); rht = fma(rhN, tN, tot[3]);
+      ss = fma(sN, sN, tot[4]);
+    }
     alpha_p = alpha_prev;
     const double rho_p = rho_prev;
     if (sqrt(ss) <= a.tol * bn) early = 1;
@@ -449,35 +567,46 @@ __global__ __launch_bounds__(kBS) void k_bicg_pv(SimArgs a, int it) {
       if (rho_k == 0.0 || omega == 0.0) early = 2;
       else beta = (rho_k / rho_p) * (alpha_p / omega);
     }
-    rN = fma(-omega, tN, sN);
-    pN = fma(beta, fma(-omega, pvN.y, pvN.x), rN);
+    double rN;
+    if (a.sepred) {                             // this block's border row, as k_reduce_a will store it
+      const double2 stb = ST[NB], pvb = PVo[NB];
+      rN = fma(-omega, stb.y, stb.x);
+      pN = fma(beta, fma(-omega, pvb.y, pvb.x), rN);
+    } else {
+      rN = fma(-omega, tN, sN);
+      pN = fma(beta, fma(-omega, pvN.y, pvN.x), rN);
+    }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       sc->early[par] = early;
+      sc->omega[par] = omega;
+      sc->beta[par] = beta;
       if (early == 1) {
-        a.x[N] = fma(alpha_p, pvN.x, a.x[N]);
+        if (!a.sepred) a.x[N] = fma(alpha_p, pvN.x, a.x[N]);
         sc->relres = sqrt(ss) / bn;
       } else if (early == 0) {
-        a.x[N] = fma(omega, sN, fma(alpha_p, pvN.x, a.x[N]));
-        a.RV[N] = make_double2(rN, 0.0);
-        a.PVn[N] = make_double2(pN, 0.0);
+        if (!a.sepred) {
+          a.x[N] = fma(omega, sN, fma(alpha_p, pvN.x, a.x[N]));
+          a.RV[N] = make_double2(rN, 0.0);
+          a.PVn[N] = make_double2(pN, 0.0);
+        }
         sc->rho[par] = rho_k;
       }
     }
     if (early == 2) return;
   }
-  const BScal b = bscal(bd);
-  const int64_t t = ((int64_t)blockIdx.x - b.block0) * kBS + threadIdx.x;
+  const int64_t t = b.first + (int64_t)threadIdx.x;
+  const bool live = (int)threadIdx.x < b.nodes;
   if (early == 1) {                             // |s| converged: x += alpha p, nothing else
-    if (t < b.count) {
-      const int64_t i = b.start + t;
+    if (live) {
+      const int64_t i = b.bstart + t;
       a.x[i] = fma(alpha_p, PVo[i].x, a.x[i]);
     }
     return;
   }
   double part[kNA] = {0.0, 0.0, 0.0};           // (rh, v), sum p, |r|^2
-  if (t < b.count) {
-    const int64_t i = b.start + t;
-    const uint32_t cnt32 = b.cnt, t32 = (uint32_t)t;
+  if (live) {
+    const int64_t i = b.bstart + t;
+    const uint32_t cnt32 = (uint32_t)b.count, t32 = (uint32_t)t;
     const Buf RVb = plane(a.RV, N + 1, 0), STb = plane(ST, N + 1, 0), PVb = plane(PVo, N + 1, 0);
     const double2 *__restrict__ RV = a.RV;
     double ri, pi;
@@ -540,21 +669,33 @@ __global__ __launch_bounds__(kBS) void k_bicg_st(SimArgs a, int it) {
     }
     return;
   }
-  const BucketDesc bd = a.tab->b[bucket_index(a.bm, blockIdx.x)];
+  const BlockDesc b = a.blk[blockIdx.x];
   double tot[kNA];
   grid_totals<kNA>(a, a.partA, sc->tot_a, tot);
   const double bn = sqrt(bnorm2);
-  const double vN = tot[1];                     // border row of v = A p: sum p
-  const double rN = a.RV[N].x;
-  const double rv = fma(a.rh[N], vN, tot[0]);
-  const double rr = fma(rN, rN, tot[2]);
+  double rv, rr, vN = 0.0, rN = 0.0;
+  if (a.sepred) {                               // border rows already in the totals
+    rv = tot[0];
+    rr = tot[2];
+  } else {
+    vN = tot[1];                                // border row of v = A p: sum p
+    rN = a.RV[N].x;
+    rv = fma(a.rh[N], vN, tot[0]);
+    rr = fma(rN, rN, tot[2]);
+  }
   const double relres = sqrt(rr) / bn;
   int stop = 0;
   if (sqrt(rr) <= a.tol * bn) stop = 1;
   else if (k >= a.maxiter) stop = 2;
   else if (rv == 0.0) stop = 3;
   const double alpha = stop ? 0.0 : rho_k / rv;
-  const double sN = fma(-alpha, vN, rN);
+  double sN;
+  if (a.sepred) {                               // this block's border row, as k_reduce_b will store it
+    const double2 rvb = a.RV[N + b.domain];
+    sN = fma(-alpha, rvb.y, rvb.x);
+  } else {
+    sN = fma(-alpha, vN, rN);
+  }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     sc->relres = relres;
     if (stop) {
@@ -563,18 +704,20 @@ __global__ __launch_bounds__(kBS) void k_bicg_st(SimArgs a, int it) {
       if (stop >= 2) sc->fail = stop == 2 ? 2 : 1;
     } else {
       sc->alpha[par] = alpha;
-      a.PVn[N].y = vN;
-      a.RV[N].y = vN;
-      a.ST[N] = make_double2(sN, 0.0);
+      if (!a.sepred) {
+        a.PVn[N].y = vN;
+        a.RV[N].y = vN;
+        a.ST[N] = make_double2(sN, 0.0);
+      }
     }
   }
   if (stop) return;
-  const BScal b = bscal(bd);
-  const int64_t t = ((int64_t)blockIdx.x - b.block0) * kBS + threadIdx.x;
+  const int64_t t = b.first + (int64_t)threadIdx.x;
+  const bool live = (int)threadIdx.x < b.nodes;
   double part[kNB] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};   // (t,s), (t,t), (rh,s), (rh,t), (s,s), sum s
-  if (t < b.count) {
-    const int64_t i = b.start + t;
-    const uint32_t cnt32 = b.cnt, t32 = (uint32_t)t;
+  if (live) {
+    const int64_t i = b.bstart + t;
+    const uint32_t cnt32 = (uint32_t)b.count, t32 = (uint32_t)t;
     const Buf RVb = plane(a.RV, N + 1, 0);
     const double2 *__restrict__ RV = a.RV;
     double acc = 0.0;
@@ -624,14 +767,15 @@ __global__ void k_chunk_end(SimArgs a) {
 // pressure gradient reads FP64 p with FT weights, accumulated in FP64.
 template <int D, class FT>
 __global__ __launch_bounds__(kBS) void k_correct_heat(SimArgs a) {
-  const BucketDesc bd = a.tab->b[bucket_index(a.bm, blockIdx.x)];
-  const BScal b = bscal(bd);
-  const int64_t t = ((int64_t)blockIdx.x - b.block0) * kBS + threadIdx.x;
+  const BlockDesc b = a.blk[blockIdx.x];
+  const int64_t t = b.first + (int64_t)threadIdx.x;
+  const bool live = (int)threadIdx.x < b.nodes;
   const int64_t N = a.N;
   const bool zero = a.sc->zero_sol != 0;
-  if (zero && blockIdx.x == 0 && threadIdx.x == 0) a.x[N] = 0.0;
-  if (t >= b.count) return;
-  const int64_t i = b.start + t;
+  if (zero && blockIdx.x == 0)
+    for (int d = threadIdx.x; d < a.K; d += blockDim.x) a.x[N + d] = 0.0;
+  if (!live) return;
+  const int64_t i = b.bstart + t;
   const FT *__restrict__ T = static_cast<const FT *>(a.T);
   FT *__restrict__ vout = static_cast<FT *>(a.vout);
   FT *__restrict__ Tnp = static_cast<FT *>(a.Tn);
@@ -643,7 +787,7 @@ __global__ __launch_bounds__(kBS) void k_correct_heat(SimArgs a) {
     if (zero) a.x[i] = 0.0;
     return;
   }
-  const uint32_t cnt32 = b.cnt, t32 = (uint32_t)t;
+  const uint32_t cnt32 = (uint32_t)b.count, t32 = (uint32_t)t;
   const Buf xb = plane(a.x, N + 1, 0), Tb = plane(T, N, 0);
   const FT *__restrict__ vs = static_cast<const FT *>(a.vs);
   const double dt = a.dt;
@@ -707,12 +851,12 @@ __global__ __launch_bounds__(kBS) void k_correct_heat(SimArgs a) {
 // new interior values (wall stencils hold the wall node and interior nodes).
 template <int D, class FT>
 __global__ __launch_bounds__(kBS) void k_neumann(SimArgs a) {
-  const BucketDesc bd = a.tab->b[bucket_index(a.bm, blockIdx.x)];
-  const BScal b = bscal(bd);
-  const int64_t t = ((int64_t)blockIdx.x - b.block0) * kBS + threadIdx.x;
-  if (t >= b.count || b.type != B_NEU) return;
-  const int64_t N = a.N, i = b.start + t;
-  const uint32_t cnt32 = b.cnt, t32 = (uint32_t)t;
+  const BlockDesc b = a.blk[blockIdx.x];
+  const int64_t t = b.first + (int64_t)threadIdx.x;
+  const bool live = (int)threadIdx.x < b.nodes;
+  if (!live || b.type != B_NEU) return;
+  const int64_t N = a.N, i = b.bstart + t;
+  const uint32_t cnt32 = (uint32_t)b.count, t32 = (uint32_t)t;
   FT *Tn = static_cast<FT *>(a.Tn);
   const Buf Tnb = plane(Tn, N, 0);
   Scalars *sc = a.sc;

@@ -149,6 +149,73 @@ def test_separate_reduction_graph_replay_matches_direct_launches():
     assert sims[0].stats()["krylov_iters_total"] == sims[1].stats()["krylov_iters_total"]
 
 
+def _three_domains():
+    # (an obstacle set much coarser than h = 0.025 is unstable under the explicit scheme, in the oracle too)
+    sets = [ng.cavity2d(h=0.0625, seed=31), ng.cavity2d(h=0.05, seed=32),
+            ng.obstacles2d(h=0.025, n_obst=2, rmin=0.08, rmax=0.12, band=0.08, seed=35)]
+    x = np.concatenate([q.x for q in sets], axis=1)
+    kind = np.concatenate([q.kind for q in sets])
+    nrm = np.concatenate([q.normal for q in sets], axis=1)
+    tbc = np.concatenate([q.tbc for q in sets])
+    off = np.cumsum([0] + [q.n for q in sets]).astype(np.int64)
+    T0 = np.where(kind == 1, tbc, 0.5)
+    T0 = np.where(kind == 0, 0.5 + 0.2 * np.sin(4 * x[0]) * np.cos(3 * x[1]), T0)
+    return sets, x, kind, nrm, off, T0
+
+
+@pytest.mark.parametrize("field_dtype", [0, 2])
+def test_multi_domain_steps_match_oracle(field_dtype):
+    # three independent domains stepped together: one border row per domain
+    hsm = _hsm()
+    sets, x, kind, nrm, off, T0 = _three_domains()
+    hs = [q.h for q in sets]
+    dt = 0.1 * min(hs) ** 2 / 2
+    prm = dict(Ra=1e4, Pr=0.71, dt=dt, T_ref=0.5)
+    dev = torch.device("cuda")
+    st = hsm.build_stencils(torch.tensor(x, device=dev), torch.tensor(kind, device=dev), torch.tensor(nrm, device=dev),
+                            hs, 2, domain_offsets=off)
+    v = np.zeros((2, len(kind)))
+    sim = hsm.Sim(st, torch.tensor(v, device=dev), torch.tensor(T0, device=dev), krylov_tol=1e-12,
+                  field_dtype=field_dtype, **prm)
+    sim.step(50)
+    stats = sim.stats()
+    assert stats["status"] == 0 and stats["steps"] == 50
+    vg, Tg, pg = [a.cpu().numpy() for a in sim.read()]
+    csr = O.to_csr(O.build(x, kind, nrm, hs, 2, dom_off=off))
+    vo, To, po = v.copy(), T0.copy(), np.zeros(len(kind) + len(sets))
+    its = O.Sim(csr, kind, dom_off=off).step(vo, To, po, 50, tol=1e-12, **prm)
+    tol = FIELD_TOL if field_dtype == 0 else F32_FIELD_TOL
+    ev, eT = _rel(vg, vo), _rel(Tg, To)
+    ep = max(_rel(pg[a:b], po[a:b]) for a, b in zip(off[:-1], off[1:]))
+    print(f"3 domains, field dtype {field_dtype}: rel L2 err v {ev:.2e} T {eT:.2e} p (worst domain) {ep:.2e}; "
+          f"krylov iters gpu {stats['krylov_iters_total']} oracle {int(its.sum())}")
+    assert ev <= tol and eT <= tol and ep <= tol
+    # every domain's pressure has zero mean
+    for a, b in zip(off[:-1], off[1:]):
+        assert abs(pg[a:b].sum()) <= 1e-9 * np.abs(pg[a:b]).sum()
+
+
+def test_multi_domain_graph_replay_matches_direct_launches():
+    hsm = _hsm()
+    sets, x, kind, nrm, off, T0 = _three_domains()
+    hs = [q.h for q in sets]
+    dt = 0.1 * min(hs) ** 2 / 2
+    dev = torch.device("cuda")
+    st = hsm.build_stencils(torch.tensor(x, device=dev), torch.tensor(kind, device=dev), torch.tensor(nrm, device=dev),
+                            hs, 2, domain_offsets=off)
+    v = np.zeros((2, len(kind)))
+    sims = [hsm.Sim(st, torch.tensor(v, device=dev), torch.tensor(T0, device=dev), Ra=1e5, Pr=0.71, dt=dt,
+                    T_ref=0.5, launch_mode=lm, krylov_chunk=8) for lm in (0, 1)]
+    for rep in range(3):
+        outs = []
+        for sim in sims:
+            sim.step(3)
+            outs.append([a.cpu().numpy() for a in sim.read()])
+            torch.cuda.synchronize()
+        for a, b in zip(*outs):
+            assert np.array_equal(a, b), f"replay {rep} differs"
+
+
 def test_graph_replay_matches_direct_launches():
     # every replay of the captured graphs against the same kernels launched
     # directly, and against graph replay with timing events around each graph
