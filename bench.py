@@ -313,14 +313,19 @@ def main():
         rec["applies"] += 3 * st.node_count(ops)
         rec["solves"] += s.n
         rec["info"] = info
-        if multi:                 # stepping is one domain per simulation for now
-            return st
         # profile=1: start/stop events around every graph launch on the stepper's stream
         sim = hsm.Sim(st, v0, T0d, Ra=Ra, Pr=0.71, dt=dt, T_ref=0.5, krylov_tol=args.tol, krylov_maxiter=200000,
                       krylov_chunk=KRYLOV_CHUNK, profile=1, field_dtype=field_dtype)
-        sim.step(args.time_steps)
+        try:
+            sim.step(args.time_steps)
+        except hsm.HsmError:
+            pass                      # the latched status is read below
         stats = sim.stats()
-        assert stats["status"] == 0, stats
+        rec["status"] = stats["status"]
+        if stats["status"] != 0:
+            if field_dtype == hsm.F64:
+                raise RuntimeError(f"time stepping failed: {stats}")
+            return st
         rec["applies"] += stats["node_applies"]
         rec["krylov_iters"] += stats["krylov_iters_total"]
         for k, (ms, n) in sim.phase_times().items():
@@ -394,7 +399,7 @@ def main():
         log(f"{name}: {el / args.steps * 1e3:.1f} ms/step, {rec['applies'] / el:.3e} node-applies/s, "
             f"krylov iters/step {rec['krylov_iters'] / args.steps:.0f}")
 
-    stepping = not multi
+    stepping = True
     fp32 = None
     if not args.skip_fp32_form and stepping:
         rec = fresh()
@@ -404,12 +409,17 @@ def main():
         el = time.perf_counter() - t0
         ref = results["hybrid"]["final"]
         err = {}
+        if rec.get("status", 0) != 0:
+            rec["final"] = [np.full_like(a, np.nan) for a in ref]
         for nm, a, b in zip(("v", "T", "p"), rec["final"], ref):
             if nm == "p":
                 a, b = a - a.mean(), b - b.mean()
             err[nm] = dict(rel_l2=float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)),
                            max_rel=float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)))
-        fp32 = dict(ms_per_step=el * 1e3, value=rec["applies"] / el,
+        fp32 = dict(status=("ok" if rec.get("status", 0) == 0 else
+                            f"hsm status {rec['status']}: FP32 velocity storage went non-finite (rounding of v* "
+                            f"divided by dt; see the design notes)"),
+                    ms_per_step=el * 1e3, value=rec["applies"] / el,
                     phase_mean_ms={k: (tot / n if n else float("nan")) for k, (tot, n) in rec["ptimes"].items()},
                     error_vs_fp64_gpu_after_time_steps=err, time_steps=args.time_steps)
         log(f"fp32 form: {el * 1e3:.1f} ms/step; error vs FP64: {err}")
@@ -440,7 +450,9 @@ def main():
                         copy_kernel_gbs=copy_gbs)
     if multi:
         mdesc = f"m per domain ({int((s.m == 2).sum())} domains m=2 n=12, {int((s.m == 4).sum())} m=4 n=30)"
-        per_step = "stencil build + 3-field apply (time stepping of many domains in one launch: not built)"
+        per_step = (f"stencil build + 3-field apply + {args.time_steps} Boussinesq steps of all domains together "
+                    f"(Ra={Ra:g}, Pr=0.71, dt=0.1 min(h)^2/2, one pressure border per domain, rel. residual "
+                    f"{args.tol})")
     else:
         n_s = 2 * int(round(np.prod([m + k for k in range(1, D + 1)]) / np.prod(range(1, D + 1))))
         mdesc = f"m={m} (n={n_s})"

@@ -57,6 +57,7 @@ struct hsm_sim {
   int32_t K = 1;              // domains (border rows)
   int64_t nblk = 0;           // blocks of every node launch
   DBuf blk, dom_blk_off, dom_blk;   // block descriptors; per-domain block lists
+  DBuf dom;                          // per-domain Krylov state [K]
   bool f32 = false;           // FP32 field form (HSM_F32_COMP)
   bool sepred = false;        // grid totals by a separate one-block kernel (large grids)
 
@@ -88,6 +89,7 @@ SimArgs make_args(hsm_sim *m, int par, int kpar) {
   a.K = m->K;
   a.dom_blk_off = m->dom_blk_off.as<int32_t>();
   a.dom_blk = m->dom_blk.as<int32_t>();
+  a.dom = m->dom.as<DomState>();
   a.N = m->N;
   a.dt = m->prm.dt; a.Ra = m->prm.Ra; a.Pr = m->prm.Pr; a.T_ref = m->prm.T_ref; a.tol = m->prm.krylov_tol;
   a.maxiter = m->prm.krylov_maxiter;
@@ -422,6 +424,8 @@ hsm_status hsm_sim_create(const hsm_stencils *st, const hsm_sim_params *prm, con
     return HSM_E_INVALID;
   }
   m->sepred = m->K > 1 || prm->reduce_mode == 2 || (prm->reduce_mode == 0 && m->nblk > kSepReduceBlocks);
+  if ((rc = m->dom.alloc(sizeof(DomState) * m->K))) return rc;
+  HSM_HIP(hipMemsetAsync(m->dom.p, 0, sizeof(DomState) * m->K, us));
   if ((rc = m->partR.alloc(sizeof(double) * kNR * (m->nblk + 1))) ||
       (rc = m->partA.alloc(sizeof(double) * kNA * (m->nblk + 1))) ||
       (rc = m->partB.alloc(sizeof(double) * kNB * (m->nblk + 1))))

@@ -33,10 +33,19 @@ struct HostFlags {
 struct Scalars {
   double rho[2], alpha[2], omega[2], beta[2];
   double bnorm2, relres;
-  double tot_r[kNR], tot_a[kNA], tot_b[kNB];   // grid totals, border rows included (reduction kernels)
   int32_t done, fail, zero_sol, nonfinite;
   int32_t it_base, iters, early[2];   // early: 1 = |s| converged, 2 = breakdown, 3 = zero right-hand side
   HostFlags mirror;
+};
+
+// Per-domain Krylov state (the reduction-kernel path): every domain runs its
+// own BiCGSTAB, with its own scalars and stopping test, in the same launches;
+// a block of a finished domain returns at once.  Slot conventions as above.
+struct DomState {
+  double rho[2], alpha[2], omega[2], beta[2];
+  double bnorm2, relres;
+  int32_t early[2];    // decided for the iteration of that parity: 1 = |s| converged, 2 = breakdown
+  int32_t done, fail, iters, zero_sol;
 };
 
 // One block of a stepper launch: up to kBS consecutive nodes of one width
@@ -78,6 +87,7 @@ struct SimArgs {
   double2 *ST, *PVo, *PVn, *RV;   // pairs (s,t), (p,v) previous/this iteration, (r,v)
   double *partR, *partA, *partB;   // block partial sums [nblk][kN*]
   Scalars *sc;
+  DomState *dom;                   // [K] (reduction-kernel path)
 };
 
 template <class F>
@@ -199,102 +209,111 @@ __device__ __forceinline__ void reduce_prev(const double *__restrict__ part, int
   }
 }
 
-// One-domain small grids: each block reduces the partials in its prologue.
-// Otherwise the reduction kernels below have written the totals.
+// Per-domain sums for the reduction kernels (one block of kRedThreads):
+// thread d (d += kRedThreads) sums every column of domain d's blocks in
+// order.  The batch flags (every domain done, any failure, worst relative
+// residual, most iterations) are order-free reductions in shared memory.
 template <int NQ>
-__device__ __forceinline__ void grid_totals(const SimArgs &a, const double *part, const double *sep,
+__device__ __forceinline__ void domain_sums(const SimArgs &a, const double *__restrict__ part, int d,
                                             double (&tot)[NQ]) {
-  if (a.sepred) {
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) tot[q] = sep[q];
-  } else {
-    reduce_prev<NQ>(part, gridDim.x, tot);
+  for (int q = 0; q < NQ; ++q) tot[q] = 0.0;
+  for (int j = a.dom_blk_off[d]; j < a.dom_blk_off[d + 1]; ++j) {
+    const int64_t b = a.dom_blk[j];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) tot[q] += part[b * NQ + q];
   }
 }
-
-// The reduction kernels (one block of kRedThreads): totals of every block's
-// partials, each thread summing a strided set of rows in order, plus the
-// border rows: thread d (d += kRedThreads) sums column qd over domain d's
-// blocks in order (the domain's share of a sum over nodes), and border(d, sum)
-// updates that border row and returns what it adds to each total.  Then wave
-// sums and the waves in order: deterministic.  Thread 0 gets the totals.
-template <int NQ, class FB, class FF>
-__device__ __forceinline__ void reduce_with_borders(const SimArgs &a, const double *__restrict__ part, int qd,
-                                                    FB &&border, FF &&finish) {
-  __shared__ double red[kRedThreads / 64][NQ];
-  double acc[NQ];
-#pragma unroll
-  for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
-  for (int64_t b = threadIdx.x; b < a.nblk; b += kRedThreads)
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) acc[q] += part[b * NQ + q];
-  for (int d = threadIdx.x; d < a.K; d += kRedThreads) {
-    double sd = 0.0;
-    for (int j = a.dom_blk_off[d]; j < a.dom_blk_off[d + 1]; ++j) sd += part[(int64_t)a.dom_blk[j] * NQ + qd];
-    const Pack<double, NQ> inc = border(d, sd);
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) acc[q] += inc.v[q];
-  }
-#pragma unroll
-  for (int q = 0; q < NQ; ++q) acc[q] = wave_sum(acc[q]);
-  if ((threadIdx.x & 63) == 0)
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) red[threadIdx.x >> 6][q] = acc[q];
+struct BatchFlags {
+  int32_t ndone, fail, iters;
+  unsigned long long relres_bits;   // non-negative doubles order like their bit patterns
+};
+__device__ __forceinline__ void batch_begin(BatchFlags &f) {
+  if (threadIdx.x == 0) { f.ndone = 0; f.fail = 0; f.iters = 0; f.relres_bits = 0ull; }
+  __syncthreads();
+}
+__device__ __forceinline__ void batch_add(BatchFlags &f, const DomState &ds) {
+  if (ds.done) atomicAdd(&f.ndone, 1);
+  if (ds.fail) atomicMax(&f.fail, ds.fail);
+  atomicMax(&f.iters, ds.iters);
+  atomicMax(&f.relres_bits, (unsigned long long)__double_as_longlong(ds.relres));
+}
+// thread 0 publishes the batch state once every domain is done
+__device__ __forceinline__ void batch_end(const SimArgs &a, BatchFlags &f) {
   __syncthreads();
   if (threadIdx.x == 0) {
-    double tot[NQ];
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      double s = red[0][q];
-#pragma unroll
-      for (int k = 1; k < kRedThreads / 64; ++k) s += red[k][q];
-      tot[q] = s;
+    Scalars *sc = a.sc;
+    sc->relres = __longlong_as_double((long long)f.relres_bits);
+    if (f.ndone == a.K) {
+      sc->done = 1;
+      sc->iters = f.iters;
+      sc->fail = f.fail;
     }
-    finish(tot);
   }
 }
 
-// After the right-hand-side kernel: border row of r0 = 0 - sum_{i in d} x_i
-// (the border unknowns of x are the multipliers, whose rows have right-hand
-// side 0); r^ = r0.  Totals: |b|^2, |r0|^2.
+// After the right-hand-side kernel, per domain: |b|^2; the border row of r0
+// (0 - sum x over the domain: the border unknowns are the multipliers, whose
+// rows have right-hand side 0); r^ = r0; rho_0 = |r0|^2.  A domain with a zero
+// right-hand side is done at once with p = 0.
 __global__ __launch_bounds__(kRedThreads) void k_reduce_r(SimArgs a) {
+  __shared__ BatchFlags f;
+  batch_begin(f);
   const int64_t N = a.N;
-  reduce_with_borders<kNR>(
-      a, a.partR, 2,
-      [&](int d, double sx) __attribute__((always_inline)) {
-        const double r = -sx;
-        a.RV[N + d] = make_double2(r, 0.0);
-        a.rh[N + d] = r;
-        return Pack<double, kNR>{{0.0, r * r, 0.0}};
-      },
-      [&](const double *tot) __attribute__((always_inline)) {
-        for (int q = 0; q < kNR; ++q) a.sc->tot_r[q] = tot[q];
-      });
+  for (int d = threadIdx.x; d < a.K; d += kRedThreads) {
+    double tot[kNR];
+    domain_sums<kNR>(a, a.partR, d, tot);
+    DomState &ds = a.dom[d];
+    const double r = -tot[2];
+    a.RV[N + d] = make_double2(r, 0.0);
+    a.rh[N + d] = r;
+    const double rr = fma(r, r, tot[1]);
+    ds.bnorm2 = tot[0];
+    ds.rho[0] = rr;
+    ds.early[0] = 0;
+    ds.fail = 0;
+    ds.iters = 0;
+    ds.zero_sol = tot[0] == 0.0;
+    ds.done = ds.zero_sol;
+    ds.relres = ds.zero_sol ? 0.0 : sqrt(rr / tot[0]);
+    batch_add(f, ds);
+  }
+  batch_end(a, f);
 }
 
-// After k_bicg_pv(it): the border rows of iteration k = it_base + it.
-// r = s - omega t, x += alpha_prev p + omega s, p' = r + beta (p - omega v)
-// (k = 0: r from k_reduce_r, p' = r), v' = sum_{i in d} p'_i; stores
-// (p', v') and (r, v').  Totals for k_bicg_st: (r^, v'), |r|^2.  If the
-// previous |s| converged (early 1): only x += alpha_prev p.
+// After k_bicg_pv(it), per unfinished domain: the border rows of iteration
+// k = it_base + it (r = s - omega t, x += alpha_prev p + omega s,
+// p' = r + beta (p - omega v); k = 0: r from k_reduce_r, p' = r), then
+// v' = sum_{i in d} p'_i; stores (p', v') and (r, v').  Then the stopping
+// test on |r| and alpha = rho / (r^, v').  A domain whose |s| converged
+// (early 1) only takes x += alpha_prev p on its border and is done; a
+// breakdown (early 2) ends it as failed.
 __global__ __launch_bounds__(kRedThreads) void k_reduce_a(SimArgs a, int it) {
   Scalars *sc = a.sc;
-  const int par = it & 1;
   if (sc->done) return;
-  const int e = sc->early[par];
-  if (e >= 2) return;
+  __shared__ BatchFlags f;
+  batch_begin(f);
+  const int par = it & 1;
   const int64_t N = a.N;
-  const bool first = (sc->it_base + it) == 0;
-  const double alpha_p = sc->alpha[par ^ 1], omega = sc->omega[par], beta = sc->beta[par];
-  if (e == 1) {
-    for (int d = threadIdx.x; d < a.K; d += kRedThreads) a.x[N + d] = fma(alpha_p, a.PVo[N + d].x, a.x[N + d]);
-    return;
-  }
-  reduce_with_borders<kNA>(
-      a, a.partA, 1,
-      [&](int d, double sp) __attribute__((always_inline)) {
+  const int k = sc->it_base + it;
+  for (int d = threadIdx.x; d < a.K; d += kRedThreads) {
+    DomState &ds = a.dom[d];
+    if (!ds.done) {
+      const int e = (k == 0) ? 0 : ds.early[par];
+      const double alpha_p = ds.alpha[par ^ 1], omega = ds.omega[par], beta = ds.beta[par];
+      if (e == 1) {
+        a.x[N + d] = fma(alpha_p, a.PVo[N + d].x, a.x[N + d]);
+        ds.done = 1;
+        ds.iters = k;
+      } else if (e == 2) {
+        ds.done = 1;
+        ds.fail = 1;
+        ds.iters = k;
+      } else {
+        double tot[kNA];
+        domain_sums<kNA>(a, a.partA, d, tot);
         double r, p;
-        if (first) {
+        if (k == 0) {
           r = a.RV[N + d].x;
           p = r;
         } else {
@@ -303,35 +322,61 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_a(SimArgs a, int it) {
           r = fma(-omega, st.y, st.x);
           p = fma(beta, fma(-omega, pv.y, pv.x), r);
         }
-        a.PVn[N + d] = make_double2(p, sp);
-        a.RV[N + d] = make_double2(r, sp);
-        return Pack<double, kNA>{{a.rh[N + d] * sp, 0.0, r * r}};
-      },
-      [&](const double *tot) __attribute__((always_inline)) {
-        for (int q = 0; q < kNA; ++q) sc->tot_a[q] = tot[q];
-      });
+        const double vb = tot[1];               // border row of v = A p': sum of p' over the domain
+        a.PVn[N + d] = make_double2(p, vb);
+        a.RV[N + d] = make_double2(r, vb);
+        const double rv = fma(a.rh[N + d], vb, tot[0]);
+        const double rr = fma(r, r, tot[2]);
+        const double bn = sqrt(ds.bnorm2);
+        ds.relres = sqrt(rr) / bn;
+        if (sqrt(rr) <= a.tol * bn) { ds.done = 1; ds.iters = k; }
+        else if (k >= a.maxiter) { ds.done = 1; ds.fail = 2; ds.iters = k; }
+        else if (rv == 0.0) { ds.done = 1; ds.fail = 1; ds.iters = k; }
+        else ds.alpha[par] = ds.rho[par] / rv;
+      }
+    }
+    batch_add(f, ds);
+  }
+  batch_end(a, f);
 }
 
-// After k_bicg_st(it): s = r - alpha v, t = sum_{i in d} s_i on the border
-// rows; stores (s, t).  Totals for the next k_bicg_pv: (t,s), (t,t), (r^,s),
-// (r^,t), (s,s).
+// After k_bicg_st(it), per unfinished domain: s = r - alpha v and
+// t = sum_{i in d} s_i on the border row (stored as (s, t)); then, for the
+// next iteration: |s| converged (early 1), breakdown (early 2), or
+// omega = (t,s)/(t,t), rho' = (r^,s) - omega (r^,t), beta = (rho'/rho)(alpha/omega).
 __global__ __launch_bounds__(kRedThreads) void k_reduce_b(SimArgs a, int it) {
   Scalars *sc = a.sc;
   if (sc->done) return;
-  const int par = it & 1;
+  const int par = it & 1, nx = par ^ 1;
   const int64_t N = a.N;
-  const double alpha = sc->alpha[par];
-  reduce_with_borders<kNB>(
-      a, a.partB, 5,
-      [&](int d, double ssum) __attribute__((always_inline)) {
-        const double2 rv = a.RV[N + d];
-        const double sb = fma(-alpha, rv.y, rv.x), tb = ssum, rhb = a.rh[N + d];
-        a.ST[N + d] = make_double2(sb, tb);
-        return Pack<double, kNB>{{tb * sb, tb * tb, rhb * sb, rhb * tb, sb * sb, 0.0}};
-      },
-      [&](const double *tot) __attribute__((always_inline)) {
-        for (int q = 0; q < kNB; ++q) sc->tot_b[q] = tot[q];
-      });
+  for (int d = threadIdx.x; d < a.K; d += kRedThreads) {
+    DomState &ds = a.dom[d];
+    if (ds.done) continue;
+    double tot[kNB];
+    domain_sums<kNB>(a, a.partB, d, tot);
+    const double alpha = ds.alpha[par];
+    const double2 rv = a.RV[N + d];
+    const double sb = fma(-alpha, rv.y, rv.x), tb = tot[5], rhb = a.rh[N + d];
+    a.ST[N + d] = make_double2(sb, tb);
+    const double ts = fma(tb, sb, tot[0]), tt = fma(tb, tb, tot[1]);
+    const double rhs_ = fma(rhb, sb, tot[2]), rht = fma(rhb, tb, tot[3]);
+    const double ss = fma(sb, sb, tot[4]);
+    const double bn = sqrt(ds.bnorm2);
+    int e = 0;
+    double omega = 0.0, beta = 0.0, rho_n = 0.0;
+    if (sqrt(ss) <= a.tol * bn) { e = 1; ds.relres = sqrt(ss) / bn; }
+    else if (tt == 0.0) e = 2;
+    else {
+      omega = ts / tt;
+      rho_n = fma(-omega, rht, rhs_);
+      if (rho_n == 0.0 || omega == 0.0) e = 2;
+      else beta = (rho_n / ds.rho[par]) * (alpha / omega);
+    }
+    ds.early[nx] = e;
+    ds.omega[nx] = omega;
+    ds.beta[nx] = beta;
+    ds.rho[nx] = rho_n;
+  }
 }
 
 // ------------------------------------------------------------- predictor --
@@ -509,56 +554,57 @@ __global__ __launch_bounds__(kBS) void k_bicg_pv(SimArgs a, int it) {
   const int64_t N = a.N;
   const int k = it_base + it;
   const bool first = (k == 0);
-  const double bn = sqrt(bnorm2);
-  double omega = 0.0, beta = 0.0, alpha_p = 0.0, rho_k = 0.0, pN;
+  double omega = 0.0, beta = 0.0, alpha_p = 0.0, pN;
   int early = 0;
   const double2 *__restrict__ ST = a.ST;
   const double2 *__restrict__ PVo = a.PVo;
-  const int64_t NB = N + b.domain;              // this block's border row
-  if (first) {
-    double tot[kNR];
-    grid_totals<kNR>(a, a.partR, sc->tot_r, tot);
-    double rN = 0.0;
-    if (a.sepred) {
-      rho_k = tot[1];                           // (rh, r0) = |r0|^2, border rows included
+  if (a.sepred) {
+    // this block's domain: its scalars were decided by k_reduce_b (or k_reduce_r)
+    const DomState &ds = a.dom[b.domain];
+    if (ds.done) return;
+    const int64_t NB = N + b.domain;
+    if (first) {
       pN = a.RV[NB].x;                          // p0 = r0 on the border row
     } else {
-      rN = -tot[2];                             // border row of r0: 0 - sum x
-      rho_k = fma(rN, rN, tot[1]);
-      pN = rN;
+      early = ds.early[par];
+      if (early == 2) return;
+      omega = ds.omega[par];
+      beta = ds.beta[par];
+      alpha_p = ds.alpha[par ^ 1];
+      const double2 stb = ST[NB], pvb = PVo[NB];  // the border row, as k_reduce_a will store it
+      const double rN = fma(-omega, stb.y, stb.x);
+      pN = fma(beta, fma(-omega, pvb.y, pvb.x), rN);
     }
+  } else if (first) {
+    // one domain, small grid: every block reduces the partials and takes the same decisions
+    double tot[kNR];
+    reduce_prev<kNR>(a.partR, gridDim.x, tot);
+    const double rN = -tot[2];                  // border row of r0: 0 - sum x
+    const double rho_k = fma(rN, rN, tot[1]);   // (rh, r0) = |r0|^2
+    pN = rN;
     if (tot[0] == 0.0) early = 3;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       sc->bnorm2 = tot[0];
-      if (!a.sepred) {
-        a.RV[N] = make_double2(rN, 0.0);
-        a.rh[N] = rN;
-        a.PVn[N] = make_double2(pN, 0.0);
-      }
+      a.RV[N] = make_double2(rN, 0.0);
+      a.rh[N] = rN;
+      a.PVn[N] = make_double2(pN, 0.0);
       sc->rho[par] = rho_k;
       sc->early[par] = early;
-      sc->omega[par] = 0.0;
-      sc->beta[par] = 0.0;
     }
     if (early) return;
   } else {
     double tot[kNB];
-    grid_totals<kNB>(a, a.partB, sc->tot_b, tot);
-    double ts, tt, rhs_, rht, ss, sN = 0.0, tN = 0.0;
-    double2 pvN = make_double2(0.0, 0.0);
-    if (a.sepred) {                             // border rows already in the totals
-      ts = tot[0]; tt = tot[1]; rhs_ = tot[2]; rht = tot[3]; ss = tot[4];
-    } else {
-      sN = ST[N].x;
-      pvN = PVo[N];
-      const double rhN = a.rh[N];
-      tN = tot[5];                              // border row of t = A s: sum s
-      ts = fma(tN, sN, tot[0]); tt = fma(tN, tN, tot[1]);
-      rhs_ = fma(rhN, sN, tot[2]); rht = fma(rhN, tN, tot[3]);
-      ss = fma(sN, sN, tot[4]);
-    }
+    reduce_prev<kNB>(a.partB, gridDim.x, tot);
+    const double bn = sqrt(bnorm2);
+    const double sN = ST[N].x, rhN = a.rh[N];
+    const double2 pvN = PVo[N];
+    const double tN = tot[5];                   // border row of t = A s: sum s
+    const double ts = fma(tN, sN, tot[0]), tt = fma(tN, tN, tot[1]);
+    const double rhs_ = fma(rhN, sN, tot[2]), rht = fma(rhN, tN, tot[3]);
+    const double ss = fma(sN, sN, tot[4]);
     alpha_p = alpha_prev;
     const double rho_p = rho_prev;
+    double rho_k = 0.0;
     if (sqrt(ss) <= a.tol * bn) early = 1;
     else if (tt == 0.0) early = 2;
     else {
@@ -567,28 +613,17 @@ __global__ __launch_bounds__(kBS) void k_bicg_pv(SimArgs a, int it) {
       if (rho_k == 0.0 || omega == 0.0) early = 2;
       else beta = (rho_k / rho_p) * (alpha_p / omega);
     }
-    double rN;
-    if (a.sepred) {                             // this block's border row, as k_reduce_a will store it
-      const double2 stb = ST[NB], pvb = PVo[NB];
-      rN = fma(-omega, stb.y, stb.x);
-      pN = fma(beta, fma(-omega, pvb.y, pvb.x), rN);
-    } else {
-      rN = fma(-omega, tN, sN);
-      pN = fma(beta, fma(-omega, pvN.y, pvN.x), rN);
-    }
+    const double rN = fma(-omega, tN, sN);
+    pN = fma(beta, fma(-omega, pvN.y, pvN.x), rN);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       sc->early[par] = early;
-      sc->omega[par] = omega;
-      sc->beta[par] = beta;
       if (early == 1) {
-        if (!a.sepred) a.x[N] = fma(alpha_p, pvN.x, a.x[N]);
+        a.x[N] = fma(alpha_p, pvN.x, a.x[N]);
         sc->relres = sqrt(ss) / bn;
       } else if (early == 0) {
-        if (!a.sepred) {
-          a.x[N] = fma(omega, sN, fma(alpha_p, pvN.x, a.x[N]));
-          a.RV[N] = make_double2(rN, 0.0);
-          a.PVn[N] = make_double2(pN, 0.0);
-        }
+        a.x[N] = fma(omega, sN, fma(alpha_p, pvN.x, a.x[N]));
+        a.RV[N] = make_double2(rN, 0.0);
+        a.PVn[N] = make_double2(pN, 0.0);
         sc->rho[par] = rho_k;
       }
     }
@@ -657,61 +692,57 @@ __global__ __launch_bounds__(kBS) void k_bicg_st(SimArgs a, int it) {
   const int par = it & 1;
   const int done = sc->done, it_base = sc->it_base, early = sc->early[par];
   const double bnorm2 = sc->bnorm2, rho_k = sc->rho[par];
+  const BlockDesc b = a.blk[blockIdx.x];
   if (done) return;
   const int64_t N = a.N;
   const int k = it_base + it;
-  if (early) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-      sc->done = 1;
-      sc->iters = (early == 3) ? 0 : k;
-      if (early == 2) sc->fail = 1;
-      if (early == 3) { sc->zero_sol = 1; sc->relres = 0.0; }
-    }
-    return;
-  }
-  const BlockDesc b = a.blk[blockIdx.x];
-  double tot[kNA];
-  grid_totals<kNA>(a, a.partA, sc->tot_a, tot);
-  const double bn = sqrt(bnorm2);
-  double rv, rr, vN = 0.0, rN = 0.0;
-  if (a.sepred) {                               // border rows already in the totals
-    rv = tot[0];
-    rr = tot[2];
-  } else {
-    vN = tot[1];                                // border row of v = A p: sum p
-    rN = a.RV[N].x;
-    rv = fma(a.rh[N], vN, tot[0]);
-    rr = fma(rN, rN, tot[2]);
-  }
-  const double relres = sqrt(rr) / bn;
-  int stop = 0;
-  if (sqrt(rr) <= a.tol * bn) stop = 1;
-  else if (k >= a.maxiter) stop = 2;
-  else if (rv == 0.0) stop = 3;
-  const double alpha = stop ? 0.0 : rho_k / rv;
-  double sN;
-  if (a.sepred) {                               // this block's border row, as k_reduce_b will store it
-    const double2 rvb = a.RV[N + b.domain];
+  double alpha, sN;
+  if (a.sepred) {
+    // this block's domain: alpha and the stopping test were decided by k_reduce_a
+    const DomState &ds = a.dom[b.domain];
+    if (ds.done) return;
+    alpha = ds.alpha[par];
+    const double2 rvb = a.RV[N + b.domain];     // the border row, as k_reduce_b will store it
     sN = fma(-alpha, rvb.y, rvb.x);
   } else {
+    if (early) {
+      if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc->done = 1;
+        sc->iters = (early == 3) ? 0 : k;
+        if (early == 2) sc->fail = 1;
+        if (early == 3) { sc->zero_sol = 1; sc->relres = 0.0; }
+      }
+      return;
+    }
+    double tot[kNA];
+    reduce_prev<kNA>(a.partA, gridDim.x, tot);
+    const double bn = sqrt(bnorm2);
+    const double vN = tot[1];                   // border row of v = A p: sum p
+    const double rN = a.RV[N].x;
+    const double rv = fma(a.rh[N], vN, tot[0]);
+    const double rr = fma(rN, rN, tot[2]);
+    const double relres = sqrt(rr) / bn;
+    int stop = 0;
+    if (sqrt(rr) <= a.tol * bn) stop = 1;
+    else if (k >= a.maxiter) stop = 2;
+    else if (rv == 0.0) stop = 3;
+    alpha = stop ? 0.0 : rho_k / rv;
     sN = fma(-alpha, vN, rN);
-  }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    sc->relres = relres;
-    if (stop) {
-      sc->done = 1;
-      sc->iters = k;
-      if (stop >= 2) sc->fail = stop == 2 ? 2 : 1;
-    } else {
-      sc->alpha[par] = alpha;
-      if (!a.sepred) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      sc->relres = relres;
+      if (stop) {
+        sc->done = 1;
+        sc->iters = k;
+        if (stop >= 2) sc->fail = stop == 2 ? 2 : 1;
+      } else {
+        sc->alpha[par] = alpha;
         a.PVn[N].y = vN;
         a.RV[N].y = vN;
         a.ST[N] = make_double2(sN, 0.0);
       }
     }
+    if (stop) return;
   }
-  if (stop) return;
   const int64_t t = b.first + (int64_t)threadIdx.x;
   const bool live = (int)threadIdx.x < b.nodes;
   double part[kNB] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};   // (t,s), (t,t), (rh,s), (rh,t), (s,s), sum s
@@ -771,9 +802,11 @@ __global__ __launch_bounds__(kBS) void k_correct_heat(SimArgs a) {
   const int64_t t = b.first + (int64_t)threadIdx.x;
   const bool live = (int)threadIdx.x < b.nodes;
   const int64_t N = a.N;
-  const bool zero = a.sc->zero_sol != 0;
-  if (zero && blockIdx.x == 0)
-    for (int d = threadIdx.x; d < a.K; d += blockDim.x) a.x[N + d] = 0.0;
+  // a domain whose pressure problem had a zero right-hand side takes p = 0
+  const bool zero = a.sepred ? a.dom[b.domain].zero_sol != 0 : a.sc->zero_sol != 0;
+  if (blockIdx.x == 0)
+    for (int d = threadIdx.x; d < a.K; d += blockDim.x)
+      if (a.sepred ? a.dom[d].zero_sol != 0 : a.sc->zero_sol != 0) a.x[N + d] = 0.0;
   if (!live) return;
   const int64_t i = b.bstart + t;
   const FT *__restrict__ T = static_cast<const FT *>(a.T);
