@@ -58,6 +58,9 @@ struct hsm_sim {
   int64_t nblk = 0;           // blocks of every node launch
   DBuf blk, dom_blk_off, dom_blk;   // block descriptors; per-domain block lists
   DBuf dom;                          // per-domain Krylov state [K]
+  DBuf dom_nodes;                    // int64 [K] nodes per domain
+  DBuf active;                       // int32 [nblk] blocks of unfinished domains
+  int64_t kry_grid = 0;              // grid of the Krylov node kernels
   bool f32 = false;           // FP32 field form (HSM_F32_COMP)
   bool sepred = false;        // grid totals by a separate one-block kernel (large grids)
 
@@ -90,6 +93,8 @@ SimArgs make_args(hsm_sim *m, int par, int kpar) {
   a.dom_blk_off = m->dom_blk_off.as<int32_t>();
   a.dom_blk = m->dom_blk.as<int32_t>();
   a.dom = m->dom.as<DomState>();
+  a.dom_nodes = m->dom_nodes.as<int64_t>();
+  a.active = m->active.as<int32_t>();
   a.N = m->N;
   a.dt = m->prm.dt; a.Ra = m->prm.Ra; a.Pr = m->prm.Pr; a.T_ref = m->prm.T_ref; a.tol = m->prm.krylov_tol;
   a.maxiter = m->prm.krylov_maxiter;
@@ -110,6 +115,18 @@ SimArgs make_args(hsm_sim *m, int par, int kpar) {
   return a;
 }
 
+// Blocks of the Krylov node kernels that the device holds at once.
+template <int D>
+hsm_status resident_blocks(int64_t &n) {
+  int dev = 0, cus = 0, bp = 0, bs = 0;
+  HSM_HIP(hipGetDevice(&dev));
+  HSM_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  HSM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&bp, k_bicg_pv<D>, kBS, 0));
+  HSM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&bs, k_bicg_st<D>, kBS, 0));
+  n = (int64_t)cus * std::max(1, std::min(bp, bs));
+  return HSM_OK;
+}
+
 // Kernel launches of each phase.
 template <int D>
 hsm_status enqueue_pre(hsm_sim *m, int par, hipStream_t s) {
@@ -122,7 +139,7 @@ hsm_status enqueue_pre(hsm_sim *m, int par, hipStream_t s) {
     hipLaunchKernelGGL((k_predict<D, double>), g, b, 0, s, a);
     hipLaunchKernelGGL((k_rhs<D, double>), g, b, 0, s, a);
   }
-  if (m->sepred) hipLaunchKernelGGL(k_reduce_r, dim3(1), dim3(kRedThreads), 0, s, a);
+  if (m->sepred) hipLaunchKernelGGL(k_reduce_r, dim3((unsigned)red_grid(m->K)), dim3(kRedThreads), 0, s, a);
   HSM_HIP(hipGetLastError());
   return HSM_OK;
 }
@@ -131,18 +148,18 @@ hsm_status enqueue_pre(hsm_sim *m, int par, hipStream_t s) {
 // iteration number, so a batch may be split across launch paths.
 template <int D>
 hsm_status enqueue_krylov(hsm_sim *m, int slot, hipStream_t s, int it0, int it1, bool flags) {
-  const dim3 g((unsigned)m->nblk), b(kBS);
+  const dim3 g((unsigned)m->kry_grid), b(kBS);
   for (int it = it0; it < it1; ++it) {
     SimArgs a = make_args(m, 0, it & 1);
     hipLaunchKernelGGL(k_bicg_pv<D>, g, b, 0, s, a, it);
-    if (m->sepred) hipLaunchKernelGGL(k_reduce_a, dim3(1), dim3(kRedThreads), 0, s, a, it);
+    if (m->sepred) hipLaunchKernelGGL(k_reduce_a, dim3((unsigned)red_grid(m->K)), dim3(kRedThreads), 0, s, a, it);
     hipLaunchKernelGGL(k_bicg_st<D>, g, b, 0, s, a, it);
-    if (m->sepred) hipLaunchKernelGGL(k_reduce_b, dim3(1), dim3(kRedThreads), 0, s, a, it);
+    if (m->sepred) hipLaunchKernelGGL(k_reduce_b, dim3((unsigned)red_grid(m->K)), dim3(kRedThreads), 0, s, a, it);
   }
   HSM_HIP(hipGetLastError());
   if (flags) {
     SimArgs a = make_args(m, 0, 0);
-    hipLaunchKernelGGL(k_chunk_end, dim3(1), dim3(64), 0, s, a);
+    hipLaunchKernelGGL(k_chunk_end, dim3(1), dim3(kRedThreads), 0, s, a);
     HSM_HIP(hipGetLastError());
     Scalars *sc = m->sc.as<Scalars>();
     HSM_HIP(hipMemcpyAsync(&m->hflags[slot], &sc->mirror, sizeof(HostFlags), hipMemcpyDeviceToHost, s));
@@ -272,6 +289,7 @@ hsm_status run_steps(hsm_sim *m, int nsteps) {
         // batches in which every iteration did work: batch time per iteration
         if (!f.done && (rc = add_time(m, HSM_PH_KRYLOV_ITER, m->ep_kry[c & 1][0], m->ep_kry[c & 1][1], m->chunk)))
           return rc;
+        if ((rc = add_time(m, HSM_PH_KRYLOV_TOTAL, m->ep_kry[c & 1][0], m->ep_kry[c & 1][1], 1))) return rc;
       }
       if (f.done || f.nonfinite) break;
       if (++c > max_chunks) { f.fail = 2; break; }
@@ -283,7 +301,11 @@ hsm_status run_steps(hsm_sim *m, int nsteps) {
     m->stats.krylov_iters_last = f.iters;
     m->stats.krylov_iters_total += f.iters;
     m->stats.last_relres = f.relres;
-    m->stats.node_applies += m->n_int * (D * (D + 1) + D + 2 * D + 1) + m->N + per_iter * f.iters + m->n_neu;
+    // Krylov matvec rows: counted per domain on the reduction-kernel path (domains stop
+    // separately), two per iteration over all nodes otherwise
+    const int64_t mv = m->sepred ? (int64_t)f.node_mv : per_iter * f.iters;
+    m->stats.krylov_node_matvecs += mv;
+    m->stats.node_applies += m->n_int * (D * (D + 1) + D + 2 * D + 1) + m->N + mv + m->n_neu;
     if (f.nonfinite) { m->stats.status = HSM_E_NONFINITE; break; }
     if (f.fail) { m->stats.status = HSM_E_NOT_CONVERGED; break; }
   }
@@ -407,6 +429,7 @@ hsm_status hsm_sim_create(const hsm_stencils *st, const hsm_sim_params *prm, con
     std::vector<int32_t> fill(dbo.begin(), dbo.end() - 1);
     for (size_t b2 = 0; b2 < blocks.size(); ++b2) dbl[fill[blocks[b2].domain]++] = (int32_t)b2;
   }
+  for (size_t j2 = 0; j2 < dbl.size(); ++j2) blocks[dbl[j2]].prow = (int32_t)j2;   // one domain: prow = block index
   if ((rc = m->blk.alloc(sizeof(BlockDesc) * (blocks.size() + 1))) ||
       (rc = m->dom_blk_off.alloc(sizeof(int32_t) * dbo.size())) ||
       (rc = m->dom_blk.alloc(sizeof(int32_t) * (dbl.size() + 1))))
@@ -424,8 +447,24 @@ hsm_status hsm_sim_create(const hsm_stencils *st, const hsm_sim_params *prm, con
     return HSM_E_INVALID;
   }
   m->sepred = m->K > 1 || prm->reduce_mode == 2 || (prm->reduce_mode == 0 && m->nblk > kSepReduceBlocks);
-  if ((rc = m->dom.alloc(sizeof(DomState) * m->K))) return rc;
+  // Krylov node kernels: one block per descriptor, except for many domains,
+  // where the blocks the device holds at once walk the list of unfinished
+  // domains' blocks that the reduction kernels keep
+  m->kry_grid = m->nblk;
+  if (m->K > 1) {
+    int64_t res = 0;
+    if ((rc = (m->d == 2 ? resident_blocks<2>(res) : resident_blocks<3>(res)))) return rc;
+    m->kry_grid = std::max<int64_t>(1, std::min(m->nblk, res));
+  }
+  if ((rc = m->active.alloc(sizeof(int32_t) * (m->nblk + 1)))) return rc;
+  if ((rc = m->dom.alloc(sizeof(DomState) * m->K)) || (rc = m->dom_nodes.alloc(sizeof(int64_t) * m->K))) return rc;
   HSM_HIP(hipMemsetAsync(m->dom.p, 0, sizeof(DomState) * m->K, us));
+  {
+    std::vector<int64_t> dn(m->K);
+    for (int32_t d2 = 0; d2 < m->K; ++d2) dn[d2] = st->dom_off[d2 + 1] - st->dom_off[d2];
+    HSM_HIP(hipMemcpyAsync(m->dom_nodes.p, dn.data(), sizeof(int64_t) * m->K, hipMemcpyHostToDevice, us));
+    HSM_HIP(hipStreamSynchronize(us));
+  }
   if ((rc = m->partR.alloc(sizeof(double) * kNR * (m->nblk + 1))) ||
       (rc = m->partA.alloc(sizeof(double) * kNA * (m->nblk + 1))) ||
       (rc = m->partB.alloc(sizeof(double) * kNB * (m->nblk + 1))))

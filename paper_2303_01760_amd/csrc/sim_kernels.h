@@ -25,7 +25,7 @@ constexpr int kRedThreads = 1024;            // threads of a reduction kernel (o
 struct HostFlags {
   int32_t done, iters, fail, nonfinite;
   double relres;
-  double pad;
+  double node_mv;      // node rows through a pressure matrix-vector product so far this step (per-domain path)
 };
 
 // Krylov state.  Values a kernel computes for iteration k live in slot k & 1,
@@ -33,6 +33,9 @@ struct HostFlags {
 struct Scalars {
   double rho[2], alpha[2], omega[2], beta[2];
   double bnorm2, relres;
+  double node_mv;      // per-domain path: node rows that went through a Krylov matvec this step
+  int32_t nactive;     // per-domain path: entries of SimArgs::active
+  int32_t list_sel;    // per-domain path: 0 = every block (SimArgs::dom_blk), 1 = SimArgs::active
   int32_t done, fail, zero_sol, nonfinite;
   int32_t it_base, iters, early[2];   // early: 1 = |s| converged, 2 = breakdown, 3 = zero right-hand side
   HostFlags mirror;
@@ -44,6 +47,7 @@ struct Scalars {
 struct DomState {
   double rho[2], alpha[2], omega[2], beta[2];
   double bnorm2, relres;
+  int64_t mv;          // node rows of this domain through a matvec in this solve
   int32_t early[2];    // decided for the iteration of that parity: 1 = |s| converged, 2 = breakdown
   int32_t done, fail, iters, zero_sol;
 };
@@ -61,7 +65,9 @@ struct BlockDesc {
   int32_t count;       // the bucket's node count: the SoA stride
   int32_t type, width;
   int32_t domain;      // the border row of this block's nodes is N + domain
-  int32_t pad[2];
+  int32_t prow;        // row of this block's partial sums: its place in the per-domain block lists,
+                       // so each domain's rows are contiguous
+  int32_t pad;
 };
 static_assert(sizeof(BlockDesc) == 64, "one 64-byte scalar load per block");
 
@@ -72,6 +78,8 @@ struct SimArgs {
   int32_t K;                       // domains: Krylov vectors hold N + K entries, slot N + k is domain k's border
   const int32_t *dom_blk_off;      // [K+1] per-domain ranges of dom_blk
   const int32_t *dom_blk;          // the blocks of each domain, ascending
+  const int64_t *dom_nodes;        // [K] nodes per domain
+  int32_t *active;                 // [nblk] blocks of unfinished domains (per-domain path), rebuilt as domains finish
   double dt, Ra, Pr, T_ref, tol;
   int32_t maxiter, chunk;
   int32_t sepred;      // 1: grid totals (border rows included) come from the reduction kernels;
@@ -150,7 +158,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 // the first NQ threads write the block's partials.  No fences or atomics:
 // the consumer is a later kernel.
 template <int NQ>
-__device__ __forceinline__ void block_partials(double (&v)[NQ], double *part) {
+__device__ __forceinline__ void block_partials(double (&v)[NQ], double *part, int64_t row = -1, bool again = false) {
   __shared__ double red[kBS / 64][NQ];
   const int wv = threadIdx.x >> 6;
 #pragma unroll
@@ -164,8 +172,9 @@ __device__ __forceinline__ void block_partials(double (&v)[NQ], double *part) {
     double s = red[0][q];
 #pragma unroll
     for (int k = 1; k < kBS / 64; ++k) s += red[k][q];
-    part[(int64_t)blockIdx.x * NQ + q] = s;
+    part[(row < 0 ? (int64_t)blockIdx.x : row) * NQ + q] = s;
   }
+  if (again) __syncthreads();                  // the shared array is reused by this block's next row
 }
 
 // Grid totals of a previous kernel's block partials, reduced by every block
@@ -209,27 +218,100 @@ __device__ __forceinline__ void reduce_prev(const double *__restrict__ part, int
   }
 }
 
-// Per-domain sums for the reduction kernels (one block of kRedThreads):
-// thread d (d += kRedThreads) sums every column of domain d's blocks in
-// order.  The batch flags (every domain done, any failure, worst relative
-// residual, most iterations) are order-free reductions in shared memory.
-template <int NQ>
-__device__ __forceinline__ void domain_sums(const SimArgs &a, const double *__restrict__ part, int d,
-                                            double (&tot)[NQ]) {
-#pragma unroll
-  for (int q = 0; q < NQ; ++q) tot[q] = 0.0;
-  for (int j = a.dom_blk_off[d]; j < a.dom_blk_off[d + 1]; ++j) {
-    const int64_t b = a.dom_blk[j];
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) tot[q] += part[b * NQ + q];
-  }
+// ------------------------------------------------------ reduction kernels --
+// The per-domain reductions run as a grid over domains: G waves of a
+// kRedThreads block sum one domain's block partials (G = 16 for one domain,
+// down to 1 for sixteen or more domains, sixteen to a block).  Lanes stride
+// over the domain's partial rows (contiguous: BlockDesc::prow), a DPP wave
+// sum folds the lanes and the G wave sums are added in order: a fixed
+// order, so the totals are deterministic.  Each domain's update touches
+// only its own state, so the blocks need no fences or atomics between them:
+// with several domains, the batch flags and the list of unfinished domains'
+// blocks are gathered once per batch of iterations (k_chunk_end); with one
+// domain (one block) they are published at once.
+constexpr int kRedWaves = kRedThreads / 64;
+
+// Waves per domain for K domains.
+__host__ __device__ constexpr int red_group(int K) {
+  int p = 1;
+  while (p < K && p < kRedWaves) p <<= 1;
+  return kRedWaves / p;
 }
+// Blocks of a reduction launch.
+inline int64_t red_grid(int K) {
+  const int dpb = kRedWaves / red_group(K);
+  return (K + dpb - 1) / dpb;
+}
+
+struct RedSlot {
+  int d;         // this wave's domain (>= K: none)
+  int g;         // this wave's share of it, 0 .. G-1
+  bool lead;     // the thread that updates the domain: share 0, lane 0
+};
+__device__ __forceinline__ RedSlot red_slot(int K) {
+  const int G = red_group(K), wv = threadIdx.x >> 6;
+  RedSlot r;
+  r.d = (int)blockIdx.x * (kRedWaves / G) + wv / G;
+  r.g = wv % G;
+  r.lead = r.g == 0 && (threadIdx.x & 63) == 0 && r.d < K;
+  return r;
+}
+
+// Totals of domain r.d's block partials, valid in the lead thread.  `need`
+// is the same in every lane of a wave.  Every thread of the block calls it.
+template <int NQ>
+__device__ __forceinline__ void domain_sums(const SimArgs &a, const double *__restrict__ part, const RedSlot &r,
+                                            bool need, double (&tot)[NQ]) {
+  __shared__ double red[kRedWaves][NQ];
+  const int G = red_group(a.K), wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  double acc[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
+  if (need) {
+    // four passes' loads issued before their sums (rows past the end read
+    // as 0.0, which leaves every sum unchanged)
+    constexpr int U = 4;
+    const int j1 = a.dom_blk_off[r.d + 1], step = G * 64;
+    for (int j = a.dom_blk_off[r.d] + r.g * 64 + lane; j < j1; j += U * step) {
+      double vals[U][NQ];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const bool in = j + u * step < j1;
+        const int64_t row = in ? (int64_t)(j + u * step) : (int64_t)j;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+          const double x = part[row * NQ + q];
+          vals[u][q] = in ? x : 0.0;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) acc[q] += vals[u][q];
+    }
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) acc[q] = wave_sum(acc[q]);
+  }
+  if (lane == 0)
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) red[wv][q] = acc[q];
+  __syncthreads();
+  if (r.lead)
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      double t = red[wv][q];
+      for (int k = 1; k < G; ++k) t += red[wv + k][q];
+      tot[q] = t;
+    }
+}
+
 struct BatchFlags {
   int32_t ndone, fail, iters;
   unsigned long long relres_bits;   // non-negative doubles order like their bit patterns
+  unsigned long long mv;            // node rows through a matvec (integer sum: order-free)
 };
 __device__ __forceinline__ void batch_begin(BatchFlags &f) {
-  if (threadIdx.x == 0) { f.ndone = 0; f.fail = 0; f.iters = 0; f.relres_bits = 0ull; }
+  if (threadIdx.x == 0) { f.ndone = 0; f.fail = 0; f.iters = 0; f.relres_bits = 0ull; f.mv = 0ull; }
   __syncthreads();
 }
 __device__ __forceinline__ void batch_add(BatchFlags &f, const DomState &ds) {
@@ -237,18 +319,63 @@ __device__ __forceinline__ void batch_add(BatchFlags &f, const DomState &ds) {
   if (ds.fail) atomicMax(&f.fail, ds.fail);
   atomicMax(&f.iters, ds.iters);
   atomicMax(&f.relres_bits, (unsigned long long)__double_as_longlong(ds.relres));
+  atomicAdd(&f.mv, (unsigned long long)ds.mv);
 }
-// thread 0 publishes the batch state once every domain is done
+// Thread 0 publishes the flags of every domain (every domain done: the
+// batch is done); node_mv is this solve's running total.
 __device__ __forceinline__ void batch_end(const SimArgs &a, BatchFlags &f) {
   __syncthreads();
   if (threadIdx.x == 0) {
     Scalars *sc = a.sc;
     sc->relres = __longlong_as_double((long long)f.relres_bits);
+    sc->node_mv = (double)f.mv;
     if (f.ndone == a.K) {
       sc->done = 1;
       sc->iters = f.iters;
       sc->fail = f.fail;
     }
+  }
+}
+
+// The list of blocks of unfinished domains, domain by domain in order (a
+// block-wide scan of their block counts), for the per-domain Krylov kernels.
+__device__ __forceinline__ void build_active(const SimArgs &a) {
+  __shared__ int32_t scan[kRedThreads];
+  __shared__ int32_t carry;
+  const int tid = threadIdx.x;
+  if (tid == 0) carry = 0;
+  __syncthreads();
+  for (int d0 = 0; d0 < a.K; d0 += kRedThreads) {
+    const int d = d0 + tid;
+    const int c = (d < a.K && !a.dom[d].done) ? a.dom_blk_off[d + 1] - a.dom_blk_off[d] : 0;
+    scan[tid] = c;
+    __syncthreads();
+    for (int off = 1; off < kRedThreads; off <<= 1) {
+      const int v = tid >= off ? scan[tid - off] : 0;
+      __syncthreads();
+      scan[tid] += v;
+      __syncthreads();
+    }
+    // entry e of this chunk belongs to the first domain whose inclusive
+    // count exceeds e
+    const int total = scan[kRedThreads - 1], base = carry;
+    for (int e = tid; e < total; e += kRedThreads) {
+      int lo = 0, hi = kRedThreads - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (scan[mid] > e) hi = mid;
+        else lo = mid + 1;
+      }
+      const int before = lo > 0 ? scan[lo - 1] : 0;
+      a.active[base + e] = a.dom_blk[a.dom_blk_off[d0 + lo] + (e - before)];
+    }
+    __syncthreads();
+    if (tid == 0) carry = base + total;
+    __syncthreads();
+  }
+  if (tid == 0) {
+    a.sc->nactive = carry;
+    a.sc->list_sel = 1;
   }
 }
 
@@ -258,11 +385,14 @@ __device__ __forceinline__ void batch_end(const SimArgs &a, BatchFlags &f) {
 // right-hand side is done at once with p = 0.
 __global__ __launch_bounds__(kRedThreads) void k_reduce_r(SimArgs a) {
   __shared__ BatchFlags f;
-  batch_begin(f);
+  const bool one = a.K == 1;
+  if (one) batch_begin(f);
   const int64_t N = a.N;
-  for (int d = threadIdx.x; d < a.K; d += kRedThreads) {
-    double tot[kNR];
-    domain_sums<kNR>(a, a.partR, d, tot);
+  const RedSlot rs = red_slot(a.K);
+  const int d = rs.d;
+  double tot[kNR];
+  domain_sums<kNR>(a, a.partR, rs, d < a.K, tot);
+  if (rs.lead) {
     DomState &ds = a.dom[d];
     const double r = -tot[2];
     a.RV[N + d] = make_double2(r, 0.0);
@@ -273,12 +403,13 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_r(SimArgs a) {
     ds.early[0] = 0;
     ds.fail = 0;
     ds.iters = 0;
+    ds.mv = 0;
     ds.zero_sol = tot[0] == 0.0;
     ds.done = ds.zero_sol;
     ds.relres = ds.zero_sol ? 0.0 : sqrt(rr / tot[0]);
-    batch_add(f, ds);
+    if (one) batch_add(f, ds);
   }
-  batch_end(a, f);
+  if (one) batch_end(a, f);
 }
 
 // After k_bicg_pv(it), per unfinished domain: the border rows of iteration
@@ -292,17 +423,34 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_a(SimArgs a, int it) {
   Scalars *sc = a.sc;
   if (sc->done) return;
   __shared__ BatchFlags f;
-  batch_begin(f);
+  const bool one = a.K == 1;
+  if (one) batch_begin(f);
   const int par = it & 1;
   const int64_t N = a.N;
   const int k = sc->it_base + it;
-  for (int d = threadIdx.x; d < a.K; d += kRedThreads) {
+  const RedSlot rs = red_slot(a.K);
+  const int d = rs.d;
+  const bool live = d < a.K && !a.dom[d].done;
+  const int e = (live && k != 0) ? a.dom[d].early[par] : 0;
+  // the lead's border rows and scalars, loaded while the partials are summed
+  double alpha_p = 0.0, omega = 0.0, beta = 0.0, bnorm2 = 0.0, rho = 0.0, xb = 0.0, rhb = 0.0;
+  double2 rvb = make_double2(0.0, 0.0), stb = rvb, pvb = rvb;
+  int64_t nodes = 0;
+  if (rs.lead && live) {
+    const DomState &ds = a.dom[d];
+    alpha_p = ds.alpha[par ^ 1]; omega = ds.omega[par]; beta = ds.beta[par];
+    bnorm2 = ds.bnorm2; rho = ds.rho[par];
+    xb = a.x[N + d]; rhb = a.rh[N + d];
+    rvb = a.RV[N + d]; stb = a.ST[N + d]; pvb = a.PVo[N + d];
+    nodes = a.dom_nodes[d];
+  }
+  double tot[kNA];
+  domain_sums<kNA>(a, a.partA, rs, live && e == 0, tot);
+  if (rs.lead) {
     DomState &ds = a.dom[d];
-    if (!ds.done) {
-      const int e = (k == 0) ? 0 : ds.early[par];
-      const double alpha_p = ds.alpha[par ^ 1], omega = ds.omega[par], beta = ds.beta[par];
+    if (live) {
       if (e == 1) {
-        a.x[N + d] = fma(alpha_p, a.PVo[N + d].x, a.x[N + d]);
+        a.x[N + d] = fma(alpha_p, pvb.x, xb);
         ds.done = 1;
         ds.iters = k;
       } else if (e == 2) {
@@ -310,34 +458,35 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_a(SimArgs a, int it) {
         ds.fail = 1;
         ds.iters = k;
       } else {
-        double tot[kNA];
-        domain_sums<kNA>(a, a.partA, d, tot);
+        ds.mv += nodes;                         // k_bicg_pv's matvec on this domain
         double r, p;
         if (k == 0) {
-          r = a.RV[N + d].x;
+          r = rvb.x;
           p = r;
         } else {
-          const double2 st = a.ST[N + d], pv = a.PVo[N + d];
-          a.x[N + d] = fma(omega, st.x, fma(alpha_p, pv.x, a.x[N + d]));
-          r = fma(-omega, st.y, st.x);
-          p = fma(beta, fma(-omega, pv.y, pv.x), r);
+          a.x[N + d] = fma(omega, stb.x, fma(alpha_p, pvb.x, xb));
+          r = fma(-omega, stb.y, stb.x);
+          p = fma(beta, fma(-omega, pvb.y, pvb.x), r);
         }
         const double vb = tot[1];               // border row of v = A p': sum of p' over the domain
         a.PVn[N + d] = make_double2(p, vb);
         a.RV[N + d] = make_double2(r, vb);
-        const double rv = fma(a.rh[N + d], vb, tot[0]);
+        const double rv = fma(rhb, vb, tot[0]);
         const double rr = fma(r, r, tot[2]);
-        const double bn = sqrt(ds.bnorm2);
+        const double bn = sqrt(bnorm2);
         ds.relres = sqrt(rr) / bn;
         if (sqrt(rr) <= a.tol * bn) { ds.done = 1; ds.iters = k; }
         else if (k >= a.maxiter) { ds.done = 1; ds.fail = 2; ds.iters = k; }
         else if (rv == 0.0) { ds.done = 1; ds.fail = 1; ds.iters = k; }
-        else ds.alpha[par] = ds.rho[par] / rv;
+        else {
+          ds.alpha[par] = rho / rv;
+          ds.mv += nodes;                       // k_bicg_st's matvec follows
+        }
       }
     }
-    batch_add(f, ds);
+    if (one) batch_add(f, ds);
   }
-  batch_end(a, f);
+  if (one) batch_end(a, f);
 }
 
 // After k_bicg_st(it), per unfinished domain: s = r - alpha v and
@@ -349,34 +498,42 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_b(SimArgs a, int it) {
   if (sc->done) return;
   const int par = it & 1, nx = par ^ 1;
   const int64_t N = a.N;
-  for (int d = threadIdx.x; d < a.K; d += kRedThreads) {
-    DomState &ds = a.dom[d];
-    if (ds.done) continue;
-    double tot[kNB];
-    domain_sums<kNB>(a, a.partB, d, tot);
-    const double alpha = ds.alpha[par];
-    const double2 rv = a.RV[N + d];
-    const double sb = fma(-alpha, rv.y, rv.x), tb = tot[5], rhb = a.rh[N + d];
-    a.ST[N + d] = make_double2(sb, tb);
-    const double ts = fma(tb, sb, tot[0]), tt = fma(tb, tb, tot[1]);
-    const double rhs_ = fma(rhb, sb, tot[2]), rht = fma(rhb, tb, tot[3]);
-    const double ss = fma(sb, sb, tot[4]);
-    const double bn = sqrt(ds.bnorm2);
-    int e = 0;
-    double omega = 0.0, beta = 0.0, rho_n = 0.0;
-    if (sqrt(ss) <= a.tol * bn) { e = 1; ds.relres = sqrt(ss) / bn; }
-    else if (tt == 0.0) e = 2;
-    else {
-      omega = ts / tt;
-      rho_n = fma(-omega, rht, rhs_);
-      if (rho_n == 0.0 || omega == 0.0) e = 2;
-      else beta = (rho_n / ds.rho[par]) * (alpha / omega);
-    }
-    ds.early[nx] = e;
-    ds.omega[nx] = omega;
-    ds.beta[nx] = beta;
-    ds.rho[nx] = rho_n;
+  const RedSlot rs = red_slot(a.K);
+  const int d = rs.d;
+  const bool live = d < a.K && !a.dom[d].done;
+  // the lead's border rows and scalars, loaded while the partials are summed
+  double alpha = 0.0, rho = 0.0, bnorm2 = 0.0, rhb = 0.0;
+  double2 rv = make_double2(0.0, 0.0);
+  if (rs.lead && live) {
+    const DomState &ds = a.dom[d];
+    alpha = ds.alpha[par]; rho = ds.rho[par]; bnorm2 = ds.bnorm2;
+    rv = a.RV[N + d];
+    rhb = a.rh[N + d];
   }
+  double tot[kNB];
+  domain_sums<kNB>(a, a.partB, rs, live, tot);
+  if (!(rs.lead && live)) return;
+  DomState &ds = a.dom[d];
+  const double sb = fma(-alpha, rv.y, rv.x), tb = tot[5];
+  a.ST[N + d] = make_double2(sb, tb);
+  const double ts = fma(tb, sb, tot[0]), tt = fma(tb, tb, tot[1]);
+  const double rhs_ = fma(rhb, sb, tot[2]), rht = fma(rhb, tb, tot[3]);
+  const double ss = fma(sb, sb, tot[4]);
+  const double bn = sqrt(bnorm2);
+  int e = 0;
+  double omega = 0.0, beta = 0.0, rho_n = 0.0;
+  if (sqrt(ss) <= a.tol * bn) { e = 1; ds.relres = sqrt(ss) / bn; }
+  else if (tt == 0.0) e = 2;
+  else {
+    omega = ts / tt;
+    rho_n = fma(-omega, rht, rhs_);
+    if (rho_n == 0.0 || omega == 0.0) e = 2;
+    else beta = (rho_n / rho) * (alpha / omega);
+  }
+  ds.early[nx] = e;
+  ds.omega[nx] = omega;
+  ds.beta[nx] = beta;
+  ds.rho[nx] = rho_n;
 }
 
 // ------------------------------------------------------------- predictor --
@@ -472,8 +629,10 @@ __global__ __launch_bounds__(kBS) void k_rhs(SimArgs a) {
   const double lam = a.x[N + b.domain];        // this domain's border multiplier
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     Scalars *sc = a.sc;
-    sc->done = 0; sc->fail = 0; sc->zero_sol = 0; sc->it_base = 0; sc->iters = 0;
+    sc->done = 0; sc->fail = 0; sc->zero_sol = 0; sc->it_base = 0; sc->iters = 0; sc->node_mv = 0.0;
     sc->early[0] = 0; sc->early[1] = 0;
+    sc->list_sel = 0;                           // a new solve starts from every block
+    sc->nactive = (int32_t)a.nblk;
   }
   if (live) {
     const int64_t i = b.bstart + t;
@@ -527,7 +686,7 @@ __global__ __launch_bounds__(kBS) void k_rhs(SimArgs a) {
     part[1] = r * r;
     part[2] = x[i];
   }
-  block_partials<kNR>(part, a.partR);
+  block_partials<kNR>(part, a.partR, b.prow);
 }
 
 // ------------------------------------------------------- BiCGSTAB steps --
@@ -542,93 +701,13 @@ __global__ __launch_bounds__(kBS) void k_rhs(SimArgs a) {
 // Vectors gathered together are stored as pairs, one 16-byte load per
 // neighbour: (s, t), (p, v) (two generations) and (r, v).  The border row
 // and column (zero mean, multiplier) are slot N of every vector.
+// The node rows of one block of k_bicg_pv.
 template <int D>
-__global__ __launch_bounds__(kBS) void k_bicg_pv(SimArgs a, int it) {
-  Scalars *sc = a.sc;
-  const int par = it & 1;
-  // independent loads first (one wait), then the early exit
-  const int done = sc->done, it_base = sc->it_base;
-  const double bnorm2 = sc->bnorm2, alpha_prev = sc->alpha[par ^ 1], rho_prev = sc->rho[par ^ 1];
-  const BlockDesc b = a.blk[blockIdx.x];
-  if (done) return;
+__device__ __forceinline__ void pv_rows(const SimArgs &a, const BlockDesc &b, bool again, bool first,
+                                        int early, double omega, double beta, double alpha_p, double pN) {
   const int64_t N = a.N;
-  const int k = it_base + it;
-  const bool first = (k == 0);
-  double omega = 0.0, beta = 0.0, alpha_p = 0.0, pN;
-  int early = 0;
   const double2 *__restrict__ ST = a.ST;
   const double2 *__restrict__ PVo = a.PVo;
-  if (a.sepred) {
-    // this block's domain: its scalars were decided by k_reduce_b (or k_reduce_r)
-    const DomState &ds = a.dom[b.domain];
-    if (ds.done) return;
-    const int64_t NB = N + b.domain;
-    if (first) {
-      pN = a.RV[NB].x;                          // p0 = r0 on the border row
-    } else {
-      early = ds.early[par];
-      if (early == 2) return;
-      omega = ds.omega[par];
-      beta = ds.beta[par];
-      alpha_p = ds.alpha[par ^ 1];
-      const double2 stb = ST[NB], pvb = PVo[NB];  // the border row, as k_reduce_a will store it
-      const double rN = fma(-omega, stb.y, stb.x);
-      pN = fma(beta, fma(-omega, pvb.y, pvb.x), rN);
-    }
-  } else if (first) {
-    // one domain, small grid: every block reduces the partials and takes the same decisions
-    double tot[kNR];
-    reduce_prev<kNR>(a.partR, gridDim.x, tot);
-    const double rN = -tot[2];                  // border row of r0: 0 - sum x
-    const double rho_k = fma(rN, rN, tot[1]);   // (rh, r0) = |r0|^2
-    pN = rN;
-    if (tot[0] == 0.0) early = 3;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-      sc->bnorm2 = tot[0];
-      a.RV[N] = make_double2(rN, 0.0);
-      a.rh[N] = rN;
-      a.PVn[N] = make_double2(pN, 0.0);
-      sc->rho[par] = rho_k;
-      sc->early[par] = early;
-    }
-    if (early) return;
-  } else {
-    double tot[kNB];
-    reduce_prev<kNB>(a.partB, gridDim.x, tot);
-    const double bn = sqrt(bnorm2);
-    const double sN = ST[N].x, rhN = a.rh[N];
-    const double2 pvN = PVo[N];
-    const double tN = tot[5];                   // border row of t = A s: sum s
-    const double ts = fma(tN, sN, tot[0]), tt = fma(tN, tN, tot[1]);
-    const double rhs_ = fma(rhN, sN, tot[2]), rht = fma(rhN, tN, tot[3]);
-    const double ss = fma(sN, sN, tot[4]);
-    alpha_p = alpha_prev;
-    const double rho_p = rho_prev;
-    double rho_k = 0.0;
-    if (sqrt(ss) <= a.tol * bn) early = 1;
-    else if (tt == 0.0) early = 2;
-    else {
-      omega = ts / tt;
-      rho_k = fma(-omega, rht, rhs_);
-      if (rho_k == 0.0 || omega == 0.0) early = 2;
-      else beta = (rho_k / rho_p) * (alpha_p / omega);
-    }
-    const double rN = fma(-omega, tN, sN);
-    pN = fma(beta, fma(-omega, pvN.y, pvN.x), rN);
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-      sc->early[par] = early;
-      if (early == 1) {
-        a.x[N] = fma(alpha_p, pvN.x, a.x[N]);
-        sc->relres = sqrt(ss) / bn;
-      } else if (early == 0) {
-        a.x[N] = fma(omega, sN, fma(alpha_p, pvN.x, a.x[N]));
-        a.RV[N] = make_double2(rN, 0.0);
-        a.PVn[N] = make_double2(pN, 0.0);
-        sc->rho[par] = rho_k;
-      }
-    }
-    if (early == 2) return;
-  }
   const int64_t t = b.first + (int64_t)threadIdx.x;
   const bool live = (int)threadIdx.x < b.nodes;
   if (early == 1) {                             // |s| converged: x += alpha p, nothing else
@@ -683,66 +762,111 @@ __global__ __launch_bounds__(kBS) void k_bicg_pv(SimArgs a, int it) {
     part[1] = pi;
     part[2] = ri * ri;
   }
-  block_partials<kNA>(part, a.partA);
+  block_partials<kNA>(part, a.partA, b.prow, again);
 }
 
 template <int D>
-__global__ __launch_bounds__(kBS) void k_bicg_st(SimArgs a, int it) {
+__global__ __launch_bounds__(kBS) void k_bicg_pv(SimArgs a, int it) {
   Scalars *sc = a.sc;
   const int par = it & 1;
-  const int done = sc->done, it_base = sc->it_base, early = sc->early[par];
-  const double bnorm2 = sc->bnorm2, rho_k = sc->rho[par];
-  const BlockDesc b = a.blk[blockIdx.x];
+  // independent loads first (one wait), then the early exit
+  const int done = sc->done, it_base = sc->it_base, nact = sc->nactive, lsel = sc->list_sel;
+  const double bnorm2 = sc->bnorm2, alpha_prev = sc->alpha[par ^ 1], rho_prev = sc->rho[par ^ 1];
   if (done) return;
   const int64_t N = a.N;
   const int k = it_base + it;
-  double alpha, sN;
+  const bool first = (k == 0);
+  const double2 *__restrict__ ST = a.ST;
+  const double2 *__restrict__ PVo = a.PVo;
   if (a.sepred) {
-    // this block's domain: alpha and the stopping test were decided by k_reduce_a
-    const DomState &ds = a.dom[b.domain];
-    if (ds.done) return;
-    alpha = ds.alpha[par];
-    const double2 rvb = a.RV[N + b.domain];     // the border row, as k_reduce_b will store it
-    sN = fma(-alpha, rvb.y, rvb.x);
-  } else {
-    if (early) {
-      if (blockIdx.x == 0 && threadIdx.x == 0) {
-        sc->done = 1;
-        sc->iters = (early == 3) ? 0 : k;
-        if (early == 2) sc->fail = 1;
-        if (early == 3) { sc->zero_sol = 1; sc->relres = 0.0; }
-      }
-      return;
-    }
-    double tot[kNA];
-    reduce_prev<kNA>(a.partA, gridDim.x, tot);
-    const double bn = sqrt(bnorm2);
-    const double vN = tot[1];                   // border row of v = A p: sum p
-    const double rN = a.RV[N].x;
-    const double rv = fma(a.rh[N], vN, tot[0]);
-    const double rr = fma(rN, rN, tot[2]);
-    const double relres = sqrt(rr) / bn;
-    int stop = 0;
-    if (sqrt(rr) <= a.tol * bn) stop = 1;
-    else if (k >= a.maxiter) stop = 2;
-    else if (rv == 0.0) stop = 3;
-    alpha = stop ? 0.0 : rho_k / rv;
-    sN = fma(-alpha, vN, rN);
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-      sc->relres = relres;
-      if (stop) {
-        sc->done = 1;
-        sc->iters = k;
-        if (stop >= 2) sc->fail = stop == 2 ? 2 : 1;
+    // the listed blocks (every block, or those of domains unfinished at the
+    // last batch end) of unfinished domains; each domain's scalars were
+    // decided by k_reduce_b (or k_reduce_r)
+    const int32_t *lst = lsel ? a.active : a.dom_blk;
+    for (int64_t v = blockIdx.x; v < nact; v += gridDim.x) {
+      const int32_t bi = a.K == 1 ? (int32_t)v : lst[v];   // one domain: every block, in order
+      const BlockDesc b = a.blk[bi];
+      const DomState &ds = a.dom[b.domain];
+      const int64_t NB = N + b.domain;
+      if (ds.done) continue;
+      if (first) {
+        pv_rows<D>(a, b, true, true, 0, 0.0, 0.0, 0.0, a.RV[NB].x);   // p0 = r0 on the border row
       } else {
-        sc->alpha[par] = alpha;
-        a.PVn[N].y = vN;
-        a.RV[N].y = vN;
-        a.ST[N] = make_double2(sN, 0.0);
+        const int early = ds.early[par];
+        if (early == 2) continue;
+        const double omega = ds.omega[par], beta = ds.beta[par];
+        const double2 stb = ST[NB], pvb = PVo[NB];  // the border row, as k_reduce_a will store it
+        const double pN = fma(beta, fma(-omega, pvb.y, pvb.x), fma(-omega, stb.y, stb.x));
+        pv_rows<D>(a, b, true, false, early, omega, beta, ds.alpha[par ^ 1], pN);
       }
     }
-    if (stop) return;
+    return;
   }
+  // one domain, small grid: every block reduces the partials and takes the same decisions
+  const BlockDesc b = a.blk[blockIdx.x];
+  double omega = 0.0, beta = 0.0, alpha_p = 0.0, pN;
+  int early = 0;
+  if (first) {
+    double tot[kNR];
+    reduce_prev<kNR>(a.partR, gridDim.x, tot);
+    const double rN = -tot[2];                  // border row of r0: 0 - sum x
+    const double rho_k = fma(rN, rN, tot[1]);   // (rh, r0) = |r0|^2
+    pN = rN;
+    if (tot[0] == 0.0) early = 3;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      sc->bnorm2 = tot[0];
+      a.RV[N] = make_double2(rN, 0.0);
+      a.rh[N] = rN;
+      a.PVn[N] = make_double2(pN, 0.0);
+      sc->rho[par] = rho_k;
+      sc->early[par] = early;
+    }
+    if (early) return;
+  } else {
+    double tot[kNB];
+    reduce_prev<kNB>(a.partB, gridDim.x, tot);
+    const double bn = sqrt(bnorm2);
+    const double sN = ST[N].x, rhN = a.rh[N];
+    const double2 pvN = PVo[N];
+    const double tN = tot[5];                   // border row of t = A s: sum s
+    const double ts = fma(tN, sN, tot[0]), tt = fma(tN, tN, tot[1]);
+    const double rhs_ = fma(rhN, sN, tot[2]), rht = fma(rhN, tN, tot[3]);
+    const double ss = fma(sN, sN, tot[4]);
+    alpha_p = alpha_prev;
+    const double rho_p = rho_prev;
+    double rho_k = 0.0;
+    if (sqrt(ss) <= a.tol * bn) early = 1;
+    else if (tt == 0.0) early = 2;
+    else {
+      omega = ts / tt;
+      rho_k = fma(-omega, rht, rhs_);
+      if (rho_k == 0.0 || omega == 0.0) early = 2;
+      else beta = (rho_k / rho_p) * (alpha_p / omega);
+    }
+    const double rN = fma(-omega, tN, sN);
+    pN = fma(beta, fma(-omega, pvN.y, pvN.x), rN);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      sc->early[par] = early;
+      if (early == 1) {
+        a.x[N] = fma(alpha_p, pvN.x, a.x[N]);
+        sc->relres = sqrt(ss) / bn;
+      } else if (early == 0) {
+        a.x[N] = fma(omega, sN, fma(alpha_p, pvN.x, a.x[N]));
+        a.RV[N] = make_double2(rN, 0.0);
+        a.PVn[N] = make_double2(pN, 0.0);
+        sc->rho[par] = rho_k;
+      }
+    }
+    if (early == 2) return;
+  }
+  pv_rows<D>(a, b, false, first, early, omega, beta, alpha_p, pN);
+}
+
+// The node rows of one block of k_bicg_st.
+template <int D>
+__device__ __forceinline__ void st_rows(const SimArgs &a, const BlockDesc &b, bool again, double alpha,
+                                        double sN) {
+  const int64_t N = a.N;
   const int64_t t = b.first + (int64_t)threadIdx.x;
   const bool live = (int)threadIdx.x < b.nodes;
   double part[kNB] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};   // (t,s), (t,t), (rh,s), (rh,t), (s,s), sum s
@@ -774,14 +898,88 @@ __global__ __launch_bounds__(kBS) void k_bicg_st(SimArgs a, int it) {
     part[4] = si * si;
     part[5] = si;
   }
-  block_partials<kNB>(part, a.partB);
+  block_partials<kNB>(part, a.partB, b.prow, again);
 }
 
-// End of a batch of iterations: advance the iteration base and publish a
-// summary for the host.
-__global__ void k_chunk_end(SimArgs a) {
-  if (threadIdx.x != 0) return;
+template <int D>
+__global__ __launch_bounds__(kBS) void k_bicg_st(SimArgs a, int it) {
   Scalars *sc = a.sc;
+  const int par = it & 1;
+  const int done = sc->done, it_base = sc->it_base, early = sc->early[par], nact = sc->nactive, lsel = sc->list_sel;
+  const double bnorm2 = sc->bnorm2, rho_k = sc->rho[par];
+  if (done) return;
+  const int64_t N = a.N;
+  const int k = it_base + it;
+  if (a.sepred) {
+    // the listed blocks of unfinished domains; alpha was decided by k_reduce_a
+    const int32_t *lst = lsel ? a.active : a.dom_blk;
+    for (int64_t v = blockIdx.x; v < nact; v += gridDim.x) {
+      const int32_t bi = a.K == 1 ? (int32_t)v : lst[v];
+      const BlockDesc b = a.blk[bi];
+      const DomState &ds = a.dom[b.domain];
+      if (ds.done) continue;
+      const double alpha = ds.alpha[par];
+      const double2 rvb = a.RV[N + b.domain];   // the border row, as k_reduce_b will store it
+      st_rows<D>(a, b, true, alpha, fma(-alpha, rvb.y, rvb.x));
+    }
+    return;
+  }
+  const BlockDesc b = a.blk[blockIdx.x];
+  if (early) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      sc->done = 1;
+      sc->iters = (early == 3) ? 0 : k;
+      if (early == 2) sc->fail = 1;
+      if (early == 3) { sc->zero_sol = 1; sc->relres = 0.0; }
+    }
+    return;
+  }
+  double tot[kNA];
+  reduce_prev<kNA>(a.partA, gridDim.x, tot);
+  const double bn = sqrt(bnorm2);
+  const double vN = tot[1];                     // border row of v = A p: sum p
+  const double rN = a.RV[N].x;
+  const double rv = fma(a.rh[N], vN, tot[0]);
+  const double rr = fma(rN, rN, tot[2]);
+  const double relres = sqrt(rr) / bn;
+  int stop = 0;
+  if (sqrt(rr) <= a.tol * bn) stop = 1;
+  else if (k >= a.maxiter) stop = 2;
+  else if (rv == 0.0) stop = 3;
+  const double alpha = stop ? 0.0 : rho_k / rv;
+  const double sN = fma(-alpha, vN, rN);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    sc->relres = relres;
+    if (stop) {
+      sc->done = 1;
+      sc->iters = k;
+      if (stop >= 2) sc->fail = stop == 2 ? 2 : 1;
+    } else {
+      sc->alpha[par] = alpha;
+      a.PVn[N].y = vN;
+      a.RV[N].y = vN;
+      a.ST[N] = make_double2(sN, 0.0);
+    }
+  }
+  if (stop) return;
+  st_rows<D>(a, b, false, alpha, sN);
+}
+
+// End of a batch of iterations (one block of kRedThreads).  With several
+// domains: the batch flags from every domain's state and the list of the
+// blocks still to run.  Then: advance the iteration base and publish a
+// summary for the host.
+__global__ __launch_bounds__(kRedThreads) void k_chunk_end(SimArgs a) {
+  Scalars *sc = a.sc;
+  if (a.K > 1 && !sc->done) {
+    __shared__ BatchFlags f;
+    batch_begin(f);
+    for (int d = threadIdx.x; d < a.K; d += kRedThreads) batch_add(f, a.dom[d]);
+    batch_end(a, f);
+    __syncthreads();
+    if (!sc->done) build_active(a);
+  }
+  if (threadIdx.x != 0) return;
   if (!sc->done) sc->it_base += a.chunk;
   HostFlags &h = sc->mirror;
   h.done = sc->done;
@@ -789,7 +987,7 @@ __global__ void k_chunk_end(SimArgs a) {
   h.fail = sc->fail;
   h.nonfinite = sc->nonfinite;
   h.relres = sc->relres;
-  h.pad = 0.0;
+  h.node_mv = sc->node_mv;
 }
 
 // -------------------------------------------- projection + heat transport --

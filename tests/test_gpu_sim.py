@@ -190,7 +190,60 @@ def test_multi_domain_steps_match_oracle(field_dtype):
     print(f"3 domains, field dtype {field_dtype}: rel L2 err v {ev:.2e} T {eT:.2e} p (worst domain) {ep:.2e}; "
           f"krylov iters gpu {stats['krylov_iters_total']} oracle {int(its.sum())}")
     assert ev <= tol and eT <= tol and ep <= tol
+    # domains stop separately: fewer matvec rows than all nodes for every batch iteration
+    N = len(kind)
+    assert 0 < stats["krylov_node_matvecs"] < 2 * N * (stats["krylov_iters_total"] + 50)
     # every domain's pressure has zero mean
+    for a, b in zip(off[:-1], off[1:]):
+        assert abs(pg[a:b].sum()) <= 1e-9 * np.abs(pg[a:b]).sum()
+
+
+def _many_domains(n):
+    # n small cavities of four spacings, each with its own temperature perturbation
+    hs = [1 / 12, 1 / 16, 1 / 20, 1 / 24]
+    sets = [ng.cavity2d(h=hs[j % 4], seed=400 + j) for j in range(n)]
+    x = np.concatenate([q.x for q in sets], axis=1)
+    kind = np.concatenate([q.kind for q in sets])
+    nrm = np.concatenate([q.normal for q in sets], axis=1)
+    tbc = np.concatenate([q.tbc for q in sets])
+    off = np.cumsum([0] + [q.n for q in sets]).astype(np.int64)
+    dom = np.repeat(np.arange(n), [q.n for q in sets])
+    T0 = np.where(kind == 1, tbc, 0.5)
+    T0 = np.where(kind == 0, 0.5 + 0.2 * np.sin(4 * x[0] + dom) * np.cos(3 * x[1] - 0.5 * dom), T0)
+    return sets, x, kind, nrm, off, T0
+
+
+def test_many_domains_steps_match_oracle():
+    # 40 domains: several reduction blocks (sixteen domains to a block), and
+    # domains that stop at different iterations
+    hsm = _hsm()
+    sets, x, kind, nrm, off, T0 = _many_domains(40)
+    hs = [q.h for q in sets]
+    dt = 0.1 * min(hs) ** 2 / 2
+    prm = dict(Ra=1e4, Pr=0.71, dt=dt, T_ref=0.5)
+    dev = torch.device("cuda")
+    st = hsm.build_stencils(torch.tensor(x, device=dev), torch.tensor(kind, device=dev), torch.tensor(nrm, device=dev),
+                            hs, 2, domain_offsets=off)
+    v = np.zeros((2, len(kind)))
+    sim = hsm.Sim(st, torch.tensor(v, device=dev), torch.tensor(T0, device=dev), krylov_tol=1e-12, **prm)
+    sim.step(20)
+    stats = sim.stats()
+    assert stats["status"] == 0 and stats["steps"] == 20
+    vg, Tg, pg = [a.cpu().numpy() for a in sim.read()]
+    # the oracle steps each domain alone (pinned equal to stepping them together), with the dense solver
+    vo, To, po = v.copy(), T0.copy(), np.zeros(len(kind))
+    for j, q in enumerate(sets):
+        a, b = off[j], off[j + 1]
+        vj, Tj, pj = np.zeros((2, q.n)), T0[a:b].copy(), np.zeros(q.n + 1)
+        O.Sim(O.to_csr(O.build(q.x, q.kind, q.normal, q.h, 2)), q.kind, solver=1).step(vj, Tj, pj, 20, **prm)
+        vo[:, a:b], To[a:b], po[a:b] = vj, Tj, pj[:q.n]
+    ev, eT = _rel(vg, vo), _rel(Tg, To)
+    ep = max(_rel(pg[a:b], po[a:b]) for a, b in zip(off[:-1], off[1:]))
+    print(f"40 domains: rel L2 err v {ev:.2e} T {eT:.2e} p (worst domain) {ep:.2e}; "
+          f"krylov iters gpu {stats['krylov_iters_total']}")
+    assert ev <= FIELD_TOL and eT <= FIELD_TOL and ep <= FIELD_TOL
+    N = len(kind)
+    assert 0 < stats["krylov_node_matvecs"] < 2 * N * (stats["krylov_iters_total"] + 20)
     for a, b in zip(off[:-1], off[1:]):
         assert abs(pg[a:b].sum()) <= 1e-9 * np.abs(pg[a:b]).sum()
 
@@ -245,6 +298,10 @@ def test_graph_replay_matches_direct_launches():
     # only batches in which all 8 iterations did work are timed
     assert 0 < ph["krylov_iter"][1] <= iters[2] and ph["krylov_iter"][1] % 8 == 0, ph
     assert all(ms > 0 for ms, _ in ph.values()), ph
+    assert ph["krylov_batch"][1] >= ph["krylov_iter"][1] // 8, ph
+    # one domain, small grid: two matvec rows per node and iteration
+    st2 = sims[2].stats()
+    assert st2["krylov_node_matvecs"] == 2 * len(s.kind) * st2["krylov_iters_total"]
     with pytest.raises(hsm.HsmError):
         sims[0].phase_times()
 
