@@ -328,6 +328,7 @@ def main():
             return st
         rec["applies"] += stats["node_applies"]
         rec["krylov_iters"] += stats["krylov_iters_total"]
+        rec["node_mv"] = rec.get("node_mv", 0) + stats["krylov_node_matvecs"]
         for k, (ms, n) in sim.phase_times().items():
             t = rec["ptimes"].setdefault(k, [0.0, 0])
             t[0] += ms * n
@@ -435,10 +436,20 @@ def main():
         bytes_it = kernel_bytes(buckets, s.n, "iteration")
         it_ms = pt["krylov_iter"][0]
         achieved = bytes_it / (it_ms * 1e-3) / 1e9
+        if multi:
+            # domains stop separately: the work done is the node rows that went through a
+            # matvec (counted on the device), at the mean bytes of one node row of one matvec,
+            # over the time of every Krylov batch
+            b_ms, n_b = pt["krylov_batch"]
+            work = hy["node_mv"] * bytes_it / (2.0 * s.n)
+            achieved = work / (b_ms * n_b * 1e-3) / 1e9
         tr = traffic_record() if args.workload == "c2" else None
         roofline = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS,
                         traffic=(tr["hbm_bytes_per_iteration"] if tr else None),
-                        kernel=f"BiCGSTAB iteration (k_bicg_pv<{D}> + k_bicg_st<{D}>)", bytes_per_launch=bytes_it,
+                        kernel=(f"BiCGSTAB iterations of {s.n_domains} domains, each stopping on its own "
+                                f"(k_bicg_pv<{D}> + k_bicg_st<{D}> + reductions), bytes of the rows computed"
+                                if multi else f"BiCGSTAB iteration (k_bicg_pv<{D}> + k_bicg_st<{D}>)"),
+                        bytes_per_launch=bytes_it,
                         bytes_pv=kernel_bytes(buckets, s.n, "bicg_pv"), bytes_st=kernel_bytes(buckets, s.n, "bicg_st"),
                         mean_launch_ms=it_ms, iterations_timed=pt["krylov_iter"][1], copy_kernel_gbs=copy_gbs)
     else:

@@ -186,6 +186,7 @@ typedef struct {
   int32_t status;                /* latched hsm_status of the stepping */
   double last_relres;            /* relative residual reached in the last step */
   int64_t node_applies;          /* (operator, field, node) triples evaluated so far */
+  int64_t krylov_node_matvecs;   /* node rows through a pressure matrix-vector product so far */
 } hsm_sim_stats;
 
 /*
@@ -231,15 +232,17 @@ hsm_status hsm_sim_get_stats(hsm_sim *sim, hsm_sim_stats *out);
 hsm_status hsm_sim_read(hsm_sim *sim, double *v, double *T, double *p, void *stream);
 
 /* Phases timed in profile mode, in this order. */
-enum { HSM_PH_PRE = 0, HSM_PH_KRYLOV_ITER = 1, HSM_PH_POST = 2, HSM_PH_COUNT = 3 };
+enum { HSM_PH_PRE = 0, HSM_PH_KRYLOV_ITER = 1, HSM_PH_POST = 2, HSM_PH_KRYLOV_TOTAL = 3, HSM_PH_COUNT = 4 };
 
 /*
  * hsm_sim_phase_times -- in profile mode, mean device time (ms) of: the
  * pre-Krylov phase of a step (predictor, pressure right-hand side, initial
  * residual); one BiCGSTAB iteration (its two kernels), from the batches in
  * which every iteration did work (batch time / batch size); the post-Krylov
- * phase (projection, heat, walls).  host_count gets the number of steps,
- * iterations and steps behind each mean.  Both arrays [HSM_PH_COUNT], host.
+ * phase (projection, heat, walls); one Krylov batch, over every batch
+ * (including the last, partly idle one: with many domains, batch time
+ * against krylov_node_matvecs gives the work actually done).  host_count gets
+ * the number of steps, iterations, steps and batches behind each mean.  Both arrays [HSM_PH_COUNT], host.
  * Start/stop events bracket each graph launch on the stepper's stream.
  * Synchronises.  HSM_E_INVALID unless created with profile = 1.
  */

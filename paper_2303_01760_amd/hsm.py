@@ -49,7 +49,8 @@ class SimParamsC(ctypes.Structure):
 class SimStatsC(ctypes.Structure):
     _fields_ = [("steps", ctypes.c_int64), ("krylov_iters_total", ctypes.c_int64),
                 ("krylov_iters_last", ctypes.c_int32), ("status", ctypes.c_int32),
-                ("last_relres", ctypes.c_double), ("node_applies", ctypes.c_int64)]
+                ("last_relres", ctypes.c_double), ("node_applies", ctypes.c_int64),
+                ("krylov_node_matvecs", ctypes.c_int64)]
 
 
 _lib = None
@@ -59,7 +60,7 @@ SYMBOLS = ["hsm_build_stencils", "hsm_stencils_get_info", "hsm_stencils_export",
            "hsm_apply_operator", "hsm_apply_node_count", "hsm_sim_create", "hsm_step", "hsm_sim_get_stats",
            "hsm_sim_read", "hsm_sim_destroy", "hsm_stencils_destroy", "hsm_last_error", "hsm_last_error_node",
            "hsm_version", "hsm_sim_phase_times", "hsm_sim_sizes", "hsm_stream_copy"]
-PHASES = ["pre", "krylov_iter", "post"]
+PHASES = ["pre", "krylov_iter", "post", "krylov_batch"]
 
 
 def lib():
@@ -254,7 +255,8 @@ class Sim:
         o = SimStatsC()
         rc = lib().hsm_sim_get_stats(self._h, ctypes.byref(o))
         d = dict(steps=o.steps, krylov_iters_total=o.krylov_iters_total, krylov_iters_last=o.krylov_iters_last,
-                 status=o.status, last_relres=o.last_relres, node_applies=o.node_applies)
+                 status=o.status, last_relres=o.last_relres, node_applies=o.node_applies,
+                 krylov_node_matvecs=o.krylov_node_matvecs)
         if rc not in (OK, E_NONFINITE, E_NOT_CONVERGED):
             _check(rc)
         return d
