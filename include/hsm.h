@@ -141,6 +141,21 @@ hsm_status hsm_stencils_export(const hsm_stencils *st, uint8_t *host_class, int6
                                int32_t *host_idx, double *host_w, void *stream);
 
 /*
+ * hsm_stencils_condition -- the stability diagnostic of Section 2.2 (Fig. 2):
+ * for every node, the 2-norm condition number kappa(M) = |M|_2 |M^-1|_2 =
+ * sigma_max / sigma_min of the local system solved for its weights (the
+ * matrix is shared by every operator of the node): the RBF-FD matrix
+ * [[A, P], [P^T, 0]] at scattered nodes (monomials of degree m-1 at wall
+ * nodes that fell back), the MON matrix of the basis {1, x_a, x_a^2} on the
+ * axis cross at regular nodes, both in the local coordinates of the solve
+ * (centred at the node, scaled by its stencil radius).  Singular values by
+ * one-sided Jacobi.  kappa: device [N] doubles, caller order, written in
+ * full (+inf for a system with a zero singular value).  Asynchronous on
+ * `stream`.  Errors: HSM_E_INVALID, HSM_E_HIP.
+ */
+hsm_status hsm_stencils_condition(const hsm_stencils *st, double *kappa, void *stream);
+
+/*
  * hsm_permute -- move a field between the caller's node order and the
  * library's internal order (width buckets; spatially sorted inside each
  * bucket), in which hsm_apply_operator reads and writes fields.

@@ -441,26 +441,35 @@ void ora_apply(int64_t N, const int64_t *off, const int32_t *idx, const double *
 /* The pressure operator: row i holds the Laplacian weights at interior nodes
  * and the normal-derivative weights at boundary nodes (dp/dn = 0 on no-slip
  * walls), each row divided by its centre weight.  Each domain k's zero-mean
- * condition is added as a border row and column (its multiplier lam_k at
- * unknown N + k):  sum_j a_ij p_j + lam_dom(i) = b_i,  sum_{i in k} p_i = 0.
- * With one domain: [[A, 1], [1^T, 0]] [p; lam] = [b; 0]. */
+ * condition is added as a border row and column scaled by c_k = 1/sqrt(N_k),
+ * N_k the domain's node count (its multiplier lam_k at unknown N + k):
+ *   sum_j a_ij p_j + c_k lam_k = b_i (i in k),   c_k sum_{i in k} p_i = 0.
+ * With one domain: [[A, c 1], [c 1^T, 0]] [p; lam] = [b; 0].  The scale
+ * leaves the constraint and p unchanged; it moves the eigenvalue pair that a
+ * border of ones adds near +-sqrt(N_k) to near +-1 (reading R11). */
 typedef struct {
   int64_t N, K;
   const int64_t *off;
   const int32_t *idx;
   const int32_t *dom; /* domain of each node */
   double *a;          /* scaled row weights, CSR */
+  double *c;          /* [K] border scale 1/sqrt(N_k) */
 } pop_t;
+
+static double border_scale(const int64_t *dom_off, int64_t k) {
+  return 1.0 / sqrt((double)(dom_off[k + 1] - dom_off[k]));
+}
 
 static void pop_matvec(const pop_t *P, const double *v, double *out) {
   const int64_t N = P->N;
   for (int64_t i = 0; i < N; ++i) {
     double acc = 0.0;
     for (int64_t t = P->off[i]; t < P->off[i + 1]; ++t) acc = acc + P->a[t] * v[P->idx[t]];
-    out[i] = acc + v[N + P->dom[i]];
+    out[i] = acc + P->c[P->dom[i]] * v[N + P->dom[i]];
   }
   for (int64_t k = 0; k < P->K; ++k) out[N + k] = 0.0;
   for (int64_t i = 0; i < N; ++i) out[N + P->dom[i]] = out[N + P->dom[i]] + v[i];
+  for (int64_t k = 0; k < P->K; ++k) out[N + k] = P->c[k] * out[N + k];
 }
 
 static double dot(int64_t n, const double *a, const double *b) {
@@ -531,14 +540,16 @@ int ora_pressure_dense(int64_t N, const int64_t *off, const int32_t *idx, const 
                        const double *wn, const uint8_t *kind, int32_t K, const int64_t *dom_off, double *M) {
   const int64_t n = N + K;
   memset(M, 0, sizeof(double) * n * n);
-  for (int64_t k = 0; k < K; ++k)
+  for (int64_t k = 0; k < K; ++k) {
+    const double c = border_scale(dom_off, k);
     for (int64_t i = dom_off[k]; i < dom_off[k + 1]; ++i) {
       const double *wr = kind[i] ? wn : wlap;
       double dg = wr[off[i]];
       for (int64_t t = off[i]; t < off[i + 1]; ++t) M[i * n + idx[t]] += wr[t] / dg;
-      M[i * n + N + k] = 1.0;
-      M[(N + k) * n + i] = 1.0;
+      M[i * n + N + k] = c;
+      M[(N + k) * n + i] = c;
     }
+  }
   return ORA_OK;
 }
 
@@ -595,6 +606,8 @@ void *ora_sim_create(int d, int64_t N, const int64_t *off, const int32_t *idx, c
   int64_t nnz = off[N];
   S->P.N = N; S->P.K = K; S->P.off = off; S->P.idx = idx; S->P.dom = S->dom;
   S->P.a = malloc(sizeof(double) * (nnz > 0 ? nnz : 1));
+  S->P.c = malloc(sizeof(double) * K);
+  for (int64_t k = 0; k < K; ++k) S->P.c[k] = border_scale(dom_off, k);
   for (int64_t i = 0; i < N; ++i) {
     const double *wr = kind[i] ? wn : wop[d];
     double dg = wr[off[i]];
@@ -637,7 +650,7 @@ void *ora_sim_create(int d, int64_t N, const int64_t *off, const int32_t *idx, c
 void ora_sim_destroy(void *h) {
   ora_sim *S = (ora_sim *)h;
   if (!S) return;
-  free(S->P.a); free(S->vs); free(S->g0); free(S->g1); free(S->g2); free(S->rhs); free(S->Tn); free(S->dom);
+  free(S->P.a); free(S->P.c); free(S->vs); free(S->g0); free(S->g1); free(S->g2); free(S->rhs); free(S->Tn); free(S->dom);
   free(S->dense); free(S->dpiv);
   free(S);
 }

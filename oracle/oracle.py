@@ -208,6 +208,59 @@ def build(x, kind, normal, h, m, mode=HYBRID, dom_off=None, queries=None, n=None
     return dict(cls=cls, width=width, idx=idx, w=w, wn=wn, d=d)
 
 
+def local_matrix(xs, m=None):
+    """The matrix M of a node's local system M w = l (Section 2.2) for stencil
+    positions xs [n, d], centre first, in the solve's local coordinates
+    y = (x - x_c) / s, s = max_j |x_j - x_c| (reading R5).  m=None: the MON
+    matrix of a regular node (rows: the basis 1, y_a, y_a^2; columns: the
+    cross nodes).  Otherwise the RBF-FD matrix [[A, P], [P^T, 0]] with
+    A_jl = |y_j - y_l|^3 and P_ja = y_j^alpha for every monomial of degree
+    <= m."""
+    xs = np.asarray(xs, np.float64)
+    n, d = xs.shape
+    y = xs - xs[0]
+    s = np.sqrt((y * y).sum(axis=1)).max()
+    y = y / s
+    if m is None:
+        return np.vstack([np.ones(n), y.T, (y * y).T])
+    al = monomials(d, m)
+    P = np.stack([np.prod(y ** a, axis=1) for a in al], axis=1)
+    A = np.sqrt(((y[:, None, :] - y[None, :, :]) ** 2).sum(axis=2)) ** 3
+    Q = P.shape[1]
+    return np.block([[A, P], [P.T, np.zeros((Q, Q))]])
+
+
+def condition(x, kind, normal, h, m, mode=HYBRID, dom_off=None, queries=None, n=None):
+    """kappa(M) = |M|_2 |M^-1|_2 = sigma_max / sigma_min of each query node's
+    local system (Section 2.2, Fig. 2), singular values by LAPACK.  The system
+    is the one solved for the node's weights: MON at regular nodes, RBF-FD at
+    scattered ones, with degree m-1 at a wall node whose degree-m system is
+    singular (reading R17)."""
+    x = np.asarray(x, np.float64)
+    d, N = x.shape
+    st = build(x, kind, normal, h, m, mode=mode, dom_off=dom_off, queries=queries, n=n)
+    q = np.arange(N) if queries is None else np.asarray(queries, np.int64)
+    off = np.asarray(dom_off if dom_off is not None else [0, N], np.int64)
+    md = np.broadcast_to(np.asarray(m, np.int64), (len(off) - 1,))
+    kappa = np.empty(len(q))
+    for k, i in enumerate(q):
+        xs = x[:, st["idx"][k, :st["width"][k]]].T
+        if st["cls"][k] == 0:
+            M = local_matrix(xs)
+        else:
+            mm = int(md[np.searchsorted(off, i, side="right") - 1])
+            try:
+                rbffd(xs, mm)
+            except OracleError as e:
+                if e.code != E_SINGULAR or kind[i] == 0 or mm < 2:
+                    raise
+                mm -= 1
+            M = local_matrix(xs, mm)
+        sv = np.linalg.svd(M, compute_uv=False)
+        kappa[k] = sv[0] / sv[-1] if sv[-1] > 0 else np.inf
+    return kappa
+
+
 def to_csr(st):
     """Padded per-node stencils -> CSR (off, idx, w[d+1], wn)."""
     width = st["width"].astype(np.int64)

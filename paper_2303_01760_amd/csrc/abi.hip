@@ -238,6 +238,24 @@ int64_t hsm_apply_node_count(const hsm_stencils *st, uint32_t op_mask) {
   return total;
 }
 
+hsm_status hsm_stencils_condition(const hsm_stencils *st, double *kappa, void *stream) {
+  if (!check_ptr(st, "stencils")) return HSM_E_INVALID;
+  if (st->N == 0) return HSM_OK;
+  if (!check_ptr(kappa, "kappa")) return HSM_E_INVALID;
+  hipStream_t s = (hipStream_t)stream;
+  hsm_status rc;
+  for (const Bucket &B : st->buckets)
+    if ((rc = cond_bucket(st, B, kappa, s, nullptr, 0))) return rc;
+  if (st->n_wall_fallback > 0) {
+    // the wall nodes that were solved with degree m-1: their own system
+    const int32_t *list = st->fallback.as<int32_t>() + 1;
+    for (const Bucket &B : st->buckets)
+      if (B.type == B_DIR || B.type == B_NEU)
+        if ((rc = cond_bucket(st, B, kappa, s, list, st->n_wall_fallback))) return rc;
+  }
+  return HSM_OK;
+}
+
 void hsm_stencils_destroy(hsm_stencils *st) { delete st; }
 
 }  // extern "C"

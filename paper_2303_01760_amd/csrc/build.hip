@@ -655,6 +655,7 @@ hsm_status build_stencils_impl(const hsm_nodeset *ns, int32_t mode, hipStream_t 
       HSM_HIP(hipMemcpyAsync(&hs, d_status.p, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
     }
     st->n_wall_fallback = nretry;
+    st->fallback = std::move(d_retry);   // kept for the condition-number diagnostic
   }
   HSM_HIP(hipEventRecord(ev[3], s));
   HSM_HIP(hipStreamSynchronize(s));

@@ -107,6 +107,7 @@ struct hsm_stencils {
   std::vector<int64_t> dom_off;   // [n_domains + 1] domain ranges, caller numbering (host)
   int64_t N = 0, nnz = 0, n_regular = 0, n_scattered = 0, n_boundary = 0;
   int64_t n_wall_fallback = 0;   // wall nodes solved with monomials of degree m-1
+  hsm::DBuf fallback;            // int32 [1 + n_wall_fallback]: the count, then those nodes (internal numbering)
   std::vector<hsm::Bucket> buckets;
   hsm::DBuf perm;        // int32 [N] internal -> caller
   hsm::DBuf iperm;       // int32 [N] caller -> internal
@@ -343,6 +344,8 @@ hsm_status solve_bucket(const hsm_stencils *st, const Bucket &b, const double *x
 hsm_status solve_bucket_list(const hsm_stencils *st, const Bucket &b, const double *x_int,
                              const double *normal_int, DevStatus *status, hipStream_t s, const int32_t *list,
                              int64_t nlist);
+hsm_status cond_bucket(const hsm_stencils *st, const Bucket &b, double *kappa, hipStream_t s, const int32_t *list,
+                       int64_t nlist);
 hsm_status apply_impl(const hsm_stencils *st, uint32_t op_mask, int32_t dtype, const void *u, void *out,
                       hipStream_t s);
 hsm_status ensure_w32(const hsm_stencils *st, hipStream_t s);

@@ -59,6 +59,7 @@ struct hsm_sim {
   DBuf blk, dom_blk_off, dom_blk;   // block descriptors; per-domain block lists
   DBuf dom;                          // per-domain Krylov state [K]
   DBuf dom_nodes;                    // int64 [K] nodes per domain
+  DBuf bscale;                       // double [K] border scale 1/sqrt(nodes) per domain
   DBuf active;                       // int32 [nblk] blocks of unfinished domains
   int64_t kry_grid = 0;              // grid of the Krylov node kernels
   bool f32 = false;           // FP32 field form (HSM_F32_COMP)
@@ -94,6 +95,7 @@ SimArgs make_args(hsm_sim *m, int par, int kpar) {
   a.dom_blk = m->dom_blk.as<int32_t>();
   a.dom = m->dom.as<DomState>();
   a.dom_nodes = m->dom_nodes.as<int64_t>();
+  a.bscale = m->bscale.as<double>();
   a.active = m->active.as<int32_t>();
   a.N = m->N;
   a.dt = m->prm.dt; a.Ra = m->prm.Ra; a.Pr = m->prm.Pr; a.T_ref = m->prm.T_ref; a.tol = m->prm.krylov_tol;
@@ -457,12 +459,22 @@ hsm_status hsm_sim_create(const hsm_stencils *st, const hsm_sim_params *prm, con
     m->kry_grid = std::max<int64_t>(1, std::min(m->nblk, res));
   }
   if ((rc = m->active.alloc(sizeof(int32_t) * (m->nblk + 1)))) return rc;
-  if ((rc = m->dom.alloc(sizeof(DomState) * m->K)) || (rc = m->dom_nodes.alloc(sizeof(int64_t) * m->K))) return rc;
+  if ((rc = m->dom.alloc(sizeof(DomState) * m->K)) || (rc = m->dom_nodes.alloc(sizeof(int64_t) * m->K)) ||
+      (rc = m->bscale.alloc(sizeof(double) * m->K)))
+    return rc;
   HSM_HIP(hipMemsetAsync(m->dom.p, 0, sizeof(DomState) * m->K, us));
   {
+    // the zero-mean border of domain k holds c_k = 1/sqrt(N_k): the same
+    // constraint as a border of ones, with the border's eigenvalue pair at
+    // +-1 instead of +-sqrt(N_k)
     std::vector<int64_t> dn(m->K);
-    for (int32_t d2 = 0; d2 < m->K; ++d2) dn[d2] = st->dom_off[d2 + 1] - st->dom_off[d2];
+    std::vector<double> bs(m->K);
+    for (int32_t d2 = 0; d2 < m->K; ++d2) {
+      dn[d2] = st->dom_off[d2 + 1] - st->dom_off[d2];
+      bs[d2] = 1.0 / std::sqrt((double)dn[d2]);
+    }
     HSM_HIP(hipMemcpyAsync(m->dom_nodes.p, dn.data(), sizeof(int64_t) * m->K, hipMemcpyHostToDevice, us));
+    HSM_HIP(hipMemcpyAsync(m->bscale.p, bs.data(), sizeof(double) * m->K, hipMemcpyHostToDevice, us));
     HSM_HIP(hipStreamSynchronize(us));
   }
   if ((rc = m->partR.alloc(sizeof(double) * kNR * (m->nblk + 1))) ||

@@ -79,6 +79,7 @@ struct SimArgs {
   const int32_t *dom_blk_off;      // [K+1] per-domain ranges of dom_blk
   const int32_t *dom_blk;          // the blocks of each domain, ascending
   const int64_t *dom_nodes;        // [K] nodes per domain
+  const double *bscale;            // [K] c_k = 1/sqrt(nodes of domain k): domain k's border row and column hold c_k
   int32_t *active;                 // [nblk] blocks of unfinished domains (per-domain path), rebuilt as domains finish
   double dt, Ra, Pr, T_ref, tol;
   int32_t maxiter, chunk;
@@ -394,7 +395,7 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_r(SimArgs a) {
   domain_sums<kNR>(a, a.partR, rs, d < a.K, tot);
   if (rs.lead) {
     DomState &ds = a.dom[d];
-    const double r = -tot[2];
+    const double r = -(a.bscale[d] * tot[2]);
     a.RV[N + d] = make_double2(r, 0.0);
     a.rh[N + d] = r;
     const double rr = fma(r, r, tot[1]);
@@ -436,8 +437,10 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_a(SimArgs a, int it) {
   double alpha_p = 0.0, omega = 0.0, beta = 0.0, bnorm2 = 0.0, rho = 0.0, xb = 0.0, rhb = 0.0;
   double2 rvb = make_double2(0.0, 0.0), stb = rvb, pvb = rvb;
   int64_t nodes = 0;
+  double cb = 0.0;
   if (rs.lead && live) {
     const DomState &ds = a.dom[d];
+    cb = a.bscale[d];
     alpha_p = ds.alpha[par ^ 1]; omega = ds.omega[par]; beta = ds.beta[par];
     bnorm2 = ds.bnorm2; rho = ds.rho[par];
     xb = a.x[N + d]; rhb = a.rh[N + d];
@@ -468,7 +471,7 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_a(SimArgs a, int it) {
           r = fma(-omega, stb.y, stb.x);
           p = fma(beta, fma(-omega, pvb.y, pvb.x), r);
         }
-        const double vb = tot[1];               // border row of v = A p': sum of p' over the domain
+        const double vb = cb * tot[1];          // border row of v = A p': c_d sum of p' over the domain
         a.PVn[N + d] = make_double2(p, vb);
         a.RV[N + d] = make_double2(r, vb);
         const double rv = fma(rhb, vb, tot[0]);
@@ -502,10 +505,11 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_b(SimArgs a, int it) {
   const int d = rs.d;
   const bool live = d < a.K && !a.dom[d].done;
   // the lead's border rows and scalars, loaded while the partials are summed
-  double alpha = 0.0, rho = 0.0, bnorm2 = 0.0, rhb = 0.0;
+  double alpha = 0.0, rho = 0.0, bnorm2 = 0.0, rhb = 0.0, cb = 0.0;
   double2 rv = make_double2(0.0, 0.0);
   if (rs.lead && live) {
     const DomState &ds = a.dom[d];
+    cb = a.bscale[d];
     alpha = ds.alpha[par]; rho = ds.rho[par]; bnorm2 = ds.bnorm2;
     rv = a.RV[N + d];
     rhb = a.rh[N + d];
@@ -514,7 +518,7 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_b(SimArgs a, int it) {
   domain_sums<kNB>(a, a.partB, rs, live, tot);
   if (!(rs.lead && live)) return;
   DomState &ds = a.dom[d];
-  const double sb = fma(-alpha, rv.y, rv.x), tb = tot[5];
+  const double sb = fma(-alpha, rv.y, rv.x), tb = cb * tot[5];   // border row of t = A s: c_d sum s
   a.ST[N + d] = make_double2(sb, tb);
   const double ts = fma(tb, sb, tot[0]), tt = fma(tb, tb, tot[1]);
   const double rhs_ = fma(rhb, sb, tot[2]), rht = fma(rhb, tb, tot[3]);
@@ -626,7 +630,7 @@ __global__ __launch_bounds__(kBS) void k_rhs(SimArgs a) {
   const bool live = (int)threadIdx.x < b.nodes;
   double part[kNR] = {0.0, 0.0, 0.0};  // b.b, r.r, sum x
   const int64_t N = a.N;
-  const double lam = a.x[N + b.domain];        // this domain's border multiplier
+  const double lam = a.bscale[b.domain] * a.x[N + b.domain];   // c_d times this domain's border multiplier
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     Scalars *sc = a.sc;
     sc->done = 0; sc->fail = 0; sc->zero_sol = 0; sc->it_base = 0; sc->iters = 0; sc->node_mv = 0.0;
@@ -701,10 +705,10 @@ __global__ __launch_bounds__(kBS) void k_rhs(SimArgs a) {
 // Vectors gathered together are stored as pairs, one 16-byte load per
 // neighbour: (s, t), (p, v) (two generations) and (r, v).  The border row
 // and column (zero mean, multiplier) are slot N of every vector.
-// The node rows of one block of k_bicg_pv.
+// The node rows of one block of k_bicg_pv (cpN: c_d times the border entry of p').
 template <int D>
 __device__ __forceinline__ void pv_rows(const SimArgs &a, const BlockDesc &b, bool again, bool first,
-                                        int early, double omega, double beta, double alpha_p, double pN) {
+                                        int early, double omega, double beta, double alpha_p, double cpN) {
   const int64_t N = a.N;
   const double2 *__restrict__ ST = a.ST;
   const double2 *__restrict__ PVo = a.PVo;
@@ -755,7 +759,7 @@ __device__ __forceinline__ void pv_rows(const SimArgs &a, const BlockDesc &b, bo
             [&]() __attribute__((always_inline)) { pin(acc); });
       }
     });
-    const double vi = acc + pN;
+    const double vi = acc + cpN;                // + c_d times the border entry of p'
     a.PVn[i] = make_double2(pi, vi);
     a.RV[i] = make_double2(ri, vi);
     part[0] = a.rh[i] * vi;
@@ -790,14 +794,14 @@ __global__ __launch_bounds__(kBS) void k_bicg_pv(SimArgs a, int it) {
       const int64_t NB = N + b.domain;
       if (ds.done) continue;
       if (first) {
-        pv_rows<D>(a, b, true, true, 0, 0.0, 0.0, 0.0, a.RV[NB].x);   // p0 = r0 on the border row
+        pv_rows<D>(a, b, true, true, 0, 0.0, 0.0, 0.0, a.bscale[b.domain] * a.RV[NB].x);   // p0 = r0 on the border row
       } else {
         const int early = ds.early[par];
         if (early == 2) continue;
         const double omega = ds.omega[par], beta = ds.beta[par];
         const double2 stb = ST[NB], pvb = PVo[NB];  // the border row, as k_reduce_a will store it
         const double pN = fma(beta, fma(-omega, pvb.y, pvb.x), fma(-omega, stb.y, stb.x));
-        pv_rows<D>(a, b, true, false, early, omega, beta, ds.alpha[par ^ 1], pN);
+        pv_rows<D>(a, b, true, false, early, omega, beta, ds.alpha[par ^ 1], a.bscale[b.domain] * pN);
       }
     }
     return;
@@ -809,7 +813,7 @@ __global__ __launch_bounds__(kBS) void k_bicg_pv(SimArgs a, int it) {
   if (first) {
     double tot[kNR];
     reduce_prev<kNR>(a.partR, gridDim.x, tot);
-    const double rN = -tot[2];                  // border row of r0: 0 - sum x
+    const double rN = -(a.bscale[0] * tot[2]);  // border row of r0: 0 - c sum x
     const double rho_k = fma(rN, rN, tot[1]);   // (rh, r0) = |r0|^2
     pN = rN;
     if (tot[0] == 0.0) early = 3;
@@ -828,7 +832,7 @@ __global__ __launch_bounds__(kBS) void k_bicg_pv(SimArgs a, int it) {
     const double bn = sqrt(bnorm2);
     const double sN = ST[N].x, rhN = a.rh[N];
     const double2 pvN = PVo[N];
-    const double tN = tot[5];                   // border row of t = A s: sum s
+    const double tN = a.bscale[0] * tot[5];     // border row of t = A s: c sum s
     const double ts = fma(tN, sN, tot[0]), tt = fma(tN, tN, tot[1]);
     const double rhs_ = fma(rhN, sN, tot[2]), rht = fma(rhN, tN, tot[3]);
     const double ss = fma(sN, sN, tot[4]);
@@ -859,13 +863,13 @@ __global__ __launch_bounds__(kBS) void k_bicg_pv(SimArgs a, int it) {
     }
     if (early == 2) return;
   }
-  pv_rows<D>(a, b, false, first, early, omega, beta, alpha_p, pN);
+  pv_rows<D>(a, b, false, first, early, omega, beta, alpha_p, a.bscale[0] * pN);
 }
 
-// The node rows of one block of k_bicg_st.
+// The node rows of one block of k_bicg_st (csN: c_d times the border entry of s).
 template <int D>
 __device__ __forceinline__ void st_rows(const SimArgs &a, const BlockDesc &b, bool again, double alpha,
-                                        double sN) {
+                                        double csN) {
   const int64_t N = a.N;
   const int64_t t = b.first + (int64_t)threadIdx.x;
   const bool live = (int)threadIdx.x < b.nodes;
@@ -888,7 +892,7 @@ __device__ __forceinline__ void st_rows(const SimArgs &a, const BlockDesc &b, bo
     });
     const double2 rvi = RV[i];
     const double si = fma(-alpha, rvi.y, rvi.x);
-    const double ti = acc + sN;
+    const double ti = acc + csN;                // + c_d times the border entry of s
     const double rhi = a.rh[i];
     a.ST[i] = make_double2(si, ti);
     part[0] = ti * si;
@@ -920,7 +924,7 @@ __global__ __launch_bounds__(kBS) void k_bicg_st(SimArgs a, int it) {
       if (ds.done) continue;
       const double alpha = ds.alpha[par];
       const double2 rvb = a.RV[N + b.domain];   // the border row, as k_reduce_b will store it
-      st_rows<D>(a, b, true, alpha, fma(-alpha, rvb.y, rvb.x));
+      st_rows<D>(a, b, true, alpha, a.bscale[b.domain] * fma(-alpha, rvb.y, rvb.x));
     }
     return;
   }
@@ -937,7 +941,7 @@ __global__ __launch_bounds__(kBS) void k_bicg_st(SimArgs a, int it) {
   double tot[kNA];
   reduce_prev<kNA>(a.partA, gridDim.x, tot);
   const double bn = sqrt(bnorm2);
-  const double vN = tot[1];                     // border row of v = A p: sum p
+  const double vN = a.bscale[0] * tot[1];       // border row of v = A p: c sum p
   const double rN = a.RV[N].x;
   const double rv = fma(a.rh[N], vN, tot[0]);
   const double rr = fma(rN, rN, tot[2]);
@@ -962,7 +966,7 @@ __global__ __launch_bounds__(kBS) void k_bicg_st(SimArgs a, int it) {
     }
   }
   if (stop) return;
-  st_rows<D>(a, b, false, alpha, sN);
+  st_rows<D>(a, b, false, alpha, a.bscale[0] * sN);
 }
 
 // End of a batch of iterations (one block of kRedThreads).  With several

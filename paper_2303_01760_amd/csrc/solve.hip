@@ -19,6 +19,8 @@
 // rounded as written and the pivoting decisions are reproducible.
 #include <hip/hip_runtime.h>
 
+#include <cstring>
+
 #include "hsm_internal.h"
 
 namespace hsm {
@@ -74,28 +76,27 @@ struct SolveArgs {
   int32_t *retry;         // non-NULL: list singular nodes here (internal numbering) instead of failing
   int32_t *nretry;        // length of that list
   const int32_t *list;    // non-NULL: block b solves internal node list[b] (if it is in this bucket)
+  double *kappa;          // condition-number kernels: [N] caller order
 };
 
+// Row `lane` of the RBF-FD system of node t (Section 2.1): M = [[A, P],
+// [P^T, 0]] and the right-hand sides of d/dx_a and the Laplacian, in local
+// coordinates y_j = (x_j - x_c) / s; returns the centre c and the scale s.
+// M is symmetric, so the row is also column `lane`.
 template <int D, int M, int NS>
-__global__ __launch_bounds__(64) void k_rbffd(SolveArgs a) {
-  constexpr Monos<D, M> mono{};
+__device__ __forceinline__ void rbffd_rows(const SolveArgs &a, int64_t t, int lane,
+                                           double (&Rw)[NS + Monos<D, M>::Q], double (&B)[D + 1], int32_t &c,
+                                           double &s) {
   constexpr int Q = Monos<D, M>::Q;
   constexpr int S = NS + Q;
   constexpr int R = D + 1;
-  static_assert(S <= 64, "one system row per lane");
-  const int lane = threadIdx.x;
-  int64_t t = blockIdx.x;
-  if (a.list) {
-    const int64_t g = a.list[blockIdx.x];
-    if (g < a.start || g >= a.start + a.count) return;
-    t = g - a.start;
-  }
   const int64_t cnt = a.count, N = a.N;
+  constexpr Monos<D, M> mono{};
   __shared__ double sy[NS][D];
   __shared__ double smono[NS][Q];
 
   // local coordinates y_j = (x_j - x_c) / s, s = max_j |x_j - x_c|
-  const int32_t c = a.idx[t];
+  c = a.idx[t];
   double dxv[D], r = 0.0;
 #pragma unroll
   for (int q = 0; q < D; ++q) dxv[q] = 0.0;
@@ -110,7 +111,7 @@ __global__ __launch_bounds__(64) void k_rbffd(SolveArgs a) {
     }
     r = sqrt(sq);
   }
-  const double s = wave_max(r);
+  s = wave_max(r);
   double y[D];
 #pragma unroll
   for (int q = 0; q < D; ++q) y[q] = dxv[q] / s;
@@ -130,7 +131,6 @@ __global__ __launch_bounds__(64) void k_rbffd(SolveArgs a) {
   __syncthreads();
 
   // this lane's row of M and of the right-hand sides
-  double Rw[S], B[R];
 #pragma unroll
   for (int k = 0; k < S; ++k) Rw[k] = 0.0;
 #pragma unroll
@@ -174,6 +174,27 @@ __global__ __launch_bounds__(64) void k_rbffd(SolveArgs a) {
       }
     }
   }
+
+}
+
+template <int D, int M, int NS>
+__global__ __launch_bounds__(64) void k_rbffd(SolveArgs a) {
+  constexpr int Q = Monos<D, M>::Q;
+  constexpr int S = NS + Q;
+  constexpr int R = D + 1;
+  static_assert(S <= 64, "one system row per lane");
+  const int lane = threadIdx.x;
+  int64_t t = blockIdx.x;
+  if (a.list) {
+    const int64_t g = a.list[blockIdx.x];
+    if (g < a.start || g >= a.start + a.count) return;
+    t = g - a.start;
+  }
+  const int64_t cnt = a.count, N = a.N;
+  double Rw[S], B[R];
+  int32_t c;
+  double s;
+  rbffd_rows<D, M, NS>(a, t, lane, Rw, B, c, s);
 
   // elimination
   double amax = 0.0;
@@ -390,6 +411,140 @@ void launch_rbffd(const SolveArgs &a, hipStream_t s, int64_t nlist = -1) {
   hipLaunchKernelGGL((k_rbffd<D, M, NS>), dim3((unsigned)g), dim3(64), 0, s, a);
 }
 
+// ------------------------------------------------- condition numbers --
+// kappa(M) = |M|_2 |M^-1|_2 = sigma_max / sigma_min of a node's local system
+// (Section 2.2, Fig. 2).  The singular values come from one-sided Jacobi
+// (Hestenes 1958): plane rotations of column pairs until every pair is
+// orthogonal to working precision; the column norms are then the singular
+// values.  One wave per system, one column per lane; the S/2 disjoint pairs
+// of a round-robin round rotate at once, each lane fetching its partner's
+// column.  Both lanes of a pair form the same sums in the same order (lower
+// column first), so they take identical rotations.
+
+constexpr double kJacobiTol = 1e-15;   // rotate while |u.v| > tol |u| |v|
+constexpr int kJacobiSweeps = 40;
+
+__device__ __forceinline__ double wave_min(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// The singular value of this lane's column (lanes >= S hold zero columns).
+template <int S>
+__device__ __forceinline__ double jacobi_sv(double (&col)[S], int lane) {
+  constexpr int P = (S + 1) & ~1;      // players of the round-robin (even)
+  static_assert(P <= 64, "one column per lane");
+  for (int sweep = 0; sweep < kJacobiSweeps; ++sweep) {
+    bool rotated = false;
+    for (int r = 0; r < P - 1; ++r) {
+      int partner;
+      if (lane >= P) partner = lane;
+      else if (lane == P - 1) partner = r;
+      else if (lane == r) partner = P - 1;
+      else partner = (2 * r - lane + 2 * (P - 1)) % (P - 1);
+      double oth[S];
+#pragma unroll
+      for (int i = 0; i < S; ++i) oth[i] = __shfl(col[i], partner, 64);
+      const bool lo = lane < partner;
+      double a2 = 0.0, b2 = 0.0, g = 0.0;   // |u|^2, |v|^2, u.v with u the lower column
+#pragma unroll
+      for (int i = 0; i < S; ++i) {
+        const double u = lo ? col[i] : oth[i], v = lo ? oth[i] : col[i];
+        a2 = fma(u, u, a2);
+        b2 = fma(v, v, b2);
+        g = fma(u, v, g);
+      }
+      if (partner != lane && fabs(g) > kJacobiTol * sqrt(a2 * b2)) {
+        const double zeta = (b2 - a2) / (2.0 * g);
+        const double tn = copysign(1.0, zeta) / (fabs(zeta) + sqrt(fma(zeta, zeta, 1.0)));
+        const double cs = 1.0 / sqrt(fma(tn, tn, 1.0)), sn = cs * tn;
+#pragma unroll
+        for (int i = 0; i < S; ++i) {
+          const double u = lo ? col[i] : oth[i], v = lo ? oth[i] : col[i];
+          col[i] = lo ? cs * u - sn * v : sn * u + cs * v;
+        }
+        rotated = true;
+      }
+    }
+    if (!__any(rotated)) break;
+  }
+  double n2 = 0.0;
+#pragma unroll
+  for (int i = 0; i < S; ++i) n2 = fma(col[i], col[i], n2);
+  return sqrt(n2);
+}
+
+template <int S>
+__device__ __forceinline__ void store_kappa(const SolveArgs &a, int64_t t, int lane, double sv) {
+  const double smax = wave_max(lane < S ? sv : 0.0);
+  const double smin = wave_min(lane < S ? sv : INFINITY);
+  if (lane == 0) a.kappa[a.perm[a.start + t]] = smin > 0.0 ? smax / smin : INFINITY;
+}
+
+// RBF-FD system of a scattered node (M is symmetric: row = column).
+template <int D, int M, int NS>
+__global__ __launch_bounds__(64) void k_cond_rbffd(SolveArgs a) {
+  constexpr int S = NS + Monos<D, M>::Q;
+  static_assert(S <= 63, "one column per lane, plus a zero column when S is odd");
+  const int lane = threadIdx.x;
+  int64_t t = blockIdx.x;
+  if (a.list) {
+    const int64_t g = a.list[blockIdx.x];
+    if (g < a.start || g >= a.start + a.count) return;
+    t = g - a.start;
+  }
+  double Rw[S], B[D + 1];
+  int32_t c;
+  double s;
+  rbffd_rows<D, M, NS>(a, t, lane, Rw, B, c, s);
+  store_kappa<S>(a, t, lane, jacobi_sv<S>(Rw, lane));
+}
+
+// MON system of a regular node: column j holds the basis {1, y_a, y_a^2} at
+// cross node j, in the coordinates k_mon uses.
+template <int D>
+__global__ __launch_bounds__(64) void k_cond_mon(SolveArgs a) {
+  constexpr int S = 2 * D + 1;
+  const int lane = threadIdx.x;
+  const int64_t t = blockIdx.x, cnt = a.count, N = a.N;
+  const int32_t c = a.idx[t];
+  double dx[D], r = 0.0;
+#pragma unroll
+  for (int q = 0; q < D; ++q) dx[q] = 0.0;
+  if (lane < S) {
+    const int32_t nj = a.idx[(int64_t)lane * cnt + t];
+    double sq = 0.0;
+#pragma unroll
+    for (int q = 0; q < D; ++q) {
+      dx[q] = a.x[q * N + nj] - a.x[q * N + c];
+      const double v = dx[q] * dx[q];
+      sq = (q == 0) ? v : sq + v;
+    }
+    r = sqrt(sq);
+  }
+  const double s = wave_max(r);
+  double col[S];
+#pragma unroll
+  for (int i = 0; i < S; ++i) col[i] = 0.0;
+  if (lane < S) {
+    col[0] = 1.0;
+#pragma unroll
+    for (int q = 0; q < D; ++q) {
+      const double y = dx[q] / s;
+      col[1 + q] = y;
+      col[1 + D + q] = y * y;
+    }
+  }
+  store_kappa<S>(a, t, lane, jacobi_sv<S>(col, lane));
+}
+
+template <int D, int M, int NS>
+void launch_cond(const SolveArgs &a, hipStream_t s, int64_t nlist = -1) {
+  const int64_t g = nlist >= 0 ? nlist : a.count;
+  hipLaunchKernelGGL((k_cond_rbffd<D, M, NS>), dim3((unsigned)g), dim3(64), 0, s, a);
+}
+
 }  // namespace
 
 // (d, m, n) combinations with a compiled local-solve kernel
@@ -458,4 +613,44 @@ hsm_status solve_bucket_list(const hsm_stencils *st, const Bucket &b, const doub
   return HSM_OK;
 }
 
+
+// Condition numbers of every node of a bucket (the system solved for its
+// weights), written to kappa [N] in caller order.  With a list, only the
+// listed nodes of the bucket, with monomials of degree m-1 (the wall
+// fallback).
+hsm_status cond_bucket(const hsm_stencils *st, const Bucket &b, double *kappa, hipStream_t s, const int32_t *list,
+                       int64_t nlist) {
+  if (b.count == 0 || (list && nlist <= 0)) return HSM_OK;
+  SolveArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.x = st->x.as<double>(); a.normal = st->normal.as<double>(); a.N = st->N; a.idx = b.idx.as<int32_t>();
+  a.count = b.count; a.start = b.start; a.perm = st->perm.as<int32_t>(); a.list = list; a.kappa = kappa;
+  const int d = st->d, m = b.m, n = b.width;
+  const int64_t nl = list ? nlist : -1;
+  if (b.type == B_REG) {
+    if (list) return HSM_OK;
+    if (d == 2) hipLaunchKernelGGL(k_cond_mon<2>, dim3((unsigned)b.count), dim3(64), 0, s, a);
+    else hipLaunchKernelGGL(k_cond_mon<3>, dim3((unsigned)b.count), dim3(64), 0, s, a);
+  } else if (!list) {
+    if (d == 2 && m == 1 && n == 6) launch_cond<2, 1, 6>(a, s);
+    else if (d == 2 && m == 2 && n == 12) launch_cond<2, 2, 12>(a, s);
+    else if (d == 2 && m == 3 && n == 20) launch_cond<2, 3, 20>(a, s);
+    else if (d == 2 && m == 4 && n == 30) launch_cond<2, 4, 30>(a, s);
+    else if (d == 3 && m == 1 && n == 8) launch_cond<3, 1, 8>(a, s);
+    else if (d == 3 && m == 2 && n == 20) launch_cond<3, 2, 20>(a, s);
+    else if (d == 3 && m == 2 && n == 30) launch_cond<3, 2, 30>(a, s);
+    else if (d == 3 && m == 3 && n == 40) launch_cond<3, 3, 40>(a, s);
+    else { set_error(HSM_E_INVALID, "no condition-number kernel for this (d, m, n)"); return HSM_E_INVALID; }
+  } else {
+    if (d == 2 && m == 2 && n == 12) launch_cond<2, 1, 12>(a, s, nl);
+    else if (d == 2 && m == 3 && n == 20) launch_cond<2, 2, 20>(a, s, nl);
+    else if (d == 2 && m == 4 && n == 30) launch_cond<2, 3, 30>(a, s, nl);
+    else if (d == 3 && m == 2 && n == 20) launch_cond<3, 1, 20>(a, s, nl);
+    else if (d == 3 && m == 2 && n == 30) launch_cond<3, 1, 30>(a, s, nl);
+    else if (d == 3 && m == 3 && n == 40) launch_cond<3, 2, 40>(a, s, nl);
+    else { set_error(HSM_E_INVALID, "no reduced-degree condition-number kernel"); return HSM_E_INVALID; }
+  }
+  HSM_HIP(hipGetLastError());
+  return HSM_OK;
+}
 }  // namespace hsm

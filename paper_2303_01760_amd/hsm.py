@@ -59,7 +59,7 @@ _lib = None
 SYMBOLS = ["hsm_build_stencils", "hsm_stencils_get_info", "hsm_stencils_export", "hsm_permute",
            "hsm_apply_operator", "hsm_apply_node_count", "hsm_sim_create", "hsm_step", "hsm_sim_get_stats",
            "hsm_sim_read", "hsm_sim_destroy", "hsm_stencils_destroy", "hsm_last_error", "hsm_last_error_node",
-           "hsm_version", "hsm_sim_phase_times", "hsm_sim_sizes", "hsm_stream_copy"]
+           "hsm_version", "hsm_sim_phase_times", "hsm_sim_sizes", "hsm_stream_copy", "hsm_stencils_condition"]
 PHASES = ["pre", "krylov_iter", "post", "krylov_batch"]
 
 
@@ -105,6 +105,8 @@ def lib():
         L.hsm_sim_sizes.argtypes = [_p, _p]
         L.hsm_stream_copy.restype = st
         L.hsm_stream_copy.argtypes = [_p, _p, ctypes.c_int64, _p]
+        L.hsm_stencils_condition.restype = st
+        L.hsm_stencils_condition.argtypes = [_p, _p, _p]
         L.hsm_version.restype = ctypes.c_char_p
         L.hsm_version.argtypes = []
         _lib = L
@@ -188,6 +190,12 @@ class Stencils:
         if out is None:
             out = torch.empty((nops, self.n), dtype=tdt, device=u.device)
         apply_operator(self, op_mask, dtype, u, out, stream)
+        return out
+
+    def condition(self, stream=None) -> torch.Tensor:
+        """hsm_stencils_condition: kappa(M) of every node's local system, caller order."""
+        out = torch.empty(self.n, dtype=torch.float64, device=torch.device("cuda"))
+        _check(lib().hsm_stencils_condition(self._h, _dptr(out), _stream(stream)))
         return out
 
     def node_count(self, op_mask: int) -> int:

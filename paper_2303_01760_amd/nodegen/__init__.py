@@ -44,6 +44,7 @@ class _Params(ctypes.Structure):
         ("wall_kind", ctypes.c_int32 * 6), ("wall_T", ctypes.c_double * 6),
         ("obst_T", ctypes.c_double * 2), ("obst_kind", ctypes.c_int32),
         ("n_candidates", ctypes.c_int32), ("seed", ctypes.c_uint64),
+        ("quarters", ctypes.c_int32), ("pad", ctypes.c_int32),
     ]
 
 
@@ -87,7 +88,7 @@ class NodeSet:
 def generate(d: int, h: float, *, wall_band: float = 0.0, obst_band: float = 0.0,
              n_obst: int = 0, rmin: float = 0.0, rmax: float = 0.0, gap: float = 4.0,
              wall_kind=None, wall_T=None, obst_T=(0.0, 1.0), obst_kind: int = KIND_DIRICHLET,
-             n_candidates: int = 30, seed: int = SEED_BASE, name: str = "") -> NodeSet:
+             n_candidates: int = 30, quarters: bool = False, seed: int = SEED_BASE, name: str = "") -> NodeSet:
     lib = _load()
     p = _Params()
     p.d, p.n_obst, p.h = d, n_obst, h
@@ -99,6 +100,7 @@ def generate(d: int, h: float, *, wall_band: float = 0.0, obst_band: float = 0.0
         p.wall_T[i] = float(wt[i]) if i < len(wt) else 0.0
     p.obst_T[0], p.obst_T[1] = float(obst_T[0]), float(obst_T[1])
     p.obst_kind, p.n_candidates, p.seed = obst_kind, n_candidates, seed & 0xFFFFFFFFFFFFFFFF
+    p.quarters, p.pad = int(bool(quarters)), 0
     n = ctypes.c_int64(0)
     hnd = lib.ng_generate(ctypes.byref(p), ctypes.byref(n))
     if not hnd:
@@ -129,6 +131,23 @@ def cavity2d(h: float = 0.02, wall_band: float = 0.1, seed: int = SEED_BASE + 1,
     return generate(2, h, wall_band=wall_band,
                     wall_kind=[KIND_DIRICHLET, KIND_DIRICHLET, KIND_NEUMANN, KIND_NEUMANN],
                     wall_T=[T_hot, T_cold, 0.0, 0.0], seed=seed, name=f"cavity2d_h{h}")
+
+
+def dvd2d(h: float = 0.01, layout: str = "hybrid", seed: int = SEED_BASE + 6,
+          T_cold: float = -0.5, T_hot: float = 0.5) -> NodeSet:
+    """De Vahl Davis cavity (Section 4.1): left wall cold, right wall hot,
+    top/bottom adiabatic.  layout "hybrid": the quarters x<1/2,y<1/2 and
+    x>1/2,y>1/2 scattered, the other two a regular lattice; "regular": the
+    lattice everywhere; "scattered": Poisson-disk nodes everywhere."""
+    kinds = [KIND_DIRICHLET, KIND_DIRICHLET, KIND_NEUMANN, KIND_NEUMANN]
+    temps = [T_cold, T_hot, 0.0, 0.0]
+    if layout == "hybrid":
+        return generate(2, h, quarters=True, wall_kind=kinds, wall_T=temps, seed=seed, name=f"dvd_hybrid_h{h}")
+    if layout == "regular":
+        return generate(2, h, wall_kind=kinds, wall_T=temps, seed=seed, name=f"dvd_regular_h{h}")
+    if layout == "scattered":
+        return generate(2, h, wall_band=0.6, wall_kind=kinds, wall_T=temps, seed=seed, name=f"dvd_scattered_h{h}")
+    raise ValueError(f"unknown layout {layout!r}")
 
 
 def obstacles2d(h: float = 0.002, n_obst: int = 20, rmin: float = 0.02, rmax: float = 0.08,

@@ -38,6 +38,8 @@ typedef struct {
   int32_t obst_kind;     /* kind of obstacle boundary nodes (1 or 2) */
   int32_t n_candidates;  /* Poisson-disk candidates per active point (30) */
   uint64_t seed;
+  int32_t quarters;      /* 2D only, 1: the quarters x<1/2,y<1/2 and x>1/2,y>1/2 are scattered too */
+  int32_t pad;
 } ng_params;
 
 typedef struct {
@@ -169,9 +171,16 @@ static void free_set(ng_set *S) {
 }
 
 /* Returns an opaque set, or NULL on invalid parameters / allocation failure. */
+/* The two diagonal quarters of the unit square that the quarters layout
+ * fills with scattered nodes (points on the dividing lines stay regular). */
+static int in_quarters(const double *p) {
+  return (p[0] < 0.5 && p[1] < 0.5) || (p[0] > 0.5 && p[1] > 0.5);
+}
+
 void *ng_generate(const ng_params *P, int64_t *n_out) {
   *n_out = 0;
   if (!P || (P->d != 2 && P->d != 3) || !(P->h > 0) || P->h > 0.5 || P->n_obst < 0) return NULL;
+  if (P->quarters && P->d != 2) return NULL;
   const int d = P->d;
   const double h = P->h;
   const int nl = (int)llround(1.0 / h); /* lattice: i*h, i = 1 .. nl-1 interior */
@@ -271,8 +280,9 @@ void *ng_generate(const ng_params *P, int64_t *n_out) {
           int inband = 0;
           for (int a = 0; a < d; ++a)
             if (idx[a] < wall_band_i || idx[a] > nl - wall_band_i) inband = 1;
-          if (inband) continue;
           double p[3] = {i * h, j * h, k * h};
+          if (P->quarters && in_quarters(p)) inband = 1;
+          if (inband) continue;
           if (S->n_obst && dist_surface(S, p, NULL) < P->obst_band) continue;
           if (push(S, p, NULL, 0, 0.0, 0, -1)) { free_set(S); return NULL; }
         }
@@ -324,6 +334,7 @@ void *ng_generate(const ng_params *P, int64_t *n_out) {
       int inband = 0;
       for (int a = 0; a < d; ++a)
         if (p[a] < wb || p[a] > 1.0 - wb) inband = 1;
+      if (P->quarters && in_quarters(p)) inband = 1;
       if (S->n_obst) {
         double ds = dist_surface(S, p, NULL);
         if (ds <= 0.0) continue;              /* inside an obstacle */

@@ -275,3 +275,49 @@ def test_permute_roundtrip():
     ui = st.to_internal(u)
     assert sorted(ui.cpu().tolist()) == list(range(s.n))
     assert torch.equal(st.to_caller(ui), u)
+
+
+def _kappa_tol(k):
+    # both sides compute sigma_min to about eps * sigma_max: kappa to about kappa * eps
+    return 1e-10 + 1e3 * k * np.finfo(np.float64).eps
+
+
+@pytest.mark.parametrize("case", ["cavity_m2", "obstacles_m4", "cavity_all_scattered", "3d_m2"])
+def test_condition_numbers_match_oracle(case):
+    # Section 2.2 / Fig. 2: kappa(M) of every node's local system (MON at
+    # regular nodes, RBF-FD at scattered ones) against LAPACK's SVD of the
+    # oracle's matrices
+    hsm = _hsm()
+    mode = 0
+    if case == "cavity_m2":
+        s, m = ng.cavity2d(h=0.05), 2
+    elif case == "obstacles_m4":
+        s, m = ng.obstacles2d(h=0.02, n_obst=3, rmin=0.08, rmax=0.12, band=0.1, seed=41), 4
+    elif case == "cavity_all_scattered":
+        s, m, mode = ng.cavity2d(h=0.05), 2, 1
+    else:
+        s, m = ng.obstacles3d(h=0.1, n_obst=1, rmin=0.2, rmax=0.25, band=0.15, seed=43), 2
+    x, kind, nrm = _dev(s)
+    st = hsm.build_stencils(x, kind, nrm, s.h, m, mode=mode)
+    kg = st.condition().cpu().numpy()
+    ko = O.condition(s.x, s.kind, s.normal, s.h, m, mode=mode)
+    assert np.all(np.isfinite(ko))
+    err = np.abs(kg - ko) / ko
+    print(f"kappa {case}: N={s.n}, kappa range {ko.min():.3g}..{ko.max():.3g}, max rel err {err.max():.2e}")
+    assert np.all(err <= _kappa_tol(ko))
+
+
+def test_condition_numbers_of_wall_fallback_nodes():
+    # the 3D wall nodes that fall back to degree 1 report their own system's kappa
+    hsm = _hsm()
+    s = ng.obstacles3d(h=0.02)
+    x, kind, nrm = _dev(s)
+    st = hsm.build_stencils(x, kind, nrm, s.h, 2)
+    kg = st.condition().cpu().numpy()
+    rng = np.random.default_rng(29)
+    q = np.unique(np.concatenate([[467, 468, 515], rng.choice(s.n, 100, replace=False)]))
+    ko = O.condition(s.x, s.kind, s.normal, s.h, 2, queries=q)
+    assert np.all(np.isfinite(kg)) and np.all(np.isfinite(ko))
+    err = np.abs(kg[q] - ko) / ko
+    print(f"kappa 3D h=0.02 (fallback nodes included): max rel err {err.max():.2e}")
+    assert np.all(err <= _kappa_tol(ko))

@@ -1,0 +1,47 @@
+"""De Vahl Davis cavity in the quarters layout (Section 4.1) on the GPU:
+fields against the FP64 oracle after a short run, and the cold-wall Nusselt
+number (Eq. (5)) the validation driver computes against the oracle's, from the
+same fields."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2303_01760_amd import nodegen as ng
+
+pytestmark = pytest.mark.gpu
+
+FIELD_TOL = 1e-8
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.mark.parametrize("layout", ["hybrid", "scattered"])
+def test_dvd_steps_and_nusselt_match_oracle(layout):
+    from paper_2303_01760_amd import dvd, hsm
+    q = ng.dvd2d(0.05, layout)
+    dt = 0.1 * q.h ** 2 / 2
+    prm = dict(Ra=1e5, Pr=0.71, dt=dt, T_ref=0.0)
+    dev = torch.device("cuda")
+    st = hsm.build_stencils(torch.tensor(q.x, device=dev), torch.tensor(q.kind, device=dev),
+                            torch.tensor(q.normal, device=dev), q.h, 2)
+    v0 = np.zeros((2, q.n))
+    T0 = np.where(q.kind == ng.KIND_DIRICHLET, q.tbc, 0.0)
+    sim = hsm.Sim(st, torch.tensor(v0, device=dev), torch.tensor(T0, device=dev), krylov_tol=1e-12, **prm)
+    sim.step(40)
+    assert sim.stats()["status"] == 0
+    vg, Tg, pg = [a.cpu().numpy() for a in sim.read()]
+    csr = O.to_csr(O.build(q.x, q.kind, q.normal, q.h, 2))
+    vo, To, po = v0.copy(), T0.copy(), np.zeros(q.n + 1)
+    O.Sim(csr, q.kind, solver=1).step(vo, To, po, 40, **prm)
+    ev, eT, ep = _rel(vg, vo), _rel(Tg, To), _rel(pg, po[:q.n])
+    cold = dvd.cold_wall_nodes(q)
+    nu_g = dvd.nusselt(st, torch.tensor(Tg, device=dev), cold)
+    nu_o = O.nusselt(csr, To, cold)
+    print(f"dvd {layout}: N={q.n}, rel L2 err v {ev:.2e} T {eT:.2e} p {ep:.2e}; Nu gpu {nu_g:.12f} oracle {nu_o:.12f}")
+    assert ev <= FIELD_TOL and eT <= FIELD_TOL and ep <= FIELD_TOL
+    assert nu_g == pytest.approx(nu_o, rel=1e-9)
+    # heat flows in through the hot wall and out through the cold one: Nu above conduction's 1 once convection starts
+    assert nu_o > 1.0

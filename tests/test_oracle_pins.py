@@ -406,15 +406,26 @@ def test_bicgstab_pressure_matches_dense_solve():
 
 def test_pressure_system_is_the_bordered_neumann_problem():
     # Dense pressure matrix: rows scaled to unit centre weight, constants in the
-    # null space of the unbordered block, border of ones.
+    # null space of the unbordered block, a border of c = 1/sqrt(N) (reading R11).
     s, csr = _cavity_setup()
     N = s.n
     M = O.pressure_dense(csr, s.kind)
+    c = 1.0 / np.sqrt(N)
     np.testing.assert_allclose(np.diag(M)[:N], 1.0, rtol=1e-12)
     assert np.abs(M[:N, :N].sum(1)).max() < 1e-9
-    assert np.all(M[:N, N] == 1) and np.all(M[N, :N] == 1) and M[N, N] == 0
+    assert np.all(M[:N, N] == c) and np.all(M[N, :N] == c) and M[N, N] == 0
     # and it is nonsingular
     assert np.linalg.matrix_rank(M) == N + 1
+    # the scale changes neither the constraint nor p: the border of ones gives
+    # the same p, with multiplier c lam
+    M1 = M.copy()
+    M1[:N, N] = 1.0
+    M1[N, :N] = 1.0
+    b = np.concatenate([np.random.default_rng(3).standard_normal(N), [0.0]])
+    x, x1 = np.linalg.solve(M, b), np.linalg.solve(M1, b)
+    assert np.abs(x[:N] - x1[:N]).max() <= 1e-9 * np.abs(x1[:N]).max()
+    assert x1[N] == pytest.approx(c * x[N], rel=1e-9)
+    assert abs(x[:N].sum()) <= 1e-9 * np.abs(x[:N]).sum()
 
 
 def test_projection_reduces_divergence():
@@ -566,9 +577,11 @@ def test_multi_domain_pressure_system_has_one_border_per_domain():
     assert M.shape == (N + K, N + K)
     for k in range(K):
         rows = np.arange(off[k], off[k + 1])
-        # the border column of domain k is 1 exactly on its rows, its border row sums its nodes
-        np.testing.assert_array_equal(M[:N, N + k], np.isin(np.arange(N), rows).astype(float))
-        np.testing.assert_array_equal(M[N + k, :N], np.isin(np.arange(N), rows).astype(float))
+        # the border column of domain k is c_k = 1/sqrt(N_k) exactly on its rows, its border
+        # row sums its nodes (times c_k)
+        ck = 1.0 / np.sqrt(len(rows))
+        np.testing.assert_array_equal(M[:N, N + k], ck * np.isin(np.arange(N), rows))
+        np.testing.assert_array_equal(M[N + k, :N], ck * np.isin(np.arange(N), rows))
         # no coupling between domains
         others = np.setdiff1d(np.arange(N), rows)
         assert not M[np.ix_(rows, others)].any()
@@ -602,3 +615,104 @@ def test_multi_domain_step_equals_independent_domains():
             for got, want in ((vm[:, a:b], v), (Tm[a:b], T), (pm[a:b], p[:-1])):
                 assert np.abs(got - want).max() <= tol * max(np.abs(want).max(), 1e-30)
             assert abs(pm[N + k] - p[-1]) <= tol * max(abs(p[-1]), np.abs(p[:-1]).max())
+
+
+def test_dvd_quarters_layout_and_conduction_nusselt():
+    # Section 4.1: two diagonal quarters scattered, two regular.  Lattice nodes
+    # only in the regular quarters, Poisson-disk fill only in the scattered
+    # ones; the classifier finds regular nodes only where the lattice is.  On
+    # the conduction profile T = x - 1/2 (T_C = -0.5 at x = 0, T_H = 0.5 at
+    # x = 1) the cold-wall Nusselt number is 1: the normal-derivative weights
+    # reproduce linear functions.
+    q = ng.dvd2d(0.05, "hybrid")
+    x, y = q.x
+    scat_q = ((x < 0.5) & (y < 0.5)) | ((x > 0.5) & (y > 0.5))
+    assert not np.any(scat_q[q.origin == 0])
+    assert np.all(scat_q[q.origin == 2])
+    assert np.sum(q.origin == 2) > 0
+    st = O.build(q.x, q.kind, q.normal, q.h, 2)
+    regular = st["cls"] == 0
+    assert np.all(q.origin[regular] == 0) and regular.sum() > 0.5 * np.sum(q.origin == 0)
+    cold = np.nonzero(q.group == 0)[0]
+    assert len(cold) == round(1 / q.h) - 1 and np.all(q.x[0][cold] == 0.0) and np.all(q.tbc[cold] == -0.5)
+    csr = O.to_csr(st)
+    assert O.nusselt(csr, q.x[0] - 0.5, cold) == pytest.approx(1.0, rel=1e-12)
+
+
+def test_condition_number_of_mon_cross_closed_form():
+    # Section 2.2: kappa(M) = sigma_max / sigma_min.  On a lattice cross, in
+    # coordinates scaled by h, M M^T splits into the x_a rows (eigenvalue 2)
+    # and the x_a^2 rows, whose span holds 1 and u = sum_a x_a^2 / sqrt(d) with
+    # Gram block [[2d+1, 2 sqrt d], [2 sqrt d, 2]] (eigenvalues
+    # ((2d+3) +- sqrt((2d-1)^2 + 16d)) / 2, product 2) and eigenvalue 2 on the
+    # rest: kappa = ((2d+3) + sqrt((2d-1)^2 + 16d)) / (2 sqrt 2), independent of
+    # h and of the centre.
+    for d, h, c in ((2, 0.37, [0.3, 0.9]), (2, 1e-3, [5.0, -2.0]), (3, 0.02, [0.1, 0.2, 0.3])):
+        xs = [np.zeros(d)]
+        for a in range(d):
+            for sg in (-1, 1):
+                e = np.zeros(d)
+                e[a] = sg * h
+                xs.append(e)
+        xs = np.array(xs) + np.array(c)
+        sv = np.linalg.svd(O.local_matrix(xs), compute_uv=False)
+        disc = (2 * d - 1) ** 2 + 16 * d
+        assert sv[0] / sv[-1] == pytest.approx(((2 * d + 3) + np.sqrt(disc)) / (2 * np.sqrt(2)), rel=1e-12)
+    # every regular node of the cavity has a perfect cross
+    q = ng.cavity2d(h=0.05, seed=7)
+    kap = O.condition(q.x, q.kind, q.normal, q.h, 2)
+    st = O.build(q.x, q.kind, q.normal, q.h, 2)
+    assert np.allclose(kap[st["cls"] == 0], (7 + np.sqrt(41)) / (2 * np.sqrt(2)), rtol=1e-12)
+
+
+def test_condition_matrix_reproduces_the_weights():
+    # the matrix whose kappa is reported is the one the weights solve: M w = l
+    # with the right-hand sides of Section 2.1 gives the oracle's (pinned) weights
+    rng = np.random.default_rng(11)
+    for d, m in ((2, 2), (2, 4), (3, 2)):
+        n = O.stencil_size(d, m)
+        xs = rng.random((n, d)) * 0.1 + 0.4
+        w = O.rbffd(xs, m)
+        M = O.local_matrix(xs, m)
+        assert np.array_equal(M, M.T)
+        y = xs - xs[0]
+        s = np.sqrt((y * y).sum(1)).max()
+        y = y / s
+        r = np.sqrt((y * y).sum(1))
+        al = [tuple(a) for a in O.monomials(d, m)]
+        Q = len(al)
+        rhs = np.zeros((n + Q, d + 1))
+        for a in range(d):
+            rhs[:n, a] = -3 * r * y[:, a]
+            rhs[n + al.index(tuple(int(a == b) for b in range(d))), a] = 1.0
+            rhs[n + al.index(tuple(2 * int(a == b) for b in range(d))), d] = 2.0
+        rhs[:n, d] = 3 * (d + 1) * r
+        sol = np.linalg.solve(M, rhs)
+        assert np.allclose(sol[:n, :d].T / s, w[:d], rtol=0, atol=1e-9 * np.abs(w[:d]).max())
+        assert np.allclose(sol[:n, d] / s ** 2, w[d], rtol=0, atol=1e-9 * np.abs(w[d]).max())
+    # MON: the cross weights
+    xs = np.array([[0, 0], [-1, 0], [1, 0], [0, -1], [0, 1]]) * 0.01 + 0.5
+    M = O.local_matrix(xs)
+    rhs = np.zeros((5, 3))
+    rhs[1, 0] = rhs[2, 1] = 1.0
+    rhs[3, 2] = rhs[4, 2] = 2.0
+    sol = np.linalg.solve(M, rhs)
+    wm = O.mon(xs)
+    assert np.allclose(sol[:, :2].T / 0.01, wm[:2], atol=1e-9 * np.abs(wm[:2]).max())
+    assert np.allclose(sol[:, 2] / 1e-4, wm[2], atol=1e-9 * np.abs(wm[2]).max())
+
+
+def test_condition_number_invariances():
+    # kappa of an RBF-FD system depends only on the shape of the stencil: the
+    # same under translation, scaling and reordering of the non-centre nodes,
+    # and (M symmetric) equal to |lambda|_max / |lambda|_min
+    rng = np.random.default_rng(5)
+    xs = rng.random((12, 2))
+    k0 = np.linalg.svd(O.local_matrix(xs, 2), compute_uv=False)
+    k0 = k0[0] / k0[-1]
+    perm = np.concatenate([[0], 1 + rng.permutation(11)])
+    for ys in (xs + [3.0, -7.0], xs * 1e-3, xs[perm]):
+        sv = np.linalg.svd(O.local_matrix(ys, 2), compute_uv=False)
+        assert sv[0] / sv[-1] == pytest.approx(k0, rel=1e-9)
+    lam = np.abs(np.linalg.eigvalsh(O.local_matrix(xs, 2)))
+    assert lam.max() / lam.min() == pytest.approx(k0, rel=1e-9)
