@@ -53,7 +53,7 @@ enum {
   HSM_E_NONFINITE = -5,      /* a field became Inf/NaN during stepping */
   HSM_E_HIP = -6,            /* HIP runtime error (no device, launch failure) */
   HSM_E_OOM = -7,            /* device allocation failed */
-  HSM_E_AMBIGUOUS = -8       /* too many nodes within h_r of a node to classify it */
+  HSM_E_AMBIGUOUS = -8       /* reserved (no longer returned: crowded nodes are classified exactly) */
 };
 
 /* operator bits */
@@ -121,7 +121,7 @@ typedef struct {
  * most HSM_MAX_NODES nodes in total.
  *
  * Synchronises `stream`.  Errors: HSM_E_INVALID (arguments, a domain with
- * fewer than n usable nodes), HSM_E_DUPLICATE_NODE, HSM_E_AMBIGUOUS,
+ * fewer than n usable nodes), HSM_E_DUPLICATE_NODE,
  * HSM_E_SINGULAR (hsm_last_error_node names the node), HSM_E_OOM, HSM_E_HIP.
  * On success *out is a new handle.
  */

@@ -291,13 +291,56 @@ __global__ __launch_bounds__(128) void k_knn(KnnArgs a) {
           if (ok) { cnt[2 * ax + sg]++; fnd[2 * ax + sg] = j; }
         }
     }
+    // every node that could satisfy the cross test lies within h (1 + 3 tau);
+    // when the neighbour list does not reach beyond that radius (a dense,
+    // refined region), count the cross matches over every node of the cells
+    // within reach instead (the same rule, evaluated exhaustively)
+    const double R = h * (1.0 + 3.0 * kCrossTau);
+    if (!(bd[K - 1] > R * R)) {
+#pragma unroll
+      for (int c2 = 0; c2 < 2 * D; ++c2) { cnt[c2] = 0; fnd[c2] = -1; }
+      int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+#pragma unroll
+      for (int q = 0; q < D; ++q) {
+        double pl[D], ph[D];
+#pragma unroll
+        for (int u = 0; u < D; ++u) { pl[u] = xi[u]; ph[u] = xi[u]; }
+        pl[q] = xi[q] - 2.0 * R;
+        ph[q] = xi[q] + 2.0 * R;
+        int cl_[3] = {0, 0, 0}, ch_[3] = {0, 0, 0};
+        cell_coords<D>(g, pl, cl_);
+        cell_coords<D>(g, ph, ch_);
+        lo[q] = cl_[q];
+        hi[q] = ch_[q];
+      }
+      int c[3] = {0, 0, 0};
+      for (c[2] = (D == 3 ? lo[2] : 0); c[2] <= (D == 3 ? hi[2] : 0); ++c[2])
+        for (c[1] = lo[1]; c[1] <= hi[1]; ++c[1])
+          for (c[0] = lo[0]; c[0] <= hi[0]; ++c[0]) {
+            const int64_t id = cell_id<D>(g, c);
+            for (int64_t s = a.cell_start[id]; s < a.cell_start[id + 1]; ++s) {
+              const int32_t j = a.cell_nodes[s];
+              if (j == i) continue;
+              double tq[D];
+#pragma unroll
+              for (int q = 0; q < D; ++q) tq[q] = a.x[q * N + j] - xi[q];
+#pragma unroll
+              for (int ax = 0; ax < D; ++ax)
+#pragma unroll
+                for (int sg = 0; sg < 2; ++sg) {
+                  const double e = sg ? tq[ax] - h : tq[ax] + h;
+                  bool ok = fabs(e) <= tol;
+#pragma unroll
+                  for (int q = 0; q < D; ++q)
+                    if (q != ax && !(fabs(tq[q]) <= tol)) ok = false;
+                  if (ok) { cnt[2 * ax + sg]++; fnd[2 * ax + sg] = j; }
+                }
+            }
+          }
+    }
     bool reg = true;
 #pragma unroll
     for (int c2 = 0; c2 < 2 * D; ++c2) reg = reg && (cnt[c2] == 1);
-    // every node that could satisfy the cross test lies within h (1 + 3 tau);
-    // the neighbour list must reach beyond that radius
-    const double R = h * (1.0 + 3.0 * kCrossTau);
-    if (!(bd[K - 1] > R * R)) latch(a.status, BE_AMBIGUOUS, i);
     cl = reg ? 0 : 1;
 #pragma unroll
     for (int c2 = 0; c2 < 2 * D; ++c2) a.cross[(int64_t)c2 * N + i] = fnd[c2];

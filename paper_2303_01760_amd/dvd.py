@@ -11,6 +11,8 @@ and the wall-clock time of the stepping.
 
 Usage:
     python -m paper_2303_01760_amd.dvd --h 0.01 --layout hybrid regular scattered --t-end 0.15
+    python -m paper_2303_01760_amd.dvd --h 0.02 --layout horizontal vertical --delta-h 5 10 25 40
+(the split layouts are the study of the scattered layer width delta_h).
 
 Every step runs in the library's kernels; the host only averages |dT/dn|
 over the cold-wall nodes at report times.
@@ -44,23 +46,23 @@ def nusselt(st: hsm.Stencils, T: torch.Tensor, nodes: np.ndarray, L: float = 1.0
     return float(L / dT * np.mean(np.abs(g)))
 
 
-def run(h: float = 0.01, layout: str = "hybrid", Ra: float = 1e6, Pr: float = 0.71, t_end: float = 0.15,
-        dt: float | None = None, m: int = 2, tol: float = 1e-10, reports: int = 30, seed: int = ng.SEED_BASE + 6,
-        progress=None) -> dict:
-    """Step the cavity to t_end; return the Nu history and the midline profile."""
-    q = ng.dvd2d(h, layout, seed=seed)
-    dt = 0.1 * h * h / 2 if dt is None else dt      # the paper's time-step rule
+def run_case(q: ng.NodeSet, *, Ra: float, Pr: float = 0.71, T_ref: float, t_end: float, dt: float,
+             cold: np.ndarray, m: int = 2, tol: float = 1e-10, reports: int = 30, max_steps: int | None = None,
+             progress=None, label: str = "") -> dict:
+    """Step a node set from v = 0, T = its Dirichlet values (0 elsewhere) to
+    t_end (or max_steps); return the history of Nu over the `cold` nodes."""
     nsteps = int(math.ceil(t_end / dt - 1e-9))
+    if max_steps is not None:
+        nsteps = min(nsteps, max_steps)
     dev = torch.device("cuda")
     t0 = time.perf_counter()
     st = hsm.build_stencils(torch.tensor(q.x, device=dev), torch.tensor(q.kind, device=dev),
-                            torch.tensor(q.normal, device=dev), h, m)
+                            torch.tensor(q.normal, device=dev), q.h, m)
     torch.cuda.synchronize()
     t_build = time.perf_counter() - t0
-    v0 = torch.zeros((2, q.n), dtype=torch.float64, device=dev)
+    v0 = torch.zeros((q.d, q.n), dtype=torch.float64, device=dev)
     T0 = torch.tensor(np.where(q.kind == ng.KIND_DIRICHLET, q.tbc, 0.0), device=dev)
-    sim = hsm.Sim(st, v0, T0, Ra=Ra, Pr=Pr, dt=dt, T_ref=0.0, krylov_tol=tol)
-    cold = cold_wall_nodes(q)
+    sim = hsm.Sim(st, v0, T0, Ra=Ra, Pr=Pr, dt=dt, T_ref=T_ref, krylov_tol=tol)
     hist = []
     done, t_step = 0, 0.0
     per = max(1, nsteps // reports)
@@ -79,25 +81,49 @@ def run(h: float = 0.01, layout: str = "hybrid", Ra: float = 1e6, Pr: float = 0.
         nu = nusselt(st, T, cold)
         hist.append((done * dt, nu))
         if progress:
-            progress(f"{layout} h={h}: t={done * dt:.4f} ({done}/{nsteps} steps) Nu={nu:.4f} "
+            progress(f"{label}: t={done * dt:.5f} ({done}/{nsteps} steps) Nu={nu:.4f} "
                      f"krylov iters/step {stats['krylov_iters_total'] / done:.1f}")
     v, T, p = [a.cpu().numpy() for a in sim.read()]
     stats = sim.stats()
-    mid = np.nonzero(np.abs(q.x[1] - 0.5) <= h)[0]
-    order = mid[np.argsort(q.x[0][mid])]
+    info = st.info()
     sim.close()
     st.close()
-    return dict(layout=layout, h=h, N=q.n, n_scattered_fill=int(np.sum(q.origin == 2)),
-                n_lattice=int(np.sum(q.origin == 0)), Ra=Ra, Pr=Pr, dt=dt, t_end=nsteps * dt, steps=nsteps,
-                krylov_tol=tol, krylov_iters_total=stats["krylov_iters_total"],
-                nu_final=hist[-1][1], nu_history=hist, build_s=t_build, stepping_s=t_step,
-                midline=dict(x=q.x[0][order].tolist(), y=q.x[1][order].tolist(), v_y=v[1][order].tolist()))
+    return dict(N=q.n, n_regular=int(info["n_regular"]), n_scattered=int(info["n_scattered"]),
+                n_scattered_fill=int(np.sum(q.origin == 2)), n_lattice=int(np.sum(q.origin == 0)), Ra=Ra, Pr=Pr,
+                dt=dt, t_end=nsteps * dt, steps=nsteps, krylov_tol=tol,
+                krylov_iters_total=stats["krylov_iters_total"], nu_final=hist[-1][1], nu_history=hist,
+                build_s=t_build, stepping_s=t_step, ms_per_step=1e3 * t_step / nsteps, v=v, T=T)
+
+
+def run(h: float = 0.01, layout: str = "hybrid", Ra: float = 1e6, Pr: float = 0.71, t_end: float = 0.15,
+        dt: float | None = None, m: int = 2, tol: float = 1e-10, reports: int = 30, seed: int = ng.SEED_BASE + 6,
+        delta_h: float = 4.0, progress=None) -> dict:
+    """The cavity to t_end; layout hybrid / regular / scattered, or
+    horizontal / vertical (the split at h*delta_h); returns the Nu history
+    and the midline profile."""
+    if layout in ("horizontal", "vertical"):
+        q = ng.dvd2d_split(h, delta_h, layout, seed=seed)
+    else:
+        q = ng.dvd2d(h, layout, seed=seed)
+    dt = 0.1 * h * h / 2 if dt is None else dt      # the paper's time-step rule
+    r = run_case(q, Ra=Ra, Pr=Pr, T_ref=0.0, t_end=t_end, dt=dt, cold=cold_wall_nodes(q), m=m, tol=tol,
+                 reports=reports, progress=progress, label=f"{layout} h={h}")
+    v = r.pop("v")
+    r.pop("T")
+    mid = np.nonzero(np.abs(q.x[1] - 0.5) <= h)[0]
+    order = mid[np.argsort(q.x[0][mid])]
+    r.update(layout=layout, h=h, delta_h=delta_h if layout in ("horizontal", "vertical") else None,
+             midline=dict(x=q.x[0][order].tolist(), y=q.x[1][order].tolist(), v_y=v[1][order].tolist()))
+    return r
 
 
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--h", type=float, default=0.01)
-    ap.add_argument("--layout", nargs="+", default=["hybrid"], choices=["hybrid", "regular", "scattered"])
+    ap.add_argument("--layout", nargs="+", default=["hybrid"],
+                    choices=["hybrid", "regular", "scattered", "horizontal", "vertical"])
+    ap.add_argument("--delta-h", type=float, nargs="+", default=[4.0],
+                    help="split layouts: the scattered part ends at h*delta_h")
     ap.add_argument("--Ra", type=float, default=1e6)
     ap.add_argument("--t-end", type=float, default=0.15)
     ap.add_argument("--tol", type=float, default=1e-10)
@@ -106,11 +132,13 @@ def main(argv=None):
     a = ap.parse_args(argv)
     res = []
     for lay in a.layout:
-        r = run(h=a.h, layout=lay, Ra=a.Ra, t_end=a.t_end, tol=a.tol, reports=a.reports,
-                progress=lambda s: print(s, file=sys.stderr, flush=True))
-        print(json.dumps({k: r[k] for k in ("layout", "h", "N", "steps", "nu_final", "stepping_s",
-                                            "krylov_iters_total")}), flush=True)
-        res.append(r)
+        for dh in (a.delta_h if lay in ("horizontal", "vertical") else [None]):
+            r = run(h=a.h, layout=lay, Ra=a.Ra, t_end=a.t_end, tol=a.tol, reports=a.reports,
+                    delta_h=dh if dh is not None else 4.0,
+                    progress=lambda s: print(s, file=sys.stderr, flush=True))
+            print(json.dumps({k: r[k] for k in ("layout", "h", "delta_h", "N", "steps", "nu_final", "stepping_s",
+                                                "krylov_iters_total")}), flush=True)
+            res.append(r)
     if a.out:
         with open(a.out, "w") as f:
             json.dump(res, f)

@@ -44,7 +44,8 @@ class _Params(ctypes.Structure):
         ("wall_kind", ctypes.c_int32 * 6), ("wall_T", ctypes.c_double * 6),
         ("obst_T", ctypes.c_double * 2), ("obst_kind", ctypes.c_int32),
         ("n_candidates", ctypes.c_int32), ("seed", ctypes.c_uint64),
-        ("quarters", ctypes.c_int32), ("pad", ctypes.c_int32),
+        ("quarters", ctypes.c_int32), ("split_axis", ctypes.c_int32), ("split_pos", ctypes.c_double),
+        ("h_s", ctypes.c_double),
     ]
 
 
@@ -88,7 +89,8 @@ class NodeSet:
 def generate(d: int, h: float, *, wall_band: float = 0.0, obst_band: float = 0.0,
              n_obst: int = 0, rmin: float = 0.0, rmax: float = 0.0, gap: float = 4.0,
              wall_kind=None, wall_T=None, obst_T=(0.0, 1.0), obst_kind: int = KIND_DIRICHLET,
-             n_candidates: int = 30, quarters: bool = False, seed: int = SEED_BASE, name: str = "") -> NodeSet:
+             n_candidates: int = 30, quarters: bool = False, split_axis: int = -1, split_pos: float = 0.0,
+             h_s: float = 0.0, seed: int = SEED_BASE, name: str = "") -> NodeSet:
     lib = _load()
     p = _Params()
     p.d, p.n_obst, p.h = d, n_obst, h
@@ -100,7 +102,7 @@ def generate(d: int, h: float, *, wall_band: float = 0.0, obst_band: float = 0.0
         p.wall_T[i] = float(wt[i]) if i < len(wt) else 0.0
     p.obst_T[0], p.obst_T[1] = float(obst_T[0]), float(obst_T[1])
     p.obst_kind, p.n_candidates, p.seed = obst_kind, n_candidates, seed & 0xFFFFFFFFFFFFFFFF
-    p.quarters, p.pad = int(bool(quarters)), 0
+    p.quarters, p.split_axis, p.split_pos, p.h_s = int(bool(quarters)), int(split_axis), float(split_pos), float(h_s)
     n = ctypes.c_int64(0)
     hnd = lib.ng_generate(ctypes.byref(p), ctypes.byref(n))
     if not hnd:
@@ -148,6 +150,46 @@ def dvd2d(h: float = 0.01, layout: str = "hybrid", seed: int = SEED_BASE + 6,
     if layout == "scattered":
         return generate(2, h, wall_band=0.6, wall_kind=kinds, wall_T=temps, seed=seed, name=f"dvd_scattered_h{h}")
     raise ValueError(f"unknown layout {layout!r}")
+
+
+def dvd2d_split(h: float = 0.01, delta_h: float = 4.0, split: str = "horizontal", seed: int = SEED_BASE + 6,
+                T_cold: float = -0.5, T_hot: float = 0.5) -> NodeSet:
+    """The de Vahl Davis box split at distance h*delta_h from the origin
+    (Section 4.1, the scattered-layer-width study): "horizontal" puts scattered
+    nodes below y = h*delta_h and the lattice above, "vertical" scattered nodes
+    left of x = h*delta_h.  delta_h = 0 is all lattice, h*delta_h >= 1 all
+    scattered."""
+    axis = {"vertical": 0, "horizontal": 1}[split]
+    kinds = [KIND_DIRICHLET, KIND_DIRICHLET, KIND_NEUMANN, KIND_NEUMANN]
+    temps = [T_cold, T_hot, 0.0, 0.0]
+    return generate(2, h, split_axis=axis, split_pos=h * delta_h, wall_kind=kinds, wall_T=temps, seed=seed,
+                    name=f"dvd_{split}_h{h}_d{delta_h}")
+
+
+def refined2d(h_r: float = 0.01, ratio: float = 3.0, delta_h: float = 4.0, n_obst: int = 4,
+              rmin: float = 0.05, rmax: float = 0.1, scattered: bool = False,
+              seed: int = SEED_BASE + 7) -> NodeSet:
+    """Irregular 2D domain with h-refinement (Section 4.2): the unit square
+    minus n_obst circles (standing in for the duck shapes), spacing h_r/ratio
+    on the circles growing linearly to h_r over h_r*delta_h, which is also the
+    width of the scattered layer; scattered=True fills the whole box (same
+    refinement).  Box walls adiabatic, circles alternately T=0 / T=1."""
+    band = h_r * delta_h
+    return generate(2, h_r, obst_band=band, wall_band=0.6 if scattered else 0.0, n_obst=n_obst, rmin=rmin,
+                    rmax=rmax, h_s=h_r / ratio, wall_kind=[KIND_NEUMANN] * 4, seed=seed,
+                    name=f"refined2d_h{h_r}_d{delta_h}{'_scattered' if scattered else ''}")
+
+
+def refined3d(h_r: float = 0.025, ratio: float = 2.0, delta_h: float = 4.0, n_obst: int = 4,
+              rmin: float = 0.08, rmax: float = 0.15, scattered: bool = False,
+              seed: int = SEED_BASE + 8) -> NodeSet:
+    """The paper's 3D case (Section 4.3): the unit cube minus n_obst spheres,
+    spacing h_r/ratio on the spheres growing linearly to h_r over h_r*delta_h;
+    box walls adiabatic, spheres alternately T=0 / T=1."""
+    band = h_r * delta_h
+    return generate(3, h_r, obst_band=band, wall_band=0.6 if scattered else 0.0, n_obst=n_obst, rmin=rmin,
+                    rmax=rmax, h_s=h_r / ratio, wall_kind=[KIND_NEUMANN] * 6, seed=seed,
+                    name=f"refined3d_h{h_r}_d{delta_h}{'_scattered' if scattered else ''}")
 
 
 def obstacles2d(h: float = 0.002, n_obst: int = 20, rmin: float = 0.02, rmax: float = 0.08,

@@ -39,7 +39,9 @@ typedef struct {
   int32_t n_candidates;  /* Poisson-disk candidates per active point (30) */
   uint64_t seed;
   int32_t quarters;      /* 2D only, 1: the quarters x<1/2,y<1/2 and x>1/2,y>1/2 are scattered too */
-  int32_t pad;
+  int32_t split_axis;    /* >= 0: the part x[split_axis] < split_pos is scattered too */
+  double split_pos;
+  double h_s;            /* 0 < h_s < h: spacing at obstacle surfaces, growing linearly to h over obst_band */
 } ng_params;
 
 typedef struct {
@@ -112,6 +114,16 @@ static double dist_surface(const ng_set *S, const double *p, int *which) {
   return best;
 }
 
+/* Node spacing at p: h, or with refinement towards the obstacles (h_s > 0)
+ * h_s on their surfaces growing linearly to h at distance obst_band. */
+static double spacing(const ng_params *P, const ng_set *S, const double *p) {
+  if (!(P->h_s > 0) || P->h_s >= P->h || S->n_obst == 0 || !(P->obst_band > 0)) return P->h;
+  double f = dist_surface(S, p, NULL) / P->obst_band;
+  if (f < 0) f = 0;
+  if (f > 1) f = 1;
+  return P->h_s + (P->h - P->h_s) * f;
+}
+
 /* ---- uniform cell list used only for Poisson-disk rejection ---- */
 typedef struct { int d, nc; double cs; int64_t *head, *next; int64_t cap; int64_t ncell; } cgrid;
 static void cg_cell(const cgrid *G, const double *p, int *ci) {
@@ -181,6 +193,8 @@ void *ng_generate(const ng_params *P, int64_t *n_out) {
   *n_out = 0;
   if (!P || (P->d != 2 && P->d != 3) || !(P->h > 0) || P->h > 0.5 || P->n_obst < 0) return NULL;
   if (P->quarters && P->d != 2) return NULL;
+  if (P->split_axis < -1 || P->split_axis >= P->d) return NULL;
+  if (P->h_s < 0 || P->h_s > P->h) return NULL;
   const int d = P->d;
   const double h = P->h;
   const int nl = (int)llround(1.0 / h); /* lattice: i*h, i = 1 .. nl-1 interior */
@@ -238,13 +252,14 @@ void *ng_generate(const ng_params *P, int64_t *n_out) {
         if (push(S, p, nrm, kind, kind == 1 ? P->wall_T[face] : 0.0, 1, face)) { free_set(S); return NULL; }
       }
   }
-  /* obstacle boundary nodes */
+  /* obstacle boundary nodes, at the surface spacing */
+  const double hb = (P->h_s > 0 && P->h_s < h) ? P->h_s : h;
   for (int o = 0; o < S->n_obst; ++o) {
     const double *c = S->obst + o * (d + 1);
     const double r = c[d];
     double tb = P->obst_T[o % 2];
     if (d == 2) {
-      int n = (int)ceil(2.0 * M_PI * r / h);
+      int n = (int)ceil(2.0 * M_PI * r / hb);
       double ph = 2.0 * M_PI * rng_u01(&g);
       for (int k = 0; k < n; ++k) {
         double t = ph + 2.0 * M_PI * k / n;
@@ -254,7 +269,7 @@ void *ng_generate(const ng_params *P, int64_t *n_out) {
         if (push(S, p, nrm, P->obst_kind, P->obst_kind == 1 ? tb : 0.0, 1, 6 + o)) { free_set(S); return NULL; }
       }
     } else {
-      int n = (int)ceil(4.0 * M_PI * r * r / (h * h));
+      int n = (int)ceil(4.0 * M_PI * r * r / (hb * hb));
       double ph = 2.0 * M_PI * rng_u01(&g);
       const double ga = M_PI * (3.0 - sqrt(5.0));
       for (int k = 0; k < n; ++k) {
@@ -282,6 +297,7 @@ void *ng_generate(const ng_params *P, int64_t *n_out) {
             if (idx[a] < wall_band_i || idx[a] > nl - wall_band_i) inband = 1;
           double p[3] = {i * h, j * h, k * h};
           if (P->quarters && in_quarters(p)) inband = 1;
+          if (P->split_axis >= 0 && p[P->split_axis] < P->split_pos) inband = 1;
           if (inband) continue;
           if (S->n_obst && dist_surface(S, p, NULL) < P->obst_band) continue;
           if (push(S, p, NULL, 0, 0.0, 0, -1)) { free_set(S); return NULL; }
@@ -304,23 +320,23 @@ void *ng_generate(const ng_params *P, int64_t *n_out) {
   int64_t *active = malloc(sizeof(int64_t) * (S->cap + 16));
   int64_t act_cap = S->cap + 16, nact = 0;
   for (int64_t i = 0; i < n_boundary; ++i) active[nact++] = i;
-  const double h2 = h * h;
   const double wb = wall_band_i * h;
   while (nact > 0) {
     int64_t pick = (int64_t)(rng_u01(&g) * nact);
     if (pick >= nact) pick = nact - 1;
     int64_t a0 = active[pick];
+    const double r0 = spacing(P, S, S->x + a0 * d);
     int found = 0;
     for (int t = 0; t < P->n_candidates; ++t) {
       double p[3], dir[3], s = 0;
       if (d == 2) {
         double th = 2.0 * M_PI * rng_u01(&g);
-        double rr = h * sqrt(1.0 + 3.0 * rng_u01(&g));
+        double rr = r0 * sqrt(1.0 + 3.0 * rng_u01(&g));
         dir[0] = rr * cos(th); dir[1] = rr * sin(th);
       } else {
         double z = 2.0 * rng_u01(&g) - 1.0, th = 2.0 * M_PI * rng_u01(&g);
         double rho = sqrt(fmax(0.0, 1.0 - z * z));
-        double rr = h * cbrt(1.0 + 7.0 * rng_u01(&g));
+        double rr = r0 * cbrt(1.0 + 7.0 * rng_u01(&g));
         dir[0] = rr * rho * cos(th); dir[1] = rr * rho * sin(th); dir[2] = rr * z;
       }
       int inside = 1;
@@ -335,13 +351,15 @@ void *ng_generate(const ng_params *P, int64_t *n_out) {
       for (int a = 0; a < d; ++a)
         if (p[a] < wb || p[a] > 1.0 - wb) inband = 1;
       if (P->quarters && in_quarters(p)) inband = 1;
+      if (P->split_axis >= 0 && p[P->split_axis] < P->split_pos) inband = 1;
       if (S->n_obst) {
         double ds = dist_surface(S, p, NULL);
         if (ds <= 0.0) continue;              /* inside an obstacle */
         if (ds < P->obst_band) inband = 1;
       }
       if (!inband) continue;
-      if (!cg_far(&G, S, p, h2)) continue;
+      const double rp = spacing(P, S, p);
+      if (!cg_far(&G, S, p, rp * rp)) continue;
       if (push(S, p, NULL, 0, 0.0, 2, -1)) { free(active); free(G.head); free(G.next); free_set(S); return NULL; }
       if (cg_insert(&G, S->n - 1, p)) { free(active); free(G.head); free(G.next); free_set(S); return NULL; }
       if (nact == act_cap) {

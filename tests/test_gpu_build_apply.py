@@ -197,17 +197,33 @@ def test_collinear_stencil_is_singular():
     assert e.value.node == eo.value.node
 
 
-def test_crowded_node_is_ambiguous():
-    # more than n nodes within h_r of a node: the cross test cannot be decided
-    # from its neighbour list, which the build reports instead of guessing
+def test_crowded_node_is_classified_exactly():
+    # more than n nodes within h_r of a lattice node (a refined clump around
+    # it): its neighbour list cannot show the whole axis cross, so the build
+    # counts cross matches over every node within reach; classes and stencils
+    # match the oracle's brute-force rule
     hsm = _hsm()
-    n = 40
-    xx = np.stack([np.linspace(0, 1, n), np.full(n, 0.5)])
+    h = 0.1
+    g = np.arange(11) * h
+    lat = np.stack(np.meshgrid(g, g, indexing="ij")).reshape(2, -1)
+    rng = np.random.default_rng(17)
+    ang = rng.random(16) * 2 * np.pi
+    rad = 0.15 * h + 0.3 * h * rng.random(16)
+    c = np.array([0.5, 0.5])
+    clump = c[:, None] + rad * np.stack([np.cos(ang), np.sin(ang)])
+    xx = np.concatenate([lat, clump], axis=1)
+    n = xx.shape[1]
+    ic = int(np.argmin(((lat - c[:, None]) ** 2).sum(0)))
+    assert (np.sqrt(((xx - c[:, None]) ** 2).sum(0)) < h).sum() - 1 > 12   # the list saturates
+    kind = np.zeros(n, np.uint8)
     dev = torch.device("cuda")
-    with pytest.raises(hsm.HsmError) as e:
-        hsm.build_stencils(torch.tensor(xx, device=dev), torch.zeros(n, dtype=torch.uint8, device=dev),
-                           torch.zeros((2, n), dtype=torch.float64, device=dev), 0.3, 2)
-    assert e.value.code == hsm.E_AMBIGUOUS
+    st = hsm.build_stencils(torch.tensor(xx, device=dev), torch.tensor(kind, device=dev),
+                            torch.zeros((2, n), dtype=torch.float64, device=dev), h, 2)
+    ex = st.export()
+    ora = O.to_csr(O.build(xx, kind, np.zeros((2, n)), h, 2))
+    assert np.array_equal(ex["cls"], ora["cls"])
+    assert ex["cls"][ic] == 0
+    assert np.array_equal(ex["off"], ora["off"]) and np.array_equal(ex["idx"], ora["idx"])
 
 
 def test_ragged_tiny_domain_builds():
