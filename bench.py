@@ -32,7 +32,7 @@ HBM_PEAK_GBS = 8000.0
 KRYLOV_CHUNK = 16      # BiCGSTAB iterations per queued batch
 PMC_COMMAND = ('rocprofv3 --pmc {} --kernel-include-regex "k_bicg_pv|k_bicg_st|k_stream_copy" --output-format csv '
                '-d <dir> -o run -- python3 bench.py --steps 1 --warmup 0 --time-steps 1 --no-cpu-baseline '
-               '--skip-all-scattered')
+               '--skip-all-scattered --skip-fp32-form')
 PROFILES = os.path.join(ROOT, "profiles")
 TRAFFIC_FILE = os.path.join(PROFILES, "traffic_bicg_iteration_obstacles2d_h0.002.json")
 # device code the traffic record was measured on (the kernels and their shared helpers)
