@@ -258,11 +258,12 @@ __device__ __forceinline__ RedSlot red_slot(int K) {
   return r;
 }
 
-// Totals of domain r.d's block partials, valid in the lead thread.  `need`
-// is the same in every lane of a wave.  Every thread of the block calls it.
+// Totals of domain r.d's block partials (its rows [j0, j1)), valid in the
+// lead thread.  `need` is the same in every lane of a wave.  Every thread of
+// the block calls it.
 template <int NQ>
 __device__ __forceinline__ void domain_sums(const SimArgs &a, const double *__restrict__ part, const RedSlot &r,
-                                            bool need, double (&tot)[NQ]) {
+                                            bool need, int j0, int j1, double (&tot)[NQ]) {
   __shared__ double red[kRedWaves][NQ];
   const int G = red_group(a.K), wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   double acc[NQ];
@@ -272,8 +273,8 @@ __device__ __forceinline__ void domain_sums(const SimArgs &a, const double *__re
     // four passes' loads issued before their sums (rows past the end read
     // as 0.0, which leaves every sum unchanged)
     constexpr int U = 4;
-    const int j1 = a.dom_blk_off[r.d + 1], step = G * 64;
-    for (int j = a.dom_blk_off[r.d] + r.g * 64 + lane; j < j1; j += U * step) {
+    const int step = G * 64;
+    for (int j = j0 + r.g * 64 + lane; j < j1; j += U * step) {
       double vals[U][NQ];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
@@ -391,11 +392,13 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_r(SimArgs a) {
   const int64_t N = a.N;
   const RedSlot rs = red_slot(a.K);
   const int d = rs.d;
+  const int j0 = d < a.K ? a.dom_blk_off[d] : 0, j1 = d < a.K ? a.dom_blk_off[d + 1] : 0;
+  const double cb = d < a.K ? a.bscale[d] : 0.0;
   double tot[kNR];
-  domain_sums<kNR>(a, a.partR, rs, d < a.K, tot);
+  domain_sums<kNR>(a, a.partR, rs, d < a.K, j0, j1, tot);
   if (rs.lead) {
     DomState &ds = a.dom[d];
-    const double r = -(a.bscale[d] * tot[2]);
+    const double r = -(cb * tot[2]);
     a.RV[N + d] = make_double2(r, 0.0);
     a.rh[N + d] = r;
     const double rr = fma(r, r, tot[1]);
@@ -422,23 +425,27 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_r(SimArgs a) {
 // breakdown (early 2) ends it as failed.
 __global__ __launch_bounds__(kRedThreads) void k_reduce_a(SimArgs a, int it) {
   Scalars *sc = a.sc;
-  if (sc->done) return;
-  __shared__ BatchFlags f;
-  const bool one = a.K == 1;
-  if (one) batch_begin(f);
   const int par = it & 1;
   const int64_t N = a.N;
-  const int k = sc->it_base + it;
   const RedSlot rs = red_slot(a.K);
   const int d = rs.d;
-  const bool live = d < a.K && !a.dom[d].done;
-  const int e = (live && k != 0) ? a.dom[d].early[par] : 0;
-  // the lead's border rows and scalars, loaded while the partials are summed
+  const bool has = d < a.K;
+  // every load that depends on nothing else first (one round): the batch
+  // state, the domain's state and block range, and the lead's border rows
+  // and scalars, which it uses once the partials are summed
+  const int all_done = sc->done, it_base = sc->it_base;
+  int dd = 1, e = 0, j0 = 0, j1 = 0;
+  if (has) {
+    dd = a.dom[d].done;
+    e = a.dom[d].early[par];
+    j0 = a.dom_blk_off[d];
+    j1 = a.dom_blk_off[d + 1];
+  }
   double alpha_p = 0.0, omega = 0.0, beta = 0.0, bnorm2 = 0.0, rho = 0.0, xb = 0.0, rhb = 0.0;
   double2 rvb = make_double2(0.0, 0.0), stb = rvb, pvb = rvb;
   int64_t nodes = 0;
   double cb = 0.0;
-  if (rs.lead && live) {
+  if (rs.lead) {
     const DomState &ds = a.dom[d];
     cb = a.bscale[d];
     alpha_p = ds.alpha[par ^ 1]; omega = ds.omega[par]; beta = ds.beta[par];
@@ -447,8 +454,15 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_a(SimArgs a, int it) {
     rvb = a.RV[N + d]; stb = a.ST[N + d]; pvb = a.PVo[N + d];
     nodes = a.dom_nodes[d];
   }
+  if (all_done) return;
+  __shared__ BatchFlags f;
+  const bool one = a.K == 1;
+  if (one) batch_begin(f);
+  const int k = it_base + it;
+  const bool live = has && !dd;
+  if (!live || k == 0) e = 0;
   double tot[kNA];
-  domain_sums<kNA>(a, a.partA, rs, live && e == 0, tot);
+  domain_sums<kNA>(a, a.partA, rs, live && e == 0, j0, j1, tot);
   if (rs.lead) {
     DomState &ds = a.dom[d];
     if (live) {
@@ -498,24 +512,32 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_a(SimArgs a, int it) {
 // omega = (t,s)/(t,t), rho' = (r^,s) - omega (r^,t), beta = (rho'/rho)(alpha/omega).
 __global__ __launch_bounds__(kRedThreads) void k_reduce_b(SimArgs a, int it) {
   Scalars *sc = a.sc;
-  if (sc->done) return;
   const int par = it & 1, nx = par ^ 1;
   const int64_t N = a.N;
   const RedSlot rs = red_slot(a.K);
   const int d = rs.d;
-  const bool live = d < a.K && !a.dom[d].done;
-  // the lead's border rows and scalars, loaded while the partials are summed
+  const bool has = d < a.K;
+  // independent loads first, as in k_reduce_a
+  const int all_done = sc->done;
+  int dd = 1, j0 = 0, j1 = 0;
+  if (has) {
+    dd = a.dom[d].done;
+    j0 = a.dom_blk_off[d];
+    j1 = a.dom_blk_off[d + 1];
+  }
   double alpha = 0.0, rho = 0.0, bnorm2 = 0.0, rhb = 0.0, cb = 0.0;
   double2 rv = make_double2(0.0, 0.0);
-  if (rs.lead && live) {
+  if (rs.lead) {
     const DomState &ds = a.dom[d];
     cb = a.bscale[d];
     alpha = ds.alpha[par]; rho = ds.rho[par]; bnorm2 = ds.bnorm2;
     rv = a.RV[N + d];
     rhb = a.rh[N + d];
   }
+  if (all_done) return;
+  const bool live = has && !dd;
   double tot[kNB];
-  domain_sums<kNB>(a, a.partB, rs, live, tot);
+  domain_sums<kNB>(a, a.partB, rs, live, j0, j1, tot);
   if (!(rs.lead && live)) return;
   DomState &ds = a.dom[d];
   const double sb = fma(-alpha, rv.y, rv.x), tb = cb * tot[5];   // border row of t = A s: c_d sum s
