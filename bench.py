@@ -18,6 +18,7 @@ timed region (every (operator, field, node) triple evaluated, Krylov
 matrix-vector products included, divided by wall time).
 """
 import argparse
+from math import comb
 import hashlib
 import json
 import os
@@ -220,6 +221,14 @@ WORKLOADS = {
 }
 
 
+def bw_m(width, d):
+    """Polynomial degree of a scattered bucket from its stencil size n = 2 C(m+d, m) (3D n = 30: m = 2)."""
+    for m in range(1, 5):
+        if 2 * comb(m + d, m) == width:
+            return m
+    return 2
+
+
 def apply_bytes(buckets, N, nops, fsize):
     """Algorithmic bytes of one fused apply of nops operators to one field:
     int32 indices and every weight read once, the field read once, nops outputs written."""
@@ -338,19 +347,22 @@ def main():
             rec["final"] = [a.cpu().numpy() for a in sim.read()]
         return st
 
-    def apply_timing(st, dtype, reps=20):
-        """Mean device time of one fused 3-operator apply to one field (events on the launch stream)."""
+    def apply_timing(st, dtype, reps=20, bucket_mask=None):
+        """Mean device time of one fused 3-operator apply to one field (events on the launch stream);
+        with bucket_mask, of the apply restricted to those width buckets."""
         u = st.to_internal(fields[0])
         if dtype != hsm.F64:
             u = u.float()
         out = torch.empty((3, s.n), dtype=u.dtype, device=dev)
+        run = ((lambda: st.apply(u, ops, dtype, out=out)) if bucket_mask is None
+               else (lambda: st.apply_buckets(u, ops, bucket_mask, dtype, out=out)))
         for _ in range(3):
-            st.apply(u, ops, dtype, out=out)
+            run()
         torch.cuda.synchronize()
         a0, a1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         a0.record()
         for _ in range(reps):
-            st.apply(u, ops, dtype, out=out)
+            run()
         a1.record()
         torch.cuda.synchronize()
         return a0.elapsed_time(a1) / reps
@@ -394,6 +406,33 @@ def main():
                 am.setdefault("precision", {}).setdefault(lbl, {})[rk] = dict(
                     rel_l2=float(torch.linalg.vector_norm(got - ref).item() / torch.linalg.vector_norm(ref).item()),
                     max_rel=float((got - ref).abs().max().item() / ref.abs().max().item()))
+        # per width bucket: the fused FP64 apply restricted to the bucket, and the bucket's local solves
+        info_last = st_last.info()
+        per = []
+        for kb, (bt, bw, bc) in enumerate(info_last["buckets"]):
+            if bc == 0:
+                continue
+            ms = apply_timing(st_last, hsm.F64, bucket_mask=1 << kb)
+            by = apply_bytes([(bt, bw, bc)], bc, nops, 8)
+            S = bw + (0 if bt == 0 else comb(bw_m(bw, D) + D, D))
+            flops = (2.0 / 3.0) * S ** 3 + 2.0 * S * S * (D + 1)   # LU and d+1 solves per system
+            sms = info_last["bucket_solve_ms"][kb] if kb < 16 else float("nan")
+            per.append(dict(type=["regular", "scattered", "dirichlet_wall", "neumann_wall"][bt], width=bw, nodes=bc,
+                            apply_ms=ms, apply_node_applies_per_s=nops * bc / (ms * 1e-3),
+                            apply_gbs=by / (ms * 1e-3) / 1e9, apply_frac=by / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                            solve_ms=sms, solves_per_s=bc / (sms * 1e-3) if sms > 0 else None,
+                            solve_fp64_tflops=(bc * flops / (sms * 1e-3) / 1e12) if sms > 0 else None))
+        am["per_bucket"] = per
+        reg = [b for b in per if b["type"] == "regular"]
+        sca = [b for b in per if b["type"] == "scattered"]
+        if reg and sca:
+            # per-node throughput of the regular bucket over the scattered one, against 0.9 x the ratio of
+            # their algorithmic bytes per node (what two bandwidth-bound buckets would show)
+            r_node = (reg[0]["apply_node_applies_per_s"] / sca[0]["apply_node_applies_per_s"])
+            bpn = lambda w: (4 + nops * 8) * w + 8 + nops * 8
+            target = 0.9 * bpn(sca[0]["width"]) / bpn(reg[0]["width"])
+            am["regular_over_scattered_per_node"] = dict(measured=r_node, target_0p9_bytes_ratio=target,
+                                                         met=bool(r_node >= target))
         rec["apply"] = am
         del st_last
         results[name] = rec

@@ -93,6 +93,7 @@ typedef struct {
   int32_t bucket_type[16];             /* 0 regular, 1 scattered interior, 2 Dirichlet wall, 3 Neumann wall */
   int64_t bucket_count[16];
   double build_ms[4];                  /* device time of: neighbour search, classify+order, local solves, total */
+  double bucket_solve_ms[16];          /* device time of each bucket's local solves (first pass) */
 } hsm_stencils_info;
 
 /*
@@ -177,6 +178,17 @@ hsm_status hsm_permute(const hsm_stencils *st, int32_t direction, int32_t dtype,
  */
 hsm_status hsm_apply_operator(const hsm_stencils *st, uint32_t op_mask, int32_t dtype, const void *u,
                               void *out, void *stream);
+
+/*
+ * hsm_apply_operator_buckets -- hsm_apply_operator restricted to the width
+ * buckets whose bit is set in bucket_mask (bit k = bucket k of
+ * hsm_stencils_info, internal order); the output rows of the other buckets
+ * are left as they were.  For per-bucket throughput, and for callers that
+ * update one kind of node only.  Same arguments, layouts and errors
+ * otherwise; bucket_mask 0 is HSM_E_INVALID.
+ */
+hsm_status hsm_apply_operator_buckets(const hsm_stencils *st, uint32_t op_mask, int32_t dtype,
+                                      uint32_t bucket_mask, const void *u, void *out, void *stream);
 
 /* Number of (operator, node) pairs one hsm_apply_operator call computes. */
 int64_t hsm_apply_node_count(const hsm_stencils *st, uint32_t op_mask);

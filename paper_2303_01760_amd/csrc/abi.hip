@@ -154,6 +154,7 @@ hsm_status hsm_stencils_get_info(const hsm_stencils *st, hsm_stencils_info *o) {
     o->bucket_count[k] = st->buckets[k].count;
   }
   for (int k = 0; k < 4; ++k) o->build_ms[k] = st->build_ms[k];
+  for (int k = 0; k < 16; ++k) o->bucket_solve_ms[k] = st->bucket_solve_ms[k];
   return HSM_OK;
 }
 
@@ -223,6 +224,19 @@ hsm_status hsm_apply_operator(const hsm_stencils *st, uint32_t op_mask, int32_t 
   if (!check_ptr(u, "u") || !check_ptr(out, "out")) return HSM_E_INVALID;
   if (u == out) { set_error(HSM_E_INVALID, "u and out must not overlap"); return HSM_E_INVALID; }
   return apply_impl(st, op_mask, dtype, u, out, (hipStream_t)stream);
+}
+
+hsm_status hsm_apply_operator_buckets(const hsm_stencils *st, uint32_t op_mask, int32_t dtype, uint32_t bucket_mask,
+                                      const void *u, void *out, void *stream) {
+  if (bucket_mask == 0) { set_error(HSM_E_INVALID, "bucket_mask selects no bucket"); return HSM_E_INVALID; }
+  if (!check_ptr(st, "stencils")) return HSM_E_INVALID;
+  if (op_mask == 0 || (op_mask & ~31u)) { set_error(HSM_E_INVALID, "op_mask must be a nonzero set of HSM_OP_* bits"); return HSM_E_INVALID; }
+  if (dtype != HSM_F64 && dtype != HSM_F32 && dtype != HSM_F32_COMP) { set_error(HSM_E_INVALID, "bad dtype"); return HSM_E_INVALID; }
+  if ((op_mask & HSM_OP_DZ) && st->d < 3) { set_error(HSM_E_INVALID, "HSM_OP_DZ needs d = 3"); return HSM_E_INVALID; }
+  if (st->N == 0) return HSM_OK;
+  if (!check_ptr(u, "u") || !check_ptr(out, "out")) return HSM_E_INVALID;
+  if (u == out) { set_error(HSM_E_INVALID, "u and out must not overlap"); return HSM_E_INVALID; }
+  return apply_impl(st, op_mask, dtype, u, out, (hipStream_t)stream, bucket_mask);
 }
 
 int64_t hsm_apply_node_count(const hsm_stencils *st, uint32_t op_mask) {

@@ -136,11 +136,14 @@ __global__ void k_to_f32(const double *src, float *dst, int64_t n) {
 
 }  // namespace
 
-void make_table(const hsm_stencils *st, BucketTable &tab, int bs, uint32_t type_mask, bool fp32) {
+void make_table(const hsm_stencils *st, BucketTable &tab, int bs, uint32_t type_mask, bool fp32,
+                uint32_t bucket_mask) {
   tab.nb = 0;
   tab.nblocks = 0;
-  for (const Bucket &B : st->buckets) {
+  for (size_t k = 0; k < st->buckets.size(); ++k) {
+    const Bucket &B = st->buckets[k];
     if (!((type_mask >> B.type) & 1u) || B.count == 0) continue;
+    if (k < 32 && !((bucket_mask >> k) & 1u)) continue;
     BucketDesc &d = tab.b[tab.nb++];
     d.start = B.start;
     d.count = B.count;
@@ -174,7 +177,7 @@ hsm_status ensure_w32(const hsm_stencils *st, hipStream_t s) {
 }
 
 hsm_status apply_impl(const hsm_stencils *st, uint32_t op_mask, int32_t dtype, const void *u, void *out,
-                      hipStream_t s) {
+                      hipStream_t s, uint32_t bucket_mask) {
   ApplyArgs a;
   const int d = st->d;
   a.nops = 0;
@@ -203,30 +206,58 @@ hsm_status apply_impl(const hsm_stencils *st, uint32_t op_mask, int32_t dtype, c
     if (rc) return rc;
   }
   const int which = fp32 ? 1 : 0;
-  if (st->dtab_blocks[which] < 0) {
-    BucketTable tab;
-    make_table(st, tab, kBS, 0xFu, fp32);
-    hsm_status rc = st->dtab[which].alloc(sizeof(BucketTable));
-    if (rc) return rc;
-    HSM_HIP(hipMemcpyAsync(st->dtab[which].p, &tab, sizeof(BucketTable), hipMemcpyHostToDevice, s));
-    HSM_HIP(hipStreamSynchronize(s));
-    st->dtab_blocks[which] = tab.nblocks;
-    st->bmap[which] = make_blockmap(tab);
+  const bool all = (bucket_mask | ~((st->buckets.size() >= 32) ? 0xFFFFFFFFu
+                                                                : ((1u << st->buckets.size()) - 1u))) == 0xFFFFFFFFu;
+  int64_t nblocks;
+  if (all) {
+    if (st->dtab_blocks[which] < 0) {
+      BucketTable tab;
+      make_table(st, tab, kBS, 0xFu, fp32);
+      hsm_status rc = st->dtab[which].alloc(sizeof(BucketTable));
+      if (rc) return rc;
+      HSM_HIP(hipMemcpyAsync(st->dtab[which].p, &tab, sizeof(BucketTable), hipMemcpyHostToDevice, s));
+      HSM_HIP(hipStreamSynchronize(s));
+      st->dtab_blocks[which] = tab.nblocks;
+      st->bmap[which] = make_blockmap(tab);
+    }
+    a.tab = st->dtab[which].as<BucketTable>();
+    a.bm = st->bmap[which];
+    nblocks = st->dtab_blocks[which];
+  } else {
+    // a subset of the buckets: its own table (the last one is kept)
+    const uint32_t key = (bucket_mask & 0x7FFFFFFFu) | (fp32 ? 0x80000000u : 0u);
+    if (st->dtab_sub_key != key || !st->dtab_sub.p) {
+      BucketTable tab;
+      make_table(st, tab, kBS, 0xFu, fp32, bucket_mask);
+      hsm_status rc = st->dtab_sub.alloc(sizeof(BucketTable));
+      if (rc) return rc;
+      HSM_HIP(hipMemcpyAsync(st->dtab_sub.p, &tab, sizeof(BucketTable), hipMemcpyHostToDevice, s));
+      HSM_HIP(hipStreamSynchronize(s));
+      st->dtab_sub_key = key;
+      st->dtab_sub_blocks = tab.nblocks;
+      st->bmap_sub = make_blockmap(tab);
+    }
+    a.tab = st->dtab_sub.as<BucketTable>();
+    a.bm = st->bmap_sub;
+    nblocks = st->dtab_sub_blocks;
   }
-  a.tab = st->dtab[which].as<BucketTable>();
-  a.bm = st->bmap[which];
   a.u = u;
   a.out = out;
   a.N = st->N;
-  const int64_t nblocks = st->dtab_blocks[which];
   if (nblocks == 0 || a.nops == 0) return HSM_OK;
   const dim3 g((unsigned)nblocks), b(kBS);
-  if (nl == 0) {            // only operators that are not stored (d/dz in 2D): zeros
-    const int64_t n = (int64_t)a.nops * a.N;
-    if (dtype == HSM_F64) hipLaunchKernelGGL(k_zero<double>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
-                                             static_cast<double *>(out), n);
-    else hipLaunchKernelGGL(k_zero<float>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
-                            static_cast<float *>(out), n);
+  if (nl == 0) {            // only operators that are not stored (d/dz in 2D): zeros on the selected rows
+    for (size_t k = 0; k < st->buckets.size(); ++k) {
+      const Bucket &B = st->buckets[k];
+      if (B.count == 0 || (k < 32 && !((bucket_mask >> k) & 1u))) continue;
+      const dim3 gz((unsigned)((B.count + 255) / 256));
+      for (int o = 0; o < a.nops; ++o) {
+        const int64_t off = (int64_t)o * a.N + B.start;
+        if (dtype == HSM_F64)
+          hipLaunchKernelGGL(k_zero<double>, gz, dim3(256), 0, s, static_cast<double *>(out) + off, B.count);
+        else hipLaunchKernelGGL(k_zero<float>, gz, dim3(256), 0, s, static_cast<float *>(out) + off, B.count);
+      }
+    }
   } else if (dtype == HSM_F64) launch_apply<double, Acc<double>>(nl, g, b, s, a);
   else if (dtype == HSM_F32) launch_apply<float, Acc<float>>(nl, g, b, s, a);
   else launch_apply<float, Dot2>(nl, g, b, s, a);

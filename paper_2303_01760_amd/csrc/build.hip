@@ -677,15 +677,30 @@ hsm_status build_stencils_impl(const hsm_nodeset *ns, int32_t mode, hipStream_t 
     int32_t *retry = d_retry.as<int32_t>();
     HSM_HIP(hipMemsetAsync(retry, 0, sizeof(int32_t), s));
     auto is_wall = [](const Bucket &B) { return B.type == B_DIR || B.type == B_NEU; };
-    for (const Bucket &B : st->buckets) {
+    // each bucket's solves between events of their own (per-bucket solve rates)
+    const size_t nbk = st->buckets.size() < 16 ? st->buckets.size() : 16;
+    std::vector<hipEvent_t> bev(nbk + 1, nullptr);
+    for (auto &e : bev) HSM_HIP(hipEventCreate(&e));
+    for (size_t k = 0; k < st->buckets.size(); ++k) {
+      const Bucket &B = st->buckets[k];
+      if (k < nbk) HSM_HIP(hipEventRecord(bev[k], s));
       if ((rc = solve_bucket(st, B, st->x.as<double>(), st->normal.as<double>(), d_status.as<DevStatus>(), s,
-                             is_wall(B) ? retry + 1 : nullptr, retry)))
+                             is_wall(B) ? retry + 1 : nullptr, retry))) {
+        for (auto &e : bev) (void)hipEventDestroy(e);
         return rc;
+      }
     }
+    HSM_HIP(hipEventRecord(bev[nbk], s));
     int32_t nretry = 0;
     HSM_HIP(hipMemcpyAsync(&nretry, retry, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HSM_HIP(hipMemcpyAsync(&hs, d_status.p, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
     HSM_HIP(hipStreamSynchronize(s));
+    for (size_t k = 0; k < nbk; ++k) {
+      float ms_k = 0.0f;
+      HSM_HIP(hipEventElapsedTime(&ms_k, bev[k], bev[k + 1]));
+      st->bucket_solve_ms[k] = ms_k;
+    }
+    for (auto &e : bev) HSM_HIP(hipEventDestroy(e));
     if (nretry > 0 && !hs.bits) {
       // the fallback: those wall nodes take degree m-1 on the same stencil
       // (walls need first derivatives only); failures now latch

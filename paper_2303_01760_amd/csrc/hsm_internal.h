@@ -121,6 +121,11 @@ struct hsm_stencils {
   mutable hsm::DBuf dtab[2];     // device copies of the apply bucket table (FP64, FP32 weights)
   mutable int64_t dtab_blocks[2] = {-1, -1};
   mutable hsm::BlockMap bmap[2];
+  mutable hsm::DBuf dtab_sub;          // the table of the last bucket-masked apply
+  mutable uint32_t dtab_sub_key = 0;   // its bucket mask and precision (bit 31: FP32); 0: none
+  mutable int64_t dtab_sub_blocks = 0;
+  mutable hsm::BlockMap bmap_sub;
+  double bucket_solve_ms[16] = {};     // device time of each bucket's first solve pass
 };
 
 namespace hsm {
@@ -330,7 +335,8 @@ inline BlockMap make_blockmap(const BucketTable &tab) {
 
 // Fills tab for all buckets of st (or only those whose type bit is in type_mask),
 // with `bs` threads per block and one node per thread.  fp32 selects w32.
-void make_table(const hsm_stencils *st, BucketTable &tab, int bs, uint32_t type_mask, bool fp32);
+void make_table(const hsm_stencils *st, BucketTable &tab, int bs, uint32_t type_mask, bool fp32,
+                uint32_t bucket_mask = 0xFFFFFFFFu);
 
 // ---------------------------------------------------------------- scan ----
 // Exclusive prefix sum of n int32 values into int64 out[n+1] (out[n] = total).
@@ -347,7 +353,7 @@ hsm_status solve_bucket_list(const hsm_stencils *st, const Bucket &b, const doub
 hsm_status cond_bucket(const hsm_stencils *st, const Bucket &b, double *kappa, hipStream_t s, const int32_t *list,
                        int64_t nlist);
 hsm_status apply_impl(const hsm_stencils *st, uint32_t op_mask, int32_t dtype, const void *u, void *out,
-                      hipStream_t s);
+                      hipStream_t s, uint32_t bucket_mask = 0xFFFFFFFFu);
 hsm_status ensure_w32(const hsm_stencils *st, hipStream_t s);
 
 inline int nmono(int d, int m) {

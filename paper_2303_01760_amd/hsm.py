@@ -36,7 +36,8 @@ class StencilsInfoC(ctypes.Structure):
                 ("n_buckets", ctypes.c_int32), ("n_nodes", ctypes.c_int64), ("nnz", ctypes.c_int64),
                 ("n_regular", ctypes.c_int64), ("n_scattered", ctypes.c_int64), ("n_boundary", ctypes.c_int64),
                 ("n_wall_fallback", ctypes.c_int64), ("bucket_width", ctypes.c_int32 * 16), ("bucket_type", ctypes.c_int32 * 16),
-                ("bucket_count", ctypes.c_int64 * 16), ("build_ms", ctypes.c_double * 4)]
+                ("bucket_count", ctypes.c_int64 * 16), ("build_ms", ctypes.c_double * 4),
+                ("bucket_solve_ms", ctypes.c_double * 16)]
 
 
 class SimParamsC(ctypes.Structure):
@@ -59,7 +60,8 @@ _lib = None
 SYMBOLS = ["hsm_build_stencils", "hsm_stencils_get_info", "hsm_stencils_export", "hsm_permute",
            "hsm_apply_operator", "hsm_apply_node_count", "hsm_sim_create", "hsm_step", "hsm_sim_get_stats",
            "hsm_sim_read", "hsm_sim_destroy", "hsm_stencils_destroy", "hsm_last_error", "hsm_last_error_node",
-           "hsm_version", "hsm_sim_phase_times", "hsm_sim_sizes", "hsm_stream_copy", "hsm_stencils_condition"]
+           "hsm_version", "hsm_sim_phase_times", "hsm_sim_sizes", "hsm_stream_copy", "hsm_stencils_condition",
+           "hsm_apply_operator_buckets"]
 PHASES = ["pre", "krylov_iter", "post", "krylov_batch"]
 
 
@@ -107,6 +109,8 @@ def lib():
         L.hsm_stream_copy.argtypes = [_p, _p, ctypes.c_int64, _p]
         L.hsm_stencils_condition.restype = st
         L.hsm_stencils_condition.argtypes = [_p, _p, _p]
+        L.hsm_apply_operator_buckets.restype = st
+        L.hsm_apply_operator_buckets.argtypes = [_p, ctypes.c_uint32, ctypes.c_int32, ctypes.c_uint32, _p, _p, _p]
         L.hsm_version.restype = ctypes.c_char_p
         L.hsm_version.argtypes = []
         _lib = L
@@ -157,7 +161,7 @@ class Stencils:
                     n_regular=o.n_regular, n_scattered=o.n_scattered, n_boundary=o.n_boundary,
                     n_wall_fallback=o.n_wall_fallback,
                     buckets=[(o.bucket_type[k], o.bucket_width[k], o.bucket_count[k]) for k in range(nb)],
-                    build_ms=list(o.build_ms))
+                    build_ms=list(o.build_ms), bucket_solve_ms=list(o.bucket_solve_ms[:nb]))
 
     def export(self, stream=None) -> dict:
         """Classes, CSR stencils (caller numbering) and weights [d+2, nnz] as numpy arrays."""
@@ -196,6 +200,17 @@ class Stencils:
         """hsm_stencils_condition: kappa(M) of every node's local system, caller order."""
         out = torch.empty(self.n, dtype=torch.float64, device=torch.device("cuda"))
         _check(lib().hsm_stencils_condition(self._h, _dptr(out), _stream(stream)))
+        return out
+
+    def apply_buckets(self, u: torch.Tensor, op_mask: int, bucket_mask: int, dtype: int = F64, out=None,
+                      stream=None) -> torch.Tensor:
+        """hsm_apply_operator_buckets: Eq. (1) on the buckets in bucket_mask only (internal order)."""
+        nops = bin(op_mask & 31).count("1")
+        tdt = torch.float64 if dtype == F64 else torch.float32
+        if out is None:
+            out = torch.zeros((nops, self.n), dtype=tdt, device=u.device)
+        _check(lib().hsm_apply_operator_buckets(self._h, int(op_mask), int(dtype), int(bucket_mask), _dptr(u),
+                                                _dptr(out), _stream(stream)))
         return out
 
     def node_count(self, op_mask: int) -> int:

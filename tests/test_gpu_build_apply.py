@@ -337,3 +337,33 @@ def test_condition_numbers_of_wall_fallback_nodes():
     err = np.abs(kg[q] - ko) / ko
     print(f"kappa 3D h=0.02 (fallback nodes included): max rel err {err.max():.2e}")
     assert np.all(err <= _kappa_tol(ko))
+
+
+def test_bucket_masked_apply_adds_up_to_the_full_apply():
+    # hsm_apply_operator_buckets: each bucket alone writes exactly its rows of
+    # the full apply and leaves every other row as it was
+    hsm = _hsm()
+    s = ng.obstacles2d(h=0.02, n_obst=3, rmin=0.08, rmax=0.12, band=0.1, seed=47)
+    x, kind, nrm = _dev(s)
+    st = hsm.build_stencils(x, kind, nrm, s.h, 2)
+    info = st.info()
+    u = st.to_internal(torch.tensor(np.sin(3 * s.x[0]) * np.cos(2 * s.x[1]), device=x.device))
+    ops = hsm.OP_DX | hsm.OP_DY | hsm.OP_LAP | hsm.OP_DN
+    for dtype, td in ((hsm.F64, torch.float64), (hsm.F32_COMP, torch.float32)):
+        uu = u if dtype == hsm.F64 else u.float()
+        full = st.apply(uu, ops, dtype)
+        acc = torch.full_like(full, float("nan"))
+        start = 0
+        for kb, (_, _, cnt) in enumerate(info["buckets"]):
+            if cnt == 0:
+                continue
+            before = acc.clone()
+            st.apply_buckets(uu, ops, 1 << kb, dtype, out=acc)
+            rows = slice(start, start + cnt)
+            assert torch.equal(acc[:, rows], full[:, rows])
+            mask = torch.ones(s.n, dtype=torch.bool, device=x.device)
+            mask[rows] = False
+            assert torch.equal(acc[:, mask].isnan(), before[:, mask].isnan())
+            start += cnt
+        assert torch.equal(acc, full)
+    assert all(ms > 0 for ms, (_, _, c) in zip(info["bucket_solve_ms"], info["buckets"]) if c > 0)

@@ -716,3 +716,30 @@ def test_condition_number_invariances():
         assert sv[0] / sv[-1] == pytest.approx(k0, rel=1e-9)
     lam = np.abs(np.linalg.eigvalsh(O.local_matrix(xs, 2)))
     assert lam.max() / lam.min() == pytest.approx(k0, rel=1e-9)
+
+
+def test_refined_and_split_layouts():
+    # h-refinement (Sections 4.2, 4.3): circle nodes at spacing h_s; no lattice
+    # node within the refinement distance h_r*delta_h of a circle; every fill
+    # node keeps the spacing of its place (s(x) = h_s + (h_r - h_s) min(1,
+    # dist / (h_r delta_h))) to every node placed before it, so no two fill
+    # nodes are closer than the smaller of their spacings.
+    h_r, ratio, dh = 0.05, 3.0, 4.0
+    q = ng.refined2d(h_r=h_r, ratio=ratio, delta_h=dh, n_obst=2, rmin=0.08, rmax=0.12, seed=91)
+    h_s = h_r / ratio
+    c, r = q.obstacles[:, :2], q.obstacles[:, 2]
+    dist = (np.sqrt(((q.x.T[:, None, :] - c[None]) ** 2).sum(-1)) - r[None]).min(1)
+    for k in range(len(r)):
+        on = q.group == 6 + k
+        assert on.sum() == int(np.ceil(2 * np.pi * r[k] / h_s))
+    assert np.all(dist[q.origin == 0] >= h_r * dh)
+    sp = h_s + (h_r - h_s) * np.clip(dist / (h_r * dh), 0.0, 1.0)
+    fill = np.nonzero(q.origin == 2)[0]
+    dd = np.sqrt(((q.x.T[fill, None, :] - q.x.T[None, fill, :]) ** 2).sum(-1))
+    np.fill_diagonal(dd, np.inf)
+    assert np.all(dd >= np.minimum(sp[fill][:, None], sp[fill][None, :]) * (1 - 1e-12))
+    # the split layout (Section 4.1): lattice only beyond h*delta_h, fill only before it
+    s = ng.dvd2d_split(0.05, 6, "vertical")
+    assert np.all(s.x[0][s.origin == 0] >= 0.05 * 6) and np.all(s.x[0][s.origin == 2] < 0.05 * 6)
+    s = ng.dvd2d_split(0.05, 6, "horizontal")
+    assert np.all(s.x[1][s.origin == 0] >= 0.05 * 6) and np.all(s.x[1][s.origin == 2] < 0.05 * 6)
