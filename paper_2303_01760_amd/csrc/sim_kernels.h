@@ -769,7 +769,7 @@ __device__ __forceinline__ void pv_rows(const SimArgs &a, const BlockDesc &b, bo
             [&](int, double wj, double rj) __attribute__((always_inline)) { acc = fma(wj, rj, acc); },
             [&]() __attribute__((always_inline)) { pin(acc); });
       } else {
-        gather_chunks<W>(
+        gather_chunks<W, 8>(
             b.idx, cnt32, t32, wl,
             [&](int32_t nb) __attribute__((always_inline)) {
               return Pack<double2, 2>{{ld_at<double2>(STb, nb), ld_at<double2>(PVb, nb)}};
