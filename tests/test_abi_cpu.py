@@ -57,3 +57,24 @@ def test_apply_rejects_bad_arguments():
     assert L.hsm_apply_operator(None, 1, 0, None, None, None) == hsm.E_INVALID
     assert L.hsm_permute(None, 0, 0, None, None, None) == hsm.E_INVALID
     assert L.hsm_step(None, 1, None) == hsm.E_INVALID
+
+
+def test_size_limits_and_empty_selections_are_rejected_on_the_host():
+    # the largest node count the 32-bit buffer offsets allow, an empty domain,
+    # and an apply that selects no bucket are refused before any device work
+    import numpy as np
+    from paper_2303_01760_amd import hsm
+    L = hsm.lib()
+    out = ctypes.c_void_p()
+    h = np.array([0.1]); m = np.array([2], np.int32)
+    too_many = np.array([0, (1 << 28) - 1], np.int64)            # HSM_MAX_NODES + 1
+    ns = hsm.NodeSetC(2, 1, too_many.ctypes.data, 1, 1, 1, h.ctypes.data, m.ctypes.data, None)
+    assert L.hsm_build_stencils(ctypes.byref(ns), 0, None, ctypes.byref(out)) == hsm.E_INVALID
+    assert b"too many nodes" in L.hsm_last_error()
+    empty = np.array([0, 0], np.int64)
+    ns = hsm.NodeSetC(2, 1, empty.ctypes.data, 1, 1, 1, h.ctypes.data, m.ctypes.data, None)
+    assert L.hsm_build_stencils(ctypes.byref(ns), 0, None, ctypes.byref(out)) == hsm.E_INVALID
+    assert out.value is None
+    assert L.hsm_apply_operator_buckets(None, 1, 0, 0, None, None, None) == hsm.E_INVALID
+    assert b"no bucket" in L.hsm_last_error()
+    assert L.hsm_stencils_condition(None, None, None) == hsm.E_INVALID
