@@ -248,6 +248,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-all-scattered", action="store_true")
     ap.add_argument("--skip-fp32-form", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default tile of the internal node order")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="summarise two rocprofv3 --pmc runs into the traffic record and exit")
     ap.add_argument("--trace-summary", nargs=3, metavar=("TRACE_CSV", "STATS_CSV", "OUT"),
@@ -309,9 +310,21 @@ def main():
     del src, dst
     log(f"stream copy: {copy_gbs:.0f} GB/s")
 
+    # the tile of the internal node order, picked per layout by the autotuner (outside the timed region)
+    tiles, tuning = {}, {}
+    if not args.no_autotune:
+        from paper_2303_01760_amd import autotune
+        for mode in ([hsm.MODE_HYBRID] + ([] if args.skip_all_scattered else [hsm.MODE_ALL_SCATTERED])):
+            best, tms = autotune.tune_tile(x, kind, nrm, hdom, m, mode=mode, domain_offsets=dom_off)
+            tiles[mode] = best
+            tuning["hybrid" if mode == hsm.MODE_HYBRID else "all_scattered"] = dict(
+                chosen_tile_log2=best, fused_apply_ms={str(k): v for k, v in tms.items()})
+            log(f"autotune (mode {mode}): tile 2^{best} cells per axis; apply ms {tms}")
+
     def one_step(mode, rec, field_dtype=hsm.F64, keep=False):
         t0 = time.perf_counter()
-        st = hsm.build_stencils(x, kind, nrm, hdom, m, mode=mode, domain_offsets=dom_off)
+        st = hsm.build_stencils(x, kind, nrm, hdom, m, mode=mode, domain_offsets=dom_off,
+                                tile_log2=tiles.get(mode, 0))
         rec["build_s"] += time.perf_counter() - t0
         info = st.info()
         rec["build_dev_ms"] += info["build_ms"][0] + info["build_ms"][1] + info["build_ms"][2]
@@ -518,6 +531,8 @@ def main():
                solves_per_s=hy["solves"] / hy["build_s"], solves_per_s_device=hy["solves"] / (hy["solve_dev_ms"] * 1e-3),
                apply=hy["apply"],
                roofline=roofline)
+    if tuning:
+        out["autotune"] = tuning
     if stepping:
         out["krylov_iters_per_time_step"] = hy["krylov_iters"] / (args.steps * args.time_steps)
         out["phase_mean_ms"] = {k: v[0] for k, v in pt.items()}

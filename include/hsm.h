@@ -80,6 +80,8 @@ typedef struct {
   const double *host_h_regular;        /* [n_domains] regular lattice spacing h_r (> 0) */
   const int32_t *host_m;               /* [n_domains] monomial degree of RBF-FD stencils */
   const int32_t *host_n;               /* [n_domains] RBF-FD stencil size, or NULL for 2 C(m+d, m) */
+  int32_t tile_log2;                   /* internal node order: tiles of 2^tile_log2 search cells per axis
+                                          (1..5); 0 for the default (8x8 in 2D, 4x4x4 in 3D) */
 } hsm_nodeset;
 
 /* Summary of a built stencil set. */

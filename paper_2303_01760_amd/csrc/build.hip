@@ -27,7 +27,8 @@ struct GridDesc {
   double origin[3];
   double cs;          // cell edge
   int32_t dims[3];    // cells per axis
-  int32_t ntiles[3];  // tiles per axis (8x8 in 2D, 4x4x4 in 3D)
+  int32_t ntiles[3];  // tiles per axis
+  int32_t tl;         // tile edge 2^tl cells (default 8x8 in 2D, 4x4x4 in 3D)
   int64_t cell_off;   // first global cell id of this domain
 };
 
@@ -41,15 +42,18 @@ __device__ __forceinline__ int find_domain(int64_t i, const int64_t *off, int nd
 }
 
 // Cells are numbered tile by tile so that the cell-sorted node order is
-// spatially compact (8x8 tiles in 2D, 4x4x4 in 3D, tiles row-major).
+// spatially compact (tiles of 2^tl cells per axis, row-major; by default
+// 8x8 in 2D and 4x4x4 in 3D).
 template <int D>
 __device__ __forceinline__ int64_t cell_id(const GridDesc &g, const int *c) {
+  const int L = g.tl, msk = (1 << L) - 1;
   if (D == 2) {
-    int64_t t = (int64_t)(c[1] >> 3) * g.ntiles[0] + (c[0] >> 3);
-    return g.cell_off + (t << 6) + ((c[1] & 7) << 3) + (c[0] & 7);
+    const int64_t t = (int64_t)(c[1] >> L) * g.ntiles[0] + (c[0] >> L);
+    return g.cell_off + (t << (2 * L)) + ((int64_t)(c[1] & msk) << L) + (c[0] & msk);
   } else {
-    int64_t t = ((int64_t)(c[2] >> 2) * g.ntiles[1] + (c[1] >> 2)) * g.ntiles[0] + (c[0] >> 2);
-    return g.cell_off + (t << 6) + ((c[2] & 3) << 4) + ((c[1] & 3) << 2) + (c[0] & 3);
+    const int64_t t = ((int64_t)(c[2] >> L) * g.ntiles[1] + (c[1] >> L)) * g.ntiles[0] + (c[0] >> L);
+    return g.cell_off + (t << (3 * L)) + ((int64_t)(c[2] & msk) << (2 * L)) + ((int64_t)(c[1] & msk) << L) +
+           (c[0] & msk);
   }
 }
 
@@ -509,6 +513,7 @@ hsm_status build_stencils_impl(const hsm_nodeset *ns, int32_t mode, hipStream_t 
   int64_t ncells = 0;
   for (int k = 0; k < nd; ++k) {
     GridDesc &g = grids[k];
+    g.tl = ns->tile_log2 > 0 ? ns->tile_log2 : (d == 2 ? 3 : 2);
     const int64_t cnt = ns->host_domain_offsets[k + 1] - ns->host_domain_offsets[k];
     double ext[3] = {0, 0, 0}, vol = 1.0;
     for (int a = 0; a < d; ++a) {
@@ -529,7 +534,7 @@ hsm_status build_stencils_impl(const hsm_nodeset *ns, int32_t mode, hipStream_t 
       cells = 1;
       for (int a = 0; a < d; ++a) {
         g.dims[a] = (int32_t)std::floor(ext[a] / cs) + 1;
-        const int tile = (d == 2) ? 8 : 4;
+        const int tile = 1 << g.tl;
         g.ntiles[a] = (g.dims[a] + tile - 1) / tile;
         cells *= (int64_t)g.ntiles[a] * tile;
       }

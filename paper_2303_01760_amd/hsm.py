@@ -28,7 +28,7 @@ _p = ctypes.c_void_p
 class NodeSetC(ctypes.Structure):
     _fields_ = [("d", ctypes.c_int32), ("n_domains", ctypes.c_int32),
                 ("host_domain_offsets", _p), ("x", _p), ("kind", _p), ("normal", _p),
-                ("host_h_regular", _p), ("host_m", _p), ("host_n", _p)]
+                ("host_h_regular", _p), ("host_m", _p), ("host_n", _p), ("tile_log2", ctypes.c_int32)]
 
 
 class StencilsInfoC(ctypes.Structure):
@@ -229,7 +229,7 @@ class Stencils:
 
 
 def build_stencils(x: torch.Tensor, kind: torch.Tensor, normal: torch.Tensor, h, m, mode=MODE_HYBRID,
-                   domain_offsets=None, n=None, stream=None) -> Stencils:
+                   domain_offsets=None, n=None, tile_log2=0, stream=None) -> Stencils:
     """hsm_build_stencils on device tensors x [d,N] f64, kind [N] u8, normal [d,N] f64."""
     d, N = x.shape
     offs = np.asarray(domain_offsets if domain_offsets is not None else [0, N], np.int64)
@@ -239,7 +239,7 @@ def build_stencils(x: torch.Tensor, kind: torch.Tensor, normal: torch.Tensor, h,
     ns_ = None if n is None else np.ascontiguousarray(np.broadcast_to(np.asarray(n, np.int32), (nd,)))
     c = NodeSetC(d, nd, offs.ctypes.data, _dptr(x, torch.float64), _dptr(kind, torch.uint8),
                  _dptr(normal, torch.float64), hs.ctypes.data, ms.ctypes.data,
-                 None if ns_ is None else ns_.ctypes.data)
+                 None if ns_ is None else ns_.ctypes.data, int(tile_log2))
     h_out = _p()
     _check(lib().hsm_build_stencils(ctypes.byref(c), int(mode), _stream(stream), ctypes.byref(h_out)))
     return Stencils(h_out.value, d, N)
