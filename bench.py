@@ -121,8 +121,8 @@ def _kname(n):
 def trace_summary(trace_csv, stats_csv, warmup, steps, chunk, command, out_path):
     """Summarise a rocprofv3 --kernel-trace run of this script: the overall
     per-kernel statistics; per-kernel means inside the timed region of the
-    hybrid layout (delimited by the k_bbox launch that opens every stencil
-    build); and, as the stepper's own events measure it, the mean time of one
+    hybrid layout (delimited by the k_bbox launches that open the stencil
+    builds of the benchmark steps); and, as the stepper's own events measure it, the mean time of one
     BiCGSTAB iteration: the span between the ends of consecutive k_chunk_end
     launches (one batch of `chunk` iterations) over the batches in which every
     k_bicg_pv launch was busy (at least 3 us; launches queued past
@@ -130,9 +130,14 @@ def trace_summary(trace_csv, stats_csv, warmup, steps, chunk, command, out_path)
     import csv
     rows = list(csv.DictReader(open(trace_csv)))
     rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    # every stencil build opens with k_bbox; the builds that a time step follows (k_predict before the
+    # next build) are the benchmark steps, the others (the tile autotuner's) are skipped
     bbox = [int(r["Start_Timestamp"]) for r in rows if "k_bbox" in r["Kernel_Name"]]
-    end = lambda k: bbox[k] if len(bbox) > k else float("inf")
-    t0, t1 = bbox[warmup], end(warmup + steps)
+    pred = [int(r["Start_Timestamp"]) for r in rows if "k_predict" in r["Kernel_Name"]]
+    nxt = bbox[1:] + [float("inf")]
+    stepping = [b for b, e in zip(bbox, nxt) if any(b <= p < e for p in pred)]
+    end = lambda k: stepping[k] if len(stepping) > k else float("inf")
+    t0, t1 = stepping[warmup], end(warmup + steps)
     win = [r for r in rows if t0 <= int(r["Start_Timestamp"]) < t1]
 
     per = {}
