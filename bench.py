@@ -269,7 +269,7 @@ def main():
                       args.trace_command, args.trace_summary[2])
         return 0
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (pass --gpus 1)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path (pass --gpus 1)", file=sys.stderr)
         return 2
 
     import numpy as np
