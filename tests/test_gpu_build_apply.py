@@ -384,3 +384,54 @@ def test_tile_of_the_internal_order_changes_only_the_order():
             assert np.array_equal(ex[k], ref[k]), (L, k)
     best, times = autotune.tune_tile(x, kind, nrm, s.h, 2, reps=3)
     assert best in times and all(t > 0 for t in times.values())
+
+
+def _sampled_check(s, st, m, q, dom_off=None, hs=None):
+    """Classes, stencils and weights of the sampled nodes against the oracle, and
+    the FP64 apply at those nodes against the oracle's sum over its own stencil."""
+    hsm = _hsm()
+    ex = st.export()
+    ora = O.build(s.x, s.kind, s.normal, s.h if hs is None else hs, m, queries=q, dom_off=dom_off)
+    assert np.array_equal(ex["cls"][q], ora["cls"])
+    u = np.sin(3 * s.x[0]) * np.cos(2 * s.x[1]) + s.x[-1]
+    dev = torch.device("cuda")
+    ui = st.to_internal(torch.tensor(u, device=dev))
+    ops = hsm.OP_DX | hsm.OP_DY | hsm.OP_LAP if s.x.shape[0] == 2 else hsm.OP_DX | hsm.OP_DY | hsm.OP_DZ | hsm.OP_LAP
+    nops = bin(ops).count("1")
+    out = st.apply(ui, ops, hsm.F64)
+    got = np.stack([st.to_caller(out[k].contiguous()).cpu().numpy() for k in range(nops)])
+    for k, i in enumerate(q):
+        a, b = ex["off"][i], ex["off"][i + 1]
+        wdt = ora["width"][k]
+        assert b - a == wdt
+        idx = ora["idx"][k, :wdt]
+        assert np.array_equal(ex["idx"][a:b], idx)
+        for op in range(nops):
+            ref = ora["w"][k, op, :wdt]
+            assert np.abs(ex["w"][op, a:b] - ref).max() <= WTOL * np.abs(ref).max()
+            want = float(np.dot(ref, u[idx]))
+            assert abs(got[op, i] - want) <= 1e-12 * float(np.abs(ref) @ np.abs(u[idx]))
+
+
+@pytest.mark.parametrize("case", ["spheres3d_h0.01", "obstacles2d_h0.001_m4", "batch512"])
+def test_full_size_sampled_parity(case):
+    # the benchmark node sets at full size: a seeded sample of nodes (walls
+    # included) against the oracle, which builds each sampled node by brute
+    # force over its domain
+    hsm = _hsm()
+    rng = np.random.default_rng(61)
+    if case == "batch512":
+        b = ng.batch2d()
+        x, kind, nrm = (torch.tensor(b.x, device="cuda"), torch.tensor(b.kind, device="cuda"),
+                        torch.tensor(b.normal, device="cuda"))
+        st = hsm.build_stencils(x, kind, nrm, b.h, b.m, domain_offsets=b.off)
+        q = np.unique(np.concatenate([rng.choice(b.n, 60, replace=False), b.off[:-1][::64], b.off[1:][::64] - 1,
+                                      rng.choice(np.where(b.kind != 0)[0], 20, replace=False)]))
+        _sampled_check(b, st, b.m, q, dom_off=b.off, hs=b.h)
+        return
+    s, m = (ng.obstacles3d(h=0.01), 2) if case == "spheres3d_h0.01" else (ng.obstacles2d(h=0.001), 4)
+    x, kind, nrm = _dev(s)
+    st = hsm.build_stencils(x, kind, nrm, s.h, m)
+    q = np.unique(np.concatenate([rng.choice(s.n, 60, replace=False),
+                                  rng.choice(np.where(s.kind != 0)[0], 20, replace=False), [0, s.n - 1]]))
+    _sampled_check(s, st, m, q)

@@ -457,3 +457,32 @@ def test_large_2d_steps_properties():
                   f"node-applies {stats['node_applies']}")
         for a, b in zip(*res):
             assert np.array_equal(a, b)
+
+
+def test_full_size_step_properties():
+    # the benchmark's 2D node set at full size (167k nodes), two steps from a
+    # perturbed temperature: properties every step has at any size (walls hold
+    # v = 0 and their Dirichlet T, Neumann walls have dT/dn = 0 to rounding,
+    # the pressure has zero mean and met its residual target)
+    hsm = _hsm()
+    s = ng.obstacles2d(h=0.002)
+    st = _build(s)
+    dev = torch.device("cuda")
+    T0 = np.where(s.kind == 1, s.tbc, 0.5 + 0.1 * np.sin(5 * s.x[0]) * np.cos(4 * s.x[1]))
+    sim = hsm.Sim(st, torch.zeros((2, s.n), dtype=torch.float64, device=dev), torch.tensor(T0, device=dev),
+                  Ra=1e5, Pr=0.71, dt=0.1 * s.h ** 2 / 2, T_ref=0.5, krylov_tol=1e-10, krylov_maxiter=200000)
+    sim.step(2)
+    stats = sim.stats()
+    assert stats["status"] == 0 and stats["last_relres"] <= 1e-10
+    v, T, p = [a.cpu().numpy() for a in sim.read()]
+    assert np.all(np.isfinite(v)) and np.all(np.isfinite(T)) and np.all(np.isfinite(p))
+    wall = s.kind != 0
+    assert np.all(v[:, wall] == 0.0)
+    assert np.array_equal(T[s.kind == 1], T0[s.kind == 1])
+    assert abs(p.sum()) <= 1e-9 * np.abs(p).sum()
+    dn = st.to_caller(st.apply(st.to_internal(torch.tensor(T, device=dev)), hsm.OP_DN)[0].contiguous()).cpu().numpy()
+    ex = st.export()
+    neu = np.nonzero(s.kind == 2)[0]
+    scale = np.array([np.abs(ex["w"][s.d + 1, ex["off"][i]:ex["off"][i + 1]]).sum() for i in neu]) * np.abs(T).max()
+    assert np.all(np.abs(dn[neu]) <= 1e-12 * scale)
+    assert np.abs(v[:, ~wall]).max() > 0.0
