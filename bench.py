@@ -476,7 +476,7 @@ def main():
                            max_rel=float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)))
         fp32 = dict(status=("ok" if rec.get("status", 0) == 0 else
                             f"hsm status {rec['status']}: FP32 velocity storage went non-finite (rounding of v* "
-                            f"divided by dt; see the design notes)"),
+                            f"divided by dt overflows near a wall node with a large Neumann weight ratio)"),
                     ms_per_step=el * 1e3, value=rec["applies"] / el,
                     phase_mean_ms={k: (tot / n if n else float("nan")) for k, (tot, n) in rec["ptimes"].items()},
                     error_vs_fp64_gpu_after_time_steps=err, time_steps=args.time_steps)

@@ -233,10 +233,12 @@ typedef struct {
  * p [N] (may be NULL for zero) are device arrays in the caller's numbering,
  * copied in; T at Dirichlet nodes is their wall temperature.  The pressure
  * problem of each step is the Poisson equation of the projection with
- * dp/dn = 0 at walls and zero mean in every domain: each domain of the stencil
- * set has its own border row and column (readings in the design notes), and
- * all domains advance together with the same dt.  Uses `stream` for the
- * copies and synchronises it.
+ * dp/dn = 0 at walls and zero mean in every domain: each domain k of the
+ * stencil set has its own border row and column with entries 1/sqrt(N_k)
+ * (the zero-mean constraint with a Lagrange multiplier, scaled so that the
+ * bordered matrix keeps an O(1) eigenvalue pair), and all domains advance
+ * together with the same dt.  Uses `stream` for the copies and synchronises
+ * it.
  */
 hsm_status hsm_sim_create(const hsm_stencils *st, const hsm_sim_params *prm, const double *v,
                           const double *T, const double *p, void *stream, hsm_sim **out);

@@ -27,8 +27,9 @@
  *   ora_apply        Eq. (1): sum_i w_i u(x_i), in stencil order.
  *   ora_step         explicit Euler Boussinesq step with Chorin projection
  *                    (Section 3, Eqs. (2)-(4)); pressure Poisson problem with
- *                    Neumann walls and zero mean, solved by BiCGSTAB or by a
- *                    dense LU (readings listed in the design notes).
+ *                    Neumann walls and zero mean (a border row and column
+ *                    of 1/sqrt(N) per domain), solved by BiCGSTAB or by a
+ *                    dense LU.
  *   ora_nusselt      Eq. (5), averaged over a node list.
  *   ora_dense_lu_*   dense LU with partial pivoting (used by the above).
  *
