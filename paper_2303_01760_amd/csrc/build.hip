@@ -68,10 +68,17 @@ __device__ __forceinline__ void cell_coords(const GridDesc &g, const double *p, 
 }
 
 // ---------------------------------------------------------------- bbox ----
+// Per-domain bounding boxes in two passes: block b covers chunk b % P of
+// domain b / P (P chunks per domain) and writes its min and max; then one
+// thread per (domain, bound component) folds the P partial values.
 template <int D>
-__global__ __launch_bounds__(256) void k_bbox(const double *x, int64_t N, const int64_t *off, double *bbox) {
-  const int dm = blockIdx.x;
-  const int64_t lo = off[dm], hi = off[dm + 1];
+__global__ __launch_bounds__(256) void k_bbox_part(const double *x, int64_t N, const int64_t *off, int P,
+                                                   double *part) {
+  const int64_t b = blockIdx.x;
+  const int64_t dm = b / P, j = b % P;
+  const int64_t lo0 = off[dm], hi0 = off[dm + 1];
+  const int64_t chunk = (hi0 - lo0 + P - 1) / P;
+  const int64_t lo = lo0 + j * chunk, hi = min(lo + chunk, hi0);
   __shared__ double smin[256][D], smax[256][D];
   double mn[D], mx[D];
 #pragma unroll
@@ -79,25 +86,53 @@ __global__ __launch_bounds__(256) void k_bbox(const double *x, int64_t N, const 
   for (int64_t i = lo + threadIdx.x; i < hi; i += 256)
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-      double v = x[a * N + i];
+      const double v = x[a * N + i];
       mn[a] = fmin(mn[a], v);
       mx[a] = fmax(mx[a], v);
     }
 #pragma unroll
   for (int a = 0; a < D; ++a) { smin[threadIdx.x][a] = mn[a]; smax[threadIdx.x][a] = mx[a]; }
   __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s)
+  for (int st = 128; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st)
 #pragma unroll
       for (int a = 0; a < D; ++a) {
-        smin[threadIdx.x][a] = fmin(smin[threadIdx.x][a], smin[threadIdx.x + s][a]);
-        smax[threadIdx.x][a] = fmax(smax[threadIdx.x][a], smax[threadIdx.x + s][a]);
+        smin[threadIdx.x][a] = fmin(smin[threadIdx.x][a], smin[threadIdx.x + st][a]);
+        smax[threadIdx.x][a] = fmax(smax[threadIdx.x][a], smax[threadIdx.x + st][a]);
       }
     __syncthreads();
   }
-  if (threadIdx.x == 0)
+  if (threadIdx.x < 2 * D) {
+    const int a = threadIdx.x % D, hiside = threadIdx.x / D;
+    part[b * 6 + hiside * 3 + a] = hiside ? smax[0][a] : smin[0][a];
+  }
+}
+
+// bbox[(dm * 2 + side) * 3 + a], a < D: side 0 the minimum, 1 the maximum;
+// one wave per domain, lanes striding over the P partial boxes
+template <int D>
+__global__ __launch_bounds__(64) void k_bbox_fold(const double *part, int nd, int P, double *bbox) {
+  const int64_t dm = blockIdx.x;
+  const int lane = threadIdx.x;
+  double mn[D], mx[D];
 #pragma unroll
-    for (int a = 0; a < D; ++a) { bbox[(dm * 2 + 0) * 3 + a] = smin[0][a]; bbox[(dm * 2 + 1) * 3 + a] = smax[0][a]; }
+  for (int a = 0; a < D; ++a) { mn[a] = INFINITY; mx[a] = -INFINITY; }
+  for (int j = lane; j < P; j += 64)
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      mn[a] = fmin(mn[a], part[(dm * P + j) * 6 + a]);
+      mx[a] = fmax(mx[a], part[(dm * P + j) * 6 + 3 + a]);
+    }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      mn[a] = fmin(mn[a], __shfl_xor(mn[a], o, 64));
+      mx[a] = fmax(mx[a], __shfl_xor(mx[a], o, 64));
+    }
+  if (lane == 0)
+#pragma unroll
+    for (int a = 0; a < D; ++a) { bbox[(dm * 2 + 0) * 3 + a] = mn[a]; bbox[(dm * 2 + 1) * 3 + a] = mx[a]; }
 }
 
 // ------------------------------------------------------------ cell sort ---
@@ -143,6 +178,18 @@ __global__ void k_cell_sort(const int64_t *start, int64_t ncells, int32_t *nodes
   }
 }
 
+// positions and kinds in cell-sorted order
+template <int D>
+__global__ void k_sort_pos(const int32_t *nodes, int64_t N, const double *x, const uint8_t *kind, double *xs,
+                           uint8_t *ks) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= N) return;
+  const int32_t j = nodes[s];
+#pragma unroll
+  for (int q = 0; q < D; ++q) xs[q * N + s] = x[q * N + j];
+  ks[s] = kind[j];
+}
+
 // ------------------------------------------------- kNN + classifier -------
 struct KnnArgs {
   const double *x;
@@ -153,6 +200,10 @@ struct KnnArgs {
   const GridDesc *grids;
   const int64_t *cell_start;
   const int32_t *cell_nodes;
+  const int32_t *qlist;     // non-NULL: cell-sorted positions of the nodes that need neighbours
+  const int64_t *nq;        // length of qlist (device)
+  const double *xs;         // [D][N] positions in cell-sorted order (xs[s] = x[cell_nodes[s]])
+  const uint8_t *ks;        // [N] kinds in cell-sorted order
   const int32_t *n_dom;     // stencil size per domain
   const double *h_dom;
   int hybrid;
@@ -178,21 +229,32 @@ __device__ __forceinline__ void topk_insert(double (&bd)[K], int32_t (&bj)[K], d
 
 // One thread per node, visited in cell order.  Cells are searched ring by
 // ring (Chebyshev shells) until the k-th best squared distance is below a
-// lower bound of every node in the unvisited cells.
+// lower bound of every node in the unvisited cells.  The cells of a shell row
+// that lie in one tile along x have consecutive ids, so their nodes form one
+// contiguous range of the cell-sorted arrays: a row costs one pair of range
+// loads per tile it crosses, and candidates are fetched four at a time (the
+// best-k set under the order (distance, index) does not depend on the order
+// in which candidates arrive).
 template <int D, int K>
 __global__ __launch_bounds__(128) void k_knn(KnnArgs a) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= a.N) return;
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (a.qlist) {
+    if (t >= *a.nq) return;
+    t = a.qlist[t];
+  } else if (t >= a.N) {
+    return;
+  }
   const int64_t N = a.N;
   const int32_t i = a.cell_nodes[t];
   const int dm = find_domain(i, a.off, a.nd);
   const GridDesc g = a.grids[dm];
-  const bool bnd = a.kind[i] != 0;             // a wall node draws from interior nodes only
+  const bool bnd = a.ks[t] != 0;               // a wall node draws from interior nodes only
   double xi[D];
 #pragma unroll
-  for (int q = 0; q < D; ++q) xi[q] = a.x[q * N + i];
+  for (int q = 0; q < D; ++q) xi[q] = a.xs[q * N + t];
   int ci[3] = {0, 0, 0};
   cell_coords<D>(g, xi, ci);
+  const int msk = (1 << g.tl) - 1;
 
   double bd[K];
   int32_t bj[K];
@@ -202,24 +264,29 @@ __global__ __launch_bounds__(128) void k_knn(KnnArgs a) {
   bool dup = false;
   const double margin = 1e-6 * g.cs;
 
-  for (int r = 0;; ++r) {
-    // visit the shell of Chebyshev radius r
-    int lo[3], hi[3];
+  // candidates s0 <= s < s1 of the cell-sorted arrays
+  auto scan = [&](int64_t s0, int64_t s1) {
+    for (int64_t s = s0; s < s1; s += 4) {
+      double pq[4][D];
+      int32_t jj[4];
+      uint8_t kk[4];
 #pragma unroll
-    for (int q = 0; q < D; ++q) {
-      lo[q] = max(ci[q] - r, 0);
-      hi[q] = min(ci[q] + r, g.dims[q] - 1);
-    }
-    auto visit = [&](const int *c) {
-      const int64_t id = cell_id<D>(g, c);
-      const int64_t s0 = a.cell_start[id], s1 = a.cell_start[id + 1];
-      for (int64_t s = s0; s < s1; ++s) {
-        const int32_t j = a.cell_nodes[s];
-        if (bnd && j != i && a.kind[j] != 0) continue;
+      for (int u = 0; u < 4; ++u) {
+        const int64_t su = (s + u < s1) ? s + u : s;
+        jj[u] = a.cell_nodes[su];
+        kk[u] = a.ks[su];
+#pragma unroll
+        for (int q = 0; q < D; ++q) pq[u][q] = a.xs[q * N + su];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (s + u >= s1) break;
+        const int32_t j = jj[u];
+        if (bnd && j != i && kk[u] != 0) continue;
         double d2 = 0.0;
 #pragma unroll
         for (int q = 0; q < D; ++q) {
-          const double dq = a.x[q * N + j] - xi[q];
+          const double dq = pq[u][q] - xi[q];
           const double sq = dq * dq;
           d2 = (q == 0) ? sq : d2 + sq;
         }
@@ -229,18 +296,57 @@ __global__ __launch_bounds__(128) void k_knn(KnnArgs a) {
           filled = min(filled + 1, K);
         }
       }
-    };
-    int c[3] = {0, 0, 0};
+    }
+  };
+  // cells xa..xb of the row (c1, c2), split where the row leaves a tile.
+  // Once k candidates are held, the row is cut to the cells that can reach
+  // the current k-th distance: a lower bound of the distance across y (, z)
+  // leaves a reach along x, widened by the margin (every skipped node lies
+  // strictly beyond the k-th distance, so the best-k set is unchanged).
+  auto visit_row = [&](int c1, int c2, int xa, int xb) {
+    if (filled == K) {
+      double dyz = 0.0;
+      const int cc[3] = {0, c1, c2};
+#pragma unroll
+      for (int q = 1; q < D; ++q) {
+        const double lo = g.origin[q] + (double)cc[q] * g.cs;
+        const double e = fmax(0.0, fmax(lo - xi[q], xi[q] - (lo + g.cs)) - margin);
+        dyz += e * e;
+      }
+      const double rem = bd[K - 1] * (1.0 + 1e-12) - dyz;
+      if (rem < 0.0) return;
+      const double reach = sqrt(rem) + margin;
+      xa = max(xa, (int)fmax(floor((xi[0] - reach - g.origin[0]) / g.cs), -1.0));
+      xb = min(xb, (int)fmin(floor((xi[0] + reach - g.origin[0]) / g.cs), (double)g.dims[0]));
+    }
+    int c[3] = {xa, c1, c2};
+    while (c[0] <= xb) {
+      const int xe = min(xb, c[0] | msk);
+      const int64_t id = cell_id<D>(g, c);
+      const int64_t s0 = a.cell_start[id], s1 = a.cell_start[id + (xe - c[0]) + 1];
+      scan(s0, s1);
+      c[0] = xe + 1;
+    }
+  };
+
+  for (int r = 0;; ++r) {
+    // visit the shell of Chebyshev radius r
+    int lo[3], hi[3];
+#pragma unroll
+    for (int q = 0; q < D; ++q) {
+      lo[q] = max(ci[q] - r, 0);
+      hi[q] = min(ci[q] + r, g.dims[q] - 1);
+    }
     const int zlo = (D == 3) ? lo[2] : 0, zhi = (D == 3) ? hi[2] : 0;
-    for (c[2] = zlo; c[2] <= zhi; ++c[2])
-      for (c[1] = lo[1]; c[1] <= hi[1]; ++c[1]) {
-        const bool full_row = (abs(c[1] - ci[1]) == r) || (D == 3 && abs(c[2] - ci[2]) == r);
+    for (int z = zlo; z <= zhi; ++z)
+      for (int y = lo[1]; y <= hi[1]; ++y) {
+        const bool full_row = (abs(y - ci[1]) == r) || (D == 3 && abs(z - ci[2]) == r);
         if (full_row) {
-          for (c[0] = lo[0]; c[0] <= hi[0]; ++c[0]) visit(c);
+          visit_row(y, z, lo[0], hi[0]);
         } else {
           // rows strictly inside the shell contribute only their two end cells
-          if (ci[0] - r >= 0) { c[0] = ci[0] - r; visit(c); }
-          if (r > 0 && ci[0] + r <= g.dims[0] - 1) { c[0] = ci[0] + r; visit(c); }
+          if (ci[0] - r >= 0) visit_row(y, z, ci[0] - r, ci[0] - r);
+          if (r > 0 && ci[0] + r <= g.dims[0] - 1) visit_row(y, z, ci[0] + r, ci[0] + r);
         }
       }
     // lower bound of the distance to any node in an unvisited cell
@@ -266,90 +372,109 @@ __global__ __launch_bounds__(128) void k_knn(KnnArgs a) {
   if (filled < n_i) latch(a.status, BE_SMALL_DOMAIN, i);
 #pragma unroll
   for (int p = 0; p < K; ++p) a.knn[(int64_t)p * N + i] = bj[p];
+}
 
-  // classifier: a complete axis cross at spacing h_r among the neighbours
+// The classifier, one thread per node in cell order.  An interior node of a
+// hybrid set is regular when each of its 2d axis points x +- h_r e_a has
+// exactly one node within kCrossTau h_r (max-norm); the count runs over
+// every node of the cells that the tolerance box around the point touches
+// (widened by the margin, so no matching node is missed).  Every node also
+// looks for a coinciding node: one would lie in the cells around its own
+// position.  Wall nodes, and every node of an all-scattered set, are
+// scattered.
+template <int D>
+__global__ __launch_bounds__(128) void k_classify(KnnArgs a) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= a.N) return;
+  const int64_t N = a.N;
+  const int32_t i = a.cell_nodes[t];
+  const int dm = find_domain(i, a.off, a.nd);
+  const GridDesc g = a.grids[dm];
+  const bool bnd = a.ks[t] != 0;
+  double xi[D];
+#pragma unroll
+  for (int q = 0; q < D; ++q) xi[q] = a.xs[q * N + t];
+  const double margin = 1e-6 * g.cs;
+
+  // every node of the cells meeting the box [p - w, p + w]
+  auto each_in_box = [&](const double *p, double w, auto &&f) {
+    int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+    double pl[D], ph[D];
+#pragma unroll
+    for (int q = 0; q < D; ++q) { pl[q] = p[q] - w; ph[q] = p[q] + w; }
+    cell_coords<D>(g, pl, lo);
+    cell_coords<D>(g, ph, hi);
+    int c[3] = {0, 0, 0};
+    for (c[2] = (D == 3 ? lo[2] : 0); c[2] <= (D == 3 ? hi[2] : 0); ++c[2])
+      for (c[1] = lo[1]; c[1] <= hi[1]; ++c[1])
+        for (c[0] = lo[0]; c[0] <= hi[0]; ++c[0]) {
+          const int64_t id = cell_id<D>(g, c);
+          const int64_t s1 = a.cell_start[id + 1];
+          for (int64_t s = a.cell_start[id]; s < s1; ++s) f(s);
+        }
+  };
+
+  bool dup = false;
+  each_in_box(xi, margin, [&](int64_t s) {
+    const int32_t j = a.cell_nodes[s];
+    double d2 = 0.0;
+#pragma unroll
+    for (int q = 0; q < D; ++q) {
+      const double dq = a.xs[q * N + s] - xi[q];
+      const double sq = dq * dq;
+      d2 = (q == 0) ? sq : d2 + sq;
+    }
+    if (d2 == 0.0 && j != i) dup = true;
+  });
+  if (dup) latch(a.status, BE_DUPLICATE, i);
+
   uint8_t cl = 1;
   if (a.hybrid && !bnd) {
     const double h = a.h_dom[dm];
     const double tol = kCrossTau * h;
-    int cnt[2 * D];
-    int32_t fnd[2 * D];
+    bool reg = true;
 #pragma unroll
-    for (int c2 = 0; c2 < 2 * D; ++c2) { cnt[c2] = 0; fnd[c2] = -1; }
+    for (int ax = 0; ax < D; ++ax)
 #pragma unroll
-    for (int p = 1; p < K; ++p) {
-      const int32_t j = bj[p];
-      if (j == INT_MAX) continue;
-      double tq[D];
+      for (int sg = 0; sg < 2; ++sg) {
+        double pc[D];
 #pragma unroll
-      for (int q = 0; q < D; ++q) tq[q] = a.x[q * N + j] - xi[q];
+        for (int q = 0; q < D; ++q) pc[q] = xi[q];
+        pc[ax] = sg ? xi[ax] + h : xi[ax] - h;
+        int cnt = 0;
+        int32_t fnd = -1;
+        each_in_box(pc, tol + margin, [&](int64_t s) {
+          const int32_t j = a.cell_nodes[s];
+          if (j == i) return;
+          double tq[D];
 #pragma unroll
-      for (int ax = 0; ax < D; ++ax)
-#pragma unroll
-        for (int sg = 0; sg < 2; ++sg) {
+          for (int q = 0; q < D; ++q) tq[q] = a.xs[q * N + s] - xi[q];
           const double e = sg ? tq[ax] - h : tq[ax] + h;
           bool ok = fabs(e) <= tol;
 #pragma unroll
           for (int q = 0; q < D; ++q)
             if (q != ax && !(fabs(tq[q]) <= tol)) ok = false;
-          if (ok) { cnt[2 * ax + sg]++; fnd[2 * ax + sg] = j; }
-        }
-    }
-    // every node that could satisfy the cross test lies within h (1 + 3 tau);
-    // when the neighbour list does not reach beyond that radius (a dense,
-    // refined region), count the cross matches over every node of the cells
-    // within reach instead (the same rule, evaluated exhaustively)
-    const double R = h * (1.0 + 3.0 * kCrossTau);
-    if (!(bd[K - 1] > R * R)) {
-#pragma unroll
-      for (int c2 = 0; c2 < 2 * D; ++c2) { cnt[c2] = 0; fnd[c2] = -1; }
-      int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
-#pragma unroll
-      for (int q = 0; q < D; ++q) {
-        double pl[D], ph[D];
-#pragma unroll
-        for (int u = 0; u < D; ++u) { pl[u] = xi[u]; ph[u] = xi[u]; }
-        pl[q] = xi[q] - 2.0 * R;
-        ph[q] = xi[q] + 2.0 * R;
-        int cl_[3] = {0, 0, 0}, ch_[3] = {0, 0, 0};
-        cell_coords<D>(g, pl, cl_);
-        cell_coords<D>(g, ph, ch_);
-        lo[q] = cl_[q];
-        hi[q] = ch_[q];
+          if (ok) { ++cnt; fnd = j; }
+        });
+        reg = reg && (cnt == 1);
+        a.cross[(int64_t)(2 * ax + sg) * N + i] = fnd;
       }
-      int c[3] = {0, 0, 0};
-      for (c[2] = (D == 3 ? lo[2] : 0); c[2] <= (D == 3 ? hi[2] : 0); ++c[2])
-        for (c[1] = lo[1]; c[1] <= hi[1]; ++c[1])
-          for (c[0] = lo[0]; c[0] <= hi[0]; ++c[0]) {
-            const int64_t id = cell_id<D>(g, c);
-            for (int64_t s = a.cell_start[id]; s < a.cell_start[id + 1]; ++s) {
-              const int32_t j = a.cell_nodes[s];
-              if (j == i) continue;
-              double tq[D];
-#pragma unroll
-              for (int q = 0; q < D; ++q) tq[q] = a.x[q * N + j] - xi[q];
-#pragma unroll
-              for (int ax = 0; ax < D; ++ax)
-#pragma unroll
-                for (int sg = 0; sg < 2; ++sg) {
-                  const double e = sg ? tq[ax] - h : tq[ax] + h;
-                  bool ok = fabs(e) <= tol;
-#pragma unroll
-                  for (int q = 0; q < D; ++q)
-                    if (q != ax && !(fabs(tq[q]) <= tol)) ok = false;
-                  if (ok) { cnt[2 * ax + sg]++; fnd[2 * ax + sg] = j; }
-                }
-            }
-          }
-    }
-    bool reg = true;
-#pragma unroll
-    for (int c2 = 0; c2 < 2 * D; ++c2) reg = reg && (cnt[c2] == 1);
     cl = reg ? 0 : 1;
-#pragma unroll
-    for (int c2 = 0; c2 < 2 * D; ++c2) a.cross[(int64_t)c2 * N + i] = fnd[c2];
   }
   a.cls[i] = cl;
+}
+
+// cell-sorted positions of the scattered nodes, in cell order
+__global__ void k_flag_scattered(const int32_t *nodes, const uint8_t *cls, int64_t N, int32_t *flag) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= N) return;
+  flag[t] = cls[nodes[t]] != 0 ? 1 : 0;
+}
+
+__global__ void k_compact(const int32_t *flag, const int64_t *pos, int64_t N, int32_t *out) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= N) return;
+  if (flag[t]) out[pos[t]] = (int32_t)t;
 }
 
 // ------------------------------------------------- buckets and ordering ---
@@ -485,11 +610,16 @@ hsm_status build_stencils_impl(const hsm_nodeset *ns, int32_t mode, hipStream_t 
   st->dom_off.assign(ns->host_domain_offsets, ns->host_domain_offsets + nd + 1);
   HSM_HIP(hipGetDevice(&st->device));
 
-  DBuf d_off, d_h, d_n, d_combo, d_bbox, d_grid, d_status;
+  // chunks per domain of the bounding-box pass: about 4096 nodes each
+  int64_t max_cnt = 0;
+  for (int k = 0; k < nd; ++k)
+    max_cnt = std::max<int64_t>(max_cnt, ns->host_domain_offsets[k + 1] - ns->host_domain_offsets[k]);
+  const int bbP = (int)std::min<int64_t>(256, std::max<int64_t>(1, (max_cnt + 4095) / 4096));
+  DBuf d_off, d_h, d_n, d_combo, d_bbox, d_bbpart, d_grid, d_status;
   if ((rc = d_off.alloc(sizeof(int64_t) * (nd + 1))) || (rc = d_h.alloc(sizeof(double) * nd)) ||
       (rc = d_n.alloc(sizeof(int32_t) * nd)) || (rc = d_combo.alloc(sizeof(int32_t) * nd)) ||
-      (rc = d_bbox.alloc(sizeof(double) * nd * 6)) || (rc = d_grid.alloc(sizeof(GridDesc) * nd)) ||
-      (rc = d_status.alloc(sizeof(DevStatus))))
+      (rc = d_bbox.alloc(sizeof(double) * nd * 6)) || (rc = d_bbpart.alloc(sizeof(double) * nd * bbP * 6)) ||
+      (rc = d_grid.alloc(sizeof(GridDesc) * nd)) || (rc = d_status.alloc(sizeof(DevStatus))))
     return rc;
   HSM_HIP(hipMemcpyAsync(d_off.p, ns->host_domain_offsets, sizeof(int64_t) * (nd + 1), hipMemcpyHostToDevice, s));
   HSM_HIP(hipMemcpyAsync(d_h.p, ns->host_h_regular, sizeof(double) * nd, hipMemcpyHostToDevice, s));
@@ -503,8 +633,18 @@ hsm_status build_stencils_impl(const hsm_nodeset *ns, int32_t mode, hipStream_t 
   HSM_HIP(hipEventRecord(ev[0], s));
 
   // ---- per-domain bounding boxes -> cell grids (about two nodes per cell)
-  if (d == 2) hipLaunchKernelGGL(k_bbox<2>, dim3(nd), dim3(256), 0, s, ns->x, N, d_off.as<int64_t>(), d_bbox.as<double>());
-  else hipLaunchKernelGGL(k_bbox<3>, dim3(nd), dim3(256), 0, s, ns->x, N, d_off.as<int64_t>(), d_bbox.as<double>());
+  const unsigned bb_blocks = (unsigned)((int64_t)nd * bbP);
+  if (d == 2) {
+    hipLaunchKernelGGL(k_bbox_part<2>, dim3(bb_blocks), dim3(256), 0, s, ns->x, N, d_off.as<int64_t>(), bbP,
+                       d_bbpart.as<double>());
+    hipLaunchKernelGGL(k_bbox_fold<2>, dim3(nd), dim3(64), 0, s, d_bbpart.as<double>(), nd, bbP,
+                       d_bbox.as<double>());
+  } else {
+    hipLaunchKernelGGL(k_bbox_part<3>, dim3(bb_blocks), dim3(256), 0, s, ns->x, N, d_off.as<int64_t>(), bbP,
+                       d_bbpart.as<double>());
+    hipLaunchKernelGGL(k_bbox_fold<3>, dim3(nd), dim3(64), 0, s, d_bbpart.as<double>(), nd, bbP,
+                       d_bbox.as<double>());
+  }
   HSM_HIP(hipGetLastError());
   std::vector<double> bbox(nd * 6);
   HSM_HIP(hipMemcpyAsync(bbox.data(), d_bbox.p, sizeof(double) * nd * 6, hipMemcpyDeviceToHost, s));
@@ -577,17 +717,49 @@ hsm_status build_stencils_impl(const hsm_nodeset *ns, int32_t mode, hipStream_t 
   }
 
   // ---- k nearest neighbours and classes
-  DBuf d_knn, d_cls, d_cross;
+  DBuf d_knn, d_cls, d_cross, d_xs, d_ks;
   if ((rc = d_knn.alloc(sizeof(int32_t) * K * N)) || (rc = st->cls.alloc(N)) ||
-      (rc = d_cross.alloc(sizeof(int32_t) * 2 * d * N)))
+      (rc = d_cross.alloc(sizeof(int32_t) * 2 * d * N)) || (rc = d_xs.alloc(sizeof(double) * d * N)) ||
+      (rc = d_ks.alloc(N)))
     return rc;
+  if (N > 0) {
+    if (d == 2)
+      hipLaunchKernelGGL(k_sort_pos<2>, dim3(nblk(N, 256)), dim3(256), 0, s, d_cellnodes.as<int32_t>(), N, ns->x,
+                         ns->kind, d_xs.as<double>(), d_ks.as<uint8_t>());
+    else
+      hipLaunchKernelGGL(k_sort_pos<3>, dim3(nblk(N, 256)), dim3(256), 0, s, d_cellnodes.as<int32_t>(), N, ns->x,
+                         ns->kind, d_xs.as<double>(), d_ks.as<uint8_t>());
+    HSM_HIP(hipGetLastError());
+  }
   KnnArgs ka;
   ka.x = ns->x; ka.kind = ns->kind; ka.N = N; ka.off = d_off.as<int64_t>(); ka.nd = nd;
   ka.grids = d_grid.as<GridDesc>(); ka.cell_start = d_start.as<int64_t>(); ka.cell_nodes = d_cellnodes.as<int32_t>();
+  ka.xs = d_xs.as<double>(); ka.ks = d_ks.as<uint8_t>();
   ka.n_dom = d_n.as<int32_t>(); ka.h_dom = d_h.as<double>(); ka.hybrid = (mode == HSM_MODE_HYBRID);
   ka.knn = d_knn.as<int32_t>(); ka.cls = st->cls.as<uint8_t>(); ka.cross = d_cross.as<int32_t>();
   ka.status = d_status.as<DevStatus>();
+  ka.qlist = nullptr;
+  ka.nq = nullptr;
+  // d_bucket holds the kNN query list until the buckets are formed
+  DBuf d_bucket, d_flag, d_pos;
+  if ((rc = d_bucket.alloc(sizeof(int32_t) * N)) || (rc = d_flag.alloc(sizeof(int32_t) * N)) ||
+      (rc = d_pos.alloc(sizeof(int64_t) * (N + 1))))
+    return rc;
   if (N > 0) {
+    // classes first; in a hybrid set only the scattered and wall nodes need neighbours
+    if (d == 2) hipLaunchKernelGGL(k_classify<2>, dim3(nblk(N, 128)), dim3(128), 0, s, ka);
+    else hipLaunchKernelGGL(k_classify<3>, dim3(nblk(N, 128)), dim3(128), 0, s, ka);
+    HSM_HIP(hipGetLastError());
+    if (mode == HSM_MODE_HYBRID) {
+      hipLaunchKernelGGL(k_flag_scattered, dim3(nblk(N, 256)), dim3(256), 0, s, d_cellnodes.as<int32_t>(),
+                         st->cls.as<uint8_t>(), N, d_flag.as<int32_t>());
+      if ((rc = scan_i32_to_i64(d_flag.as<int32_t>(), d_pos.as<int64_t>(), N, s))) return rc;
+      hipLaunchKernelGGL(k_compact, dim3(nblk(N, 256)), dim3(256), 0, s, d_flag.as<int32_t>(),
+                         d_pos.as<int64_t>(), N, d_bucket.as<int32_t>());
+      HSM_HIP(hipGetLastError());
+      ka.qlist = d_bucket.as<int32_t>();
+      ka.nq = d_pos.as<int64_t>() + N;
+    }
     if (!(d == 2 ? dispatch_knn<2>(K, ka, s) : dispatch_knn<3>(K, ka, s))) {
       set_error(HSM_E_INVALID, "unsupported neighbour count");
       return HSM_E_INVALID;
@@ -598,11 +770,9 @@ hsm_status build_stencils_impl(const hsm_nodeset *ns, int32_t mode, hipStream_t 
 
   // ---- width buckets and the internal order (bucket-major, cell order inside)
   const int NBall = 1 + 3 * nc;
-  DBuf d_bucket, d_flag, d_pos;
-  if ((rc = d_bucket.alloc(sizeof(int32_t) * N)) || (rc = d_flag.alloc(sizeof(int32_t) * N)) ||
-      (rc = d_pos.alloc(sizeof(int64_t) * (N + 1))) || (rc = st->perm.alloc(sizeof(int32_t) * N)) ||
-      (rc = st->iperm.alloc(sizeof(int32_t) * N)) || (rc = st->x.alloc(sizeof(double) * d * N)) ||
-      (rc = st->kind.alloc(N)) || (rc = st->normal.alloc(sizeof(double) * d * N)))
+  if ((rc = st->perm.alloc(sizeof(int32_t) * N)) || (rc = st->iperm.alloc(sizeof(int32_t) * N)) ||
+      (rc = st->x.alloc(sizeof(double) * d * N)) || (rc = st->kind.alloc(N)) ||
+      (rc = st->normal.alloc(sizeof(double) * d * N)))
     return rc;
   if (N > 0) {
     hipLaunchKernelGGL(k_bucket_of, dim3(nblk(N, 256)), dim3(256), 0, s, st->cls.as<uint8_t>(), ns->kind, N,
@@ -674,6 +844,15 @@ hsm_status build_stencils_impl(const hsm_nodeset *ns, int32_t mode, hipStream_t 
   DevStatus hs;
   HSM_HIP(hipMemcpyAsync(&hs, d_status.p, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
   HSM_HIP(hipStreamSynchronize(s));
+  // a domain with fewer nodes than its stencil size (every one of its nodes
+  // offends; regular nodes take no neighbour search, so the host checks)
+  for (int k = 0; k < nd; ++k)
+    if (ns->host_domain_offsets[k + 1] - ns->host_domain_offsets[k] < n_dom[k]) {
+      hs.bits |= 1u << BE_SMALL_DOMAIN;
+      hs.node[BE_SMALL_DOMAIN] = std::min<unsigned long long>(hs.node[BE_SMALL_DOMAIN],
+                                                              (unsigned long long)ns->host_domain_offsets[k]);
+      break;
+    }
   HSM_HIP(hipEventRecord(ev[2], s));
   if (!(hs.bits & ((1u << BE_DUPLICATE) | (1u << BE_SMALL_DOMAIN) | (1u << BE_AMBIGUOUS) | (1u << BE_NONFINITE)))) {
     // wall nodes whose degree-m system is singular are listed, not failed

@@ -63,6 +63,14 @@ __device__ __forceinline__ double wave_max(double v) {
   return v;
 }
 
+// maximum over each group of 64 / G consecutive lanes (G = 1 or 2)
+template <int G>
+__device__ __forceinline__ double group_max(double v) {
+#pragma unroll
+  for (int o = 32 / G; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
 struct SolveArgs {
   const double *x;        // [D][N] internal order
   const double *normal;   // [D][N] internal order
@@ -82,18 +90,21 @@ struct SolveArgs {
 // Row `lane` of the RBF-FD system of node t (Section 2.1): M = [[A, P],
 // [P^T, 0]] and the right-hand sides of d/dx_a and the Laplacian, in local
 // coordinates y_j = (x_j - x_c) / s; returns the centre c and the scale s.
-// M is symmetric, so the row is also column `lane`.
-template <int D, int M, int NS>
+// M is symmetric, so the row is also column `lane`.  The wave holds G
+// systems, group `grp` of 64 / G lanes this one (lane counted in the group).
+template <int D, int M, int NS, int G = 1>
 __device__ __forceinline__ void rbffd_rows(const SolveArgs &a, int64_t t, int lane,
                                            double (&Rw)[NS + Monos<D, M>::Q], double (&B)[D + 1], int32_t &c,
-                                           double &s) {
+                                           double &s, int grp = 0) {
   constexpr int Q = Monos<D, M>::Q;
   constexpr int S = NS + Q;
   constexpr int R = D + 1;
   const int64_t cnt = a.count, N = a.N;
   constexpr Monos<D, M> mono{};
-  __shared__ double sy[NS][D];
-  __shared__ double smono[NS][Q];
+  __shared__ double sy_[G][NS][D];
+  __shared__ double smono_[G][NS][Q];
+  double (&sy)[NS][D] = sy_[grp];
+  double (&smono)[NS][Q] = smono_[grp];
 
   // local coordinates y_j = (x_j - x_c) / s, s = max_j |x_j - x_c|
   c = a.idx[t];
@@ -111,7 +122,7 @@ __device__ __forceinline__ void rbffd_rows(const SolveArgs &a, int64_t t, int la
     }
     r = sqrt(sq);
   }
-  s = wave_max(r);
+  s = group_max<G>(r);
   double y[D];
 #pragma unroll
   for (int q = 0; q < D; ++q) y[q] = dxv[q] / s;
@@ -177,30 +188,42 @@ __device__ __forceinline__ void rbffd_rows(const SolveArgs &a, int64_t t, int la
 
 }
 
-template <int D, int M, int NS>
+// G systems per wave (G = 2 when S <= 32): lanes 32 g .. 32 g + 31 hold
+// system 2 b + g of block b.  Every system takes exactly the operations of
+// the one-system form; the pivot row reaches its group by lane permutes.
+template <int D, int M, int NS, int G>
 __global__ __launch_bounds__(64) void k_rbffd(SolveArgs a) {
   constexpr int Q = Monos<D, M>::Q;
   constexpr int S = NS + Q;
   constexpr int R = D + 1;
-  static_assert(S <= 64, "one system row per lane");
-  const int lane = threadIdx.x;
-  int64_t t = blockIdx.x;
+  constexpr int GL = 64 / G;          // lanes per group
+  static_assert(S <= GL, "one system row per lane");
+  const int grp = (G == 1) ? 0 : (int)threadIdx.x / GL;
+  const int lane = (int)threadIdx.x - grp * GL;
+  const int base = grp * GL;
+  int64_t t;
+  bool live = true;
   if (a.list) {
+    // list mode: one system per block
     const int64_t g = a.list[blockIdx.x];
-    if (g < a.start || g >= a.start + a.count) return;
+    if (G != 1 || g < a.start || g >= a.start + a.count) return;
     t = g - a.start;
+  } else {
+    t = (int64_t)blockIdx.x * G + grp;
+    live = t < a.count;
+    if (!live) t = a.count - 1;       // a group past the end repeats the last system and stores nothing
   }
   const int64_t cnt = a.count, N = a.N;
   double Rw[S], B[R];
   int32_t c;
   double s;
-  rbffd_rows<D, M, NS>(a, t, lane, Rw, B, c, s);
+  rbffd_rows<D, M, NS, G>(a, t, lane, Rw, B, c, s, grp);
 
   // elimination
   double amax = 0.0;
 #pragma unroll
   for (int k = 0; k < S; ++k) amax = fmax(amax, fabs(Rw[k]));
-  amax = wave_max(amax);
+  amax = group_max<G>(amax);
   const double thr = kPivotRel * amax;
   bool used = lane >= S;
   int pstep = used ? S : -1;
@@ -209,18 +232,29 @@ __global__ __launch_bounds__(64) void k_rbffd(SolveArgs a) {
 #pragma unroll
   for (int k = 0; k < S; ++k) {
     const double cand = used ? -1.0 : fabs(Rw[k]);
-    const double best = wave_max(cand);
-    if (!(best > thr)) { singular = true; break; }
+    const double best = group_max<G>(cand);
+    if (!(best > thr)) singular = true;
+    if (G == 1 && singular) break;
     const unsigned long long mask = __ballot(!used && cand == best);
-    const int p = __ffsll((long long)mask) - 1;
+    const unsigned long long gm = (G == 1) ? mask : ((mask >> base) & 0xffffffffull);
+    const int p = gm ? __ffsll((long long)gm) - 1 : 0;
     piv[k] = p;
-    const double pk = rdlane(Rw[k], p);
-    double pr[S];
+    double pk, pr[S], pb[R];
+    if (G == 1) {
+      pk = rdlane(Rw[k], p);
 #pragma unroll
-    for (int j = k + 1; j < S; ++j) pr[j] = rdlane(Rw[j], p);
-    double pb[R];
+      for (int j = k + 1; j < S; ++j) pr[j] = rdlane(Rw[j], p);
 #pragma unroll
-    for (int q = 0; q < R; ++q) pb[q] = rdlane(B[q], p);
+      for (int q = 0; q < R; ++q) pb[q] = rdlane(B[q], p);
+    } else {
+      const int src = base + p;
+      pk = __shfl(Rw[k], src, 64);
+#pragma unroll
+      for (int j = k + 1; j < S; ++j) pr[j] = __shfl(Rw[j], src, 64);
+#pragma unroll
+      for (int q = 0; q < R; ++q) pb[q] = __shfl(B[q], src, 64);
+    }
+    if (singular) continue;
     if (lane == p) {
       used = true;
       pstep = k;
@@ -232,7 +266,7 @@ __global__ __launch_bounds__(64) void k_rbffd(SolveArgs a) {
       for (int q = 0; q < R; ++q) B[q] = B[q] - l * pb[q];
     }
   }
-  if (singular) {
+  if (G == 1 && singular) {
     if (lane == 0) {
       if (a.retry) a.retry[atomicAdd(a.nretry, 1)] = (int32_t)(a.start + t);
       else latch(a.status, BE_SINGULAR, a.perm[a.start + t]);
@@ -246,10 +280,17 @@ __global__ __launch_bounds__(64) void k_rbffd(SolveArgs a) {
 #pragma unroll
   for (int k = S - 1; k >= 0; --k) {
     const int p = piv[k];
-    const double den = rdlane(Rw[k], p);
-    double xk[R];
+    double den, xk[R];
+    if (G == 1) {
+      den = rdlane(Rw[k], p);
 #pragma unroll
-    for (int q = 0; q < R; ++q) xk[q] = rdlane(B[q], p) / den;
+      for (int q = 0; q < R; ++q) xk[q] = rdlane(B[q], p) / den;
+    } else {
+      const int src = base + p;
+      den = __shfl(Rw[k], src, 64);
+#pragma unroll
+      for (int q = 0; q < R; ++q) xk[q] = __shfl(B[q], src, 64) / den;
+    }
     if (k < NS && lane == k) {
 #pragma unroll
       for (int q = 0; q < R; ++q) myw[q] = xk[q];
@@ -258,6 +299,14 @@ __global__ __launch_bounds__(64) void k_rbffd(SolveArgs a) {
 #pragma unroll
       for (int q = 0; q < R; ++q) B[q] = B[q] - Rw[k] * xk[q];
     }
+  }
+  if (!live) return;
+  if (singular) {
+    if (lane == 0) {
+      if (a.retry) a.retry[atomicAdd(a.nretry, 1)] = (int32_t)(a.start + t);
+      else latch(a.status, BE_SINGULAR, a.perm[a.start + t]);
+    }
+    return;
   }
   if (lane < NS) {
     const int64_t WC = (int64_t)NS * cnt;
@@ -407,8 +456,15 @@ __global__ __launch_bounds__(128) void k_mon(SolveArgs a) {
 
 template <int D, int M, int NS>
 void launch_rbffd(const SolveArgs &a, hipStream_t s, int64_t nlist = -1) {
+  constexpr int S = NS + Monos<D, M>::Q;
+  if constexpr (S <= 32) {
+    if (nlist < 0) {
+      hipLaunchKernelGGL((k_rbffd<D, M, NS, 2>), dim3((unsigned)((a.count + 1) / 2)), dim3(64), 0, s, a);
+      return;
+    }
+  }
   const int64_t g = nlist >= 0 ? nlist : a.count;
-  hipLaunchKernelGGL((k_rbffd<D, M, NS>), dim3((unsigned)g), dim3(64), 0, s, a);
+  hipLaunchKernelGGL((k_rbffd<D, M, NS, 1>), dim3((unsigned)g), dim3(64), 0, s, a);
 }
 
 // ------------------------------------------------- condition numbers --
