@@ -123,6 +123,11 @@ typedef struct {
  * n + C(m+d, d) <= 64 (so 2D m=4 n=30 and 3D m=2 n=20 or 30 fit), and at
  * most HSM_MAX_NODES nodes in total.
  *
+ * Scratch memory (cell lists, neighbour lists, prefix-sum workspace) comes
+ * in two blocks from a stream-ordered memory pool that the library creates
+ * per device on first use; released blocks stay in the pool, up to 4 GiB per
+ * device, for the next build, until the process ends.
+ *
  * Synchronises `stream`.  Errors: HSM_E_INVALID (arguments, a domain with
  * fewer than n usable nodes), HSM_E_DUPLICATE_NODE,
  * HSM_E_SINGULAR (hsm_last_error_node names the node), HSM_E_OOM, HSM_E_HIP.

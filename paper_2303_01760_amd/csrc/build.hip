@@ -498,10 +498,18 @@ __global__ void k_flag(const int32_t *seq, const int32_t *bucket, int64_t N, int
   flag[t] = bucket[seq[t]] == b ? 1 : 0;
 }
 
-__global__ void k_place(const int32_t *seq, const int32_t *flag, const int64_t *pos, int64_t N, int64_t start,
-                        int32_t *perm) {
+// bucket b's size (the flag total) into counts[b]; its nodes go after those
+// of buckets 0..b-1
+__global__ void k_bucket_total(const int64_t *pos, int64_t N, int b, int64_t *counts) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) counts[b] = pos[N];
+}
+
+__global__ void k_place(const int32_t *seq, const int32_t *flag, const int64_t *pos, int64_t N,
+                        const int64_t *counts, int b, int32_t *perm) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= N) return;
+  int64_t start = 0;
+  for (int c = 0; c < b; ++c) start += counts[c];
   if (flag[t]) perm[start + pos[t]] = seq[t];
 }
 
@@ -615,12 +623,19 @@ hsm_status build_stencils_impl(const hsm_nodeset *ns, int32_t mode, hipStream_t 
   for (int k = 0; k < nd; ++k)
     max_cnt = std::max<int64_t>(max_cnt, ns->host_domain_offsets[k + 1] - ns->host_domain_offsets[k]);
   const int bbP = (int)std::min<int64_t>(256, std::max<int64_t>(1, (max_cnt + 4095) / 4096));
-  DBuf d_off, d_h, d_n, d_combo, d_bbox, d_bbpart, d_grid, d_status;
-  if ((rc = d_off.alloc(sizeof(int64_t) * (nd + 1))) || (rc = d_h.alloc(sizeof(double) * nd)) ||
-      (rc = d_n.alloc(sizeof(int32_t) * nd)) || (rc = d_combo.alloc(sizeof(int32_t) * nd)) ||
-      (rc = d_bbox.alloc(sizeof(double) * nd * 6)) || (rc = d_bbpart.alloc(sizeof(double) * nd * bbP * 6)) ||
-      (rc = d_grid.alloc(sizeof(GridDesc) * nd)) || (rc = d_status.alloc(sizeof(DevStatus))))
+  // temporaries of the build: two blocks of the scratch pool (per-domain data
+  // now, node and cell arrays once the grids are known), released in stream order
+  const size_t b_off = sizeof(int64_t) * (nd + 1), b_h = sizeof(double) * nd, b_n = sizeof(int32_t) * nd,
+               b_combo = sizeof(int32_t) * nd, b_bbox = sizeof(double) * nd * 6,
+               b_bbpart = sizeof(double) * nd * bbP * 6, b_grid = sizeof(GridDesc) * nd, b_status = sizeof(DevStatus);
+  Arena ar1;
+  if ((rc = ar1.reserve(round256(b_off) + round256(b_h) + round256(b_n) + round256(b_combo) + round256(b_bbox) +
+                            round256(b_bbpart) + round256(b_grid) + round256(b_status), s)))
     return rc;
+  const Arena::View d_off = ar1.take(b_off), d_h = ar1.take(b_h), d_n = ar1.take(b_n), d_combo = ar1.take(b_combo),
+                    d_bbox = ar1.take(b_bbox), d_bbpart = ar1.take(b_bbpart), d_grid = ar1.take(b_grid),
+                    d_status = ar1.take(b_status);
+  if (!d_status.p) { set_error(HSM_E_HIP, "scratch reservation too small"); return HSM_E_HIP; }
   HSM_HIP(hipMemcpyAsync(d_off.p, ns->host_domain_offsets, sizeof(int64_t) * (nd + 1), hipMemcpyHostToDevice, s));
   HSM_HIP(hipMemcpyAsync(d_h.p, ns->host_h_regular, sizeof(double) * nd, hipMemcpyHostToDevice, s));
   HSM_HIP(hipMemcpyAsync(d_n.p, n_dom.data(), sizeof(int32_t) * nd, hipMemcpyHostToDevice, s));
@@ -689,11 +704,25 @@ hsm_status build_stencils_impl(const hsm_nodeset *ns, int32_t mode, hipStream_t 
   HSM_HIP(hipMemcpyAsync(d_grid.p, grids.data(), sizeof(GridDesc) * nd, hipMemcpyHostToDevice, s));
 
   // ---- counting sort of nodes into cells
-  DBuf d_cell, d_count, d_start, d_fill, d_cellnodes;
-  if ((rc = d_cell.alloc(sizeof(int64_t) * N)) || (rc = d_count.alloc(sizeof(int32_t) * ncells)) ||
-      (rc = d_start.alloc(sizeof(int64_t) * (ncells + 1))) || (rc = d_fill.alloc(sizeof(int32_t) * ncells)) ||
-      (rc = d_cellnodes.alloc(sizeof(int32_t) * N)))
+  const size_t b_cell = sizeof(int64_t) * N, b_count = sizeof(int32_t) * ncells,
+               b_start = sizeof(int64_t) * (ncells + 1), b_fill = sizeof(int32_t) * ncells,
+               b_cellnodes = sizeof(int32_t) * N, b_knn = sizeof(int32_t) * K * N,
+               b_cross = sizeof(int32_t) * 2 * d * N, b_xs = sizeof(double) * d * N, b_ks = (size_t)N,
+               b_bucket = sizeof(int32_t) * N, b_flag = sizeof(int32_t) * N, b_pos = sizeof(int64_t) * (N + 1),
+               b_bcount = sizeof(int64_t) * kMaxBuckets,
+               b_scan = sizeof(int64_t) * std::max(scan_i32_to_i64_ws(ncells), scan_i32_to_i64_ws(N));
+  Arena ar2;
+  if ((rc = ar2.reserve(round256(b_cell) + round256(b_count) + round256(b_start) + round256(b_fill) +
+                            round256(b_cellnodes) + round256(b_knn) + round256(b_cross) + round256(b_xs) +
+                            round256(b_ks) + round256(b_bucket) + round256(b_flag) + round256(b_pos) +
+                            round256(b_bcount) + round256(b_scan), s)))
     return rc;
+  const Arena::View d_cell = ar2.take(b_cell), d_count = ar2.take(b_count), d_start = ar2.take(b_start),
+                    d_fill = ar2.take(b_fill), d_cellnodes = ar2.take(b_cellnodes), d_knn = ar2.take(b_knn),
+                    d_cross = ar2.take(b_cross), d_xs = ar2.take(b_xs), d_ks = ar2.take(b_ks),
+                    d_bucket = ar2.take(b_bucket), d_flag = ar2.take(b_flag), d_pos = ar2.take(b_pos),
+                    d_bcount = ar2.take(b_bcount), d_scan = ar2.take(b_scan);
+  if (!d_scan.p) { set_error(HSM_E_HIP, "scratch reservation too small"); return HSM_E_HIP; }
   HSM_HIP(hipMemsetAsync(d_count.p, 0, sizeof(int32_t) * ncells, s));
   HSM_HIP(hipMemsetAsync(d_fill.p, 0, sizeof(int32_t) * ncells, s));
   if (N > 0) {
@@ -707,7 +736,7 @@ hsm_status build_stencils_impl(const hsm_nodeset *ns, int32_t mode, hipStream_t 
                          d_status.as<DevStatus>());
     HSM_HIP(hipGetLastError());
   }
-  if ((rc = scan_i32_to_i64(d_count.as<int32_t>(), d_start.as<int64_t>(), ncells, s))) return rc;
+  if ((rc = scan_i32_to_i64(d_count.as<int32_t>(), d_start.as<int64_t>(), ncells, s, d_scan.as<int64_t>()))) return rc;
   if (N > 0) {
     hipLaunchKernelGGL(k_cell_scatter, dim3(nblk(N, 256)), dim3(256), 0, s, d_cell.as<int64_t>(), N,
                        d_start.as<int64_t>(), d_fill.as<int32_t>(), d_cellnodes.as<int32_t>());
@@ -717,11 +746,7 @@ hsm_status build_stencils_impl(const hsm_nodeset *ns, int32_t mode, hipStream_t 
   }
 
   // ---- k nearest neighbours and classes
-  DBuf d_knn, d_cls, d_cross, d_xs, d_ks;
-  if ((rc = d_knn.alloc(sizeof(int32_t) * K * N)) || (rc = st->cls.alloc(N)) ||
-      (rc = d_cross.alloc(sizeof(int32_t) * 2 * d * N)) || (rc = d_xs.alloc(sizeof(double) * d * N)) ||
-      (rc = d_ks.alloc(N)))
-    return rc;
+  if ((rc = st->cls.alloc(N))) return rc;
   if (N > 0) {
     if (d == 2)
       hipLaunchKernelGGL(k_sort_pos<2>, dim3(nblk(N, 256)), dim3(256), 0, s, d_cellnodes.as<int32_t>(), N, ns->x,
@@ -741,10 +766,7 @@ hsm_status build_stencils_impl(const hsm_nodeset *ns, int32_t mode, hipStream_t 
   ka.qlist = nullptr;
   ka.nq = nullptr;
   // d_bucket holds the kNN query list until the buckets are formed
-  DBuf d_bucket, d_flag, d_pos;
-  if ((rc = d_bucket.alloc(sizeof(int32_t) * N)) || (rc = d_flag.alloc(sizeof(int32_t) * N)) ||
-      (rc = d_pos.alloc(sizeof(int64_t) * (N + 1))))
-    return rc;
+
   if (N > 0) {
     // classes first; in a hybrid set only the scattered and wall nodes need neighbours
     if (d == 2) hipLaunchKernelGGL(k_classify<2>, dim3(nblk(N, 128)), dim3(128), 0, s, ka);
@@ -753,7 +775,7 @@ hsm_status build_stencils_impl(const hsm_nodeset *ns, int32_t mode, hipStream_t 
     if (mode == HSM_MODE_HYBRID) {
       hipLaunchKernelGGL(k_flag_scattered, dim3(nblk(N, 256)), dim3(256), 0, s, d_cellnodes.as<int32_t>(),
                          st->cls.as<uint8_t>(), N, d_flag.as<int32_t>());
-      if ((rc = scan_i32_to_i64(d_flag.as<int32_t>(), d_pos.as<int64_t>(), N, s))) return rc;
+      if ((rc = scan_i32_to_i64(d_flag.as<int32_t>(), d_pos.as<int64_t>(), N, s, d_scan.as<int64_t>()))) return rc;
       hipLaunchKernelGGL(k_compact, dim3(nblk(N, 256)), dim3(256), 0, s, d_flag.as<int32_t>(),
                          d_pos.as<int64_t>(), N, d_bucket.as<int32_t>());
       HSM_HIP(hipGetLastError());
@@ -780,25 +802,27 @@ hsm_status build_stencils_impl(const hsm_nodeset *ns, int32_t mode, hipStream_t 
     HSM_HIP(hipGetLastError());
   }
   std::vector<int64_t> bcount(NBall, 0), bstart(NBall, 0);
-  int64_t run = 0;
   for (int b = 0; b < NBall; ++b) {
     if (N > 0) {
       hipLaunchKernelGGL(k_flag, dim3(nblk(N, 256)), dim3(256), 0, s, d_cellnodes.as<int32_t>(),
                          d_bucket.as<int32_t>(), N, b, d_flag.as<int32_t>());
       HSM_HIP(hipGetLastError());
     }
-    if ((rc = scan_i32_to_i64(d_flag.as<int32_t>(), d_pos.as<int64_t>(), N, s))) return rc;
-    int64_t total = 0;
-    HSM_HIP(hipMemcpyAsync(&total, d_pos.as<int64_t>() + N, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    if (N > 0) {
+    if ((rc = scan_i32_to_i64(d_flag.as<int32_t>(), d_pos.as<int64_t>(), N, s, d_scan.as<int64_t>()))) return rc;
+    hipLaunchKernelGGL(k_bucket_total, dim3(1), dim3(64), 0, s, d_pos.as<int64_t>(), N, b,
+                       d_bcount.as<int64_t>());
+    if (N > 0)
       hipLaunchKernelGGL(k_place, dim3(nblk(N, 256)), dim3(256), 0, s, d_cellnodes.as<int32_t>(),
-                         d_flag.as<int32_t>(), d_pos.as<int64_t>(), N, run, st->perm.as<int32_t>());
-      HSM_HIP(hipGetLastError());
-    }
-    HSM_HIP(hipStreamSynchronize(s));
-    bcount[b] = total;
+                         d_flag.as<int32_t>(), d_pos.as<int64_t>(), N, d_bcount.as<int64_t>(), b,
+                         st->perm.as<int32_t>());
+    HSM_HIP(hipGetLastError());
+  }
+  HSM_HIP(hipMemcpyAsync(bcount.data(), d_bcount.p, sizeof(int64_t) * NBall, hipMemcpyDeviceToHost, s));
+  HSM_HIP(hipStreamSynchronize(s));
+  int64_t run = 0;
+  for (int b = 0; b < NBall; ++b) {
     bstart[b] = run;
-    run += total;
+    run += bcount[b];
   }
   if (run != N) { set_error(HSM_E_HIP, "bucket partition lost nodes"); return HSM_E_HIP; }
   if (N > 0) {

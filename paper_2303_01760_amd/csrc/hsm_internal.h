@@ -76,6 +76,76 @@ struct DBuf {
   template <class T> T *as() const { return static_cast<T *>(p); }
 };
 
+// Scratch memory of one call, from a stream-ordered pool of the library (one
+// per device, created on first use).  Allocation and release are ordered on
+// the stream, so temporaries need no synchronisation before they are freed,
+// and the pool keeps up to kScratchPoolKeep bytes of released memory for the
+// next call instead of returning it to the device.
+constexpr uint64_t kScratchPoolKeep = 4ull << 30;
+constexpr int kMaxDevices = 64;
+hipMemPool_t scratch_pool(int device);
+
+struct SBuf {
+  void *p = nullptr;
+  hipStream_t s = nullptr;
+  SBuf() = default;
+  SBuf(const SBuf &) = delete;
+  SBuf &operator=(const SBuf &) = delete;
+  ~SBuf() { release(); }
+  void release() {
+    if (p) (void)hipFreeAsync(p, s);
+    p = nullptr;
+  }
+  hsm_status alloc(size_t n, hipStream_t stream) {
+    release();
+    if (n == 0) n = 16;
+    int dev = 0;
+    hipMemPool_t pool = nullptr;
+    if (hipGetDevice(&dev) == hipSuccess) pool = scratch_pool(dev);
+    if (!pool) {
+      (void)hipGetLastError();
+      set_error(HSM_E_HIP, "no scratch memory pool on this device");
+      return HSM_E_HIP;
+    }
+    hipError_t e = hipMallocFromPoolAsync(&p, n, pool, stream);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      p = nullptr;
+      set_error(HSM_E_OOM, "scratch allocation of " + std::to_string(n) + " bytes failed");
+      return HSM_E_OOM;
+    }
+    s = stream;
+    return HSM_OK;
+  }
+  template <class T> T *as() const { return static_cast<T *>(p); }
+};
+
+// Bump allocation of several temporaries from one scratch-pool block: the
+// caller adds up the 256-byte-rounded sizes, reserves, then takes them.
+inline size_t round256(size_t b) { return ((b ? b : 1) + 255) & ~(size_t)255; }
+struct Arena {
+  SBuf buf;
+  size_t off = 0, cap = 0;
+  hsm_status reserve(size_t bytes, hipStream_t s) {
+    off = 0;
+    cap = bytes;
+    return buf.alloc(bytes, s);
+  }
+  struct View {
+    void *p = nullptr;
+    template <class T> T *as() const { return static_cast<T *>(p); }
+  };
+  // the next `bytes` (NULL view when the reservation is exhausted)
+  View take(size_t bytes) {
+    View v;
+    const size_t b = round256(bytes);
+    if (off + b > cap) return v;
+    v.p = static_cast<char *>(buf.p) + off;
+    off += b;
+    return v;
+  }
+};
+
 // --------------------------------------------------------------- buckets --
 struct Bucket {
   int32_t type = 0;    // BucketType
@@ -340,7 +410,10 @@ void make_table(const hsm_stencils *st, BucketTable &tab, int bs, uint32_t type_
 
 // ---------------------------------------------------------------- scan ----
 // Exclusive prefix sum of n int32 values into int64 out[n+1] (out[n] = total).
-hsm_status scan_i32_to_i64(const int32_t *in, int64_t *out, int64_t n, hipStream_t s);
+// exclusive prefix sum of in[0..n) into out[0..n], out[n] = total; ws holds
+// scan_i32_to_i64_ws(n) int64 of scratch (NULL: taken from the scratch pool)
+hsm_status scan_i32_to_i64(const int32_t *in, int64_t *out, int64_t n, hipStream_t s, int64_t *ws = nullptr);
+int64_t scan_i32_to_i64_ws(int64_t n);
 
 // ------------------------------------------------------------- builders ---
 hsm_status build_stencils_impl(const hsm_nodeset *ns, int32_t mode, hipStream_t s, hsm_stencils **out);

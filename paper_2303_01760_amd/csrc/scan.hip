@@ -1,5 +1,8 @@
 // Device-wide exclusive prefix sums (three passes: tile sums, scan of the
 // tile sums, tile scans).  Deterministic: integer sums, fixed tiling.
+#include <cstring>
+#include <mutex>
+
 #include "hsm_internal.h"
 
 namespace hsm {
@@ -68,8 +71,15 @@ __global__ __launch_bounds__(kBS) void k_tile_scan(const T *in, int64_t n, const
   if (write_total && blockIdx.x == gridDim.x - 1 && threadIdx.x == kBS - 1) out[n] = run;
 }
 
+int64_t scan_ws(int64_t n) {
+  if (n <= kTile) return 0;
+  const int64_t nt = (n + kTile - 1) / kTile;
+  return 2 * nt + 1 + scan_ws(nt);
+}
+
+// ws: scan_ws(n) int64 of scratch, or NULL to take it from the scratch pool
 template <class T>
-hsm_status scan_any(const T *in, int64_t *out, int64_t n, hipStream_t s) {
+hsm_status scan_any(const T *in, int64_t *out, int64_t n, hipStream_t s, int64_t *ws) {
   if (n <= 0) {
     hipLaunchKernelGGL(k_tile_scan<T>, dim3(1), dim3(kBS), 0, s, in, (int64_t)0, (const int64_t *)nullptr,
                        out, 1);
@@ -82,25 +92,51 @@ hsm_status scan_any(const T *in, int64_t *out, int64_t n, hipStream_t s) {
     HSM_HIP(hipGetLastError());
     return HSM_OK;
   }
-  DBuf sums, offs;
+  SBuf own;
   hsm_status rc;
-  if ((rc = sums.alloc(sizeof(int64_t) * nt)) != HSM_OK) return rc;
-  if ((rc = offs.alloc(sizeof(int64_t) * (nt + 1))) != HSM_OK) return rc;
-  hipLaunchKernelGGL(k_tile_sums<T>, dim3((unsigned)nt), dim3(kBS), 0, s, in, n, sums.as<int64_t>());
+  if (!ws) {
+    if ((rc = own.alloc(sizeof(int64_t) * scan_ws(n), s)) != HSM_OK) return rc;
+    ws = own.as<int64_t>();
+  }
+  int64_t *sums = ws, *offs = ws + nt;
+  hipLaunchKernelGGL(k_tile_sums<T>, dim3((unsigned)nt), dim3(kBS), 0, s, in, n, sums);
   HSM_HIP(hipGetLastError());
-  if ((rc = scan_any<int64_t>(sums.as<int64_t>(), offs.as<int64_t>(), nt, s)) != HSM_OK) return rc;
-  hipLaunchKernelGGL(k_tile_scan<T>, dim3((unsigned)nt), dim3(kBS), 0, s, in, n,
-                     (const int64_t *)offs.as<int64_t>(), out, 1);
+  if ((rc = scan_any<int64_t>(sums, offs, nt, s, ws + 2 * nt + 1)) != HSM_OK) return rc;
+  hipLaunchKernelGGL(k_tile_scan<T>, dim3((unsigned)nt), dim3(kBS), 0, s, in, n, (const int64_t *)offs, out, 1);
   HSM_HIP(hipGetLastError());
-  // keep the temporaries alive until the kernels ran
-  HSM_HIP(hipStreamSynchronize(s));
-  return HSM_OK;
+  return HSM_OK;    // the temporaries are released in stream order
 }
 
 }  // namespace
 
-hsm_status scan_i32_to_i64(const int32_t *in, int64_t *out, int64_t n, hipStream_t s) {
-  return scan_any<int32_t>(in, out, n, s);
+hsm_status scan_i32_to_i64(const int32_t *in, int64_t *out, int64_t n, hipStream_t s, int64_t *ws) {
+  return scan_any<int32_t>(in, out, n, s, ws);
+}
+
+int64_t scan_i32_to_i64_ws(int64_t n) { return scan_ws(n); }
+
+hipMemPool_t scratch_pool(int device) {
+  static std::mutex mu;
+  static hipMemPool_t pools[kMaxDevices] = {};
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> g(mu);
+  if (!pools[device]) {
+    hipMemPoolProps props;
+    std::memset(&props, 0, sizeof(props));
+    props.allocType = hipMemAllocationTypePinned;
+    props.handleTypes = hipMemHandleTypeNone;
+    props.location.type = hipMemLocationTypeDevice;
+    props.location.id = device;
+    hipMemPool_t pool = nullptr;
+    if (hipMemPoolCreate(&pool, &props) != hipSuccess) return nullptr;
+    uint64_t keep = kScratchPoolKeep;
+    if (hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep) != hipSuccess) {
+      (void)hipMemPoolDestroy(pool);
+      return nullptr;
+    }
+    pools[device] = pool;
+  }
+  return pools[device];
 }
 
 }  // namespace hsm
