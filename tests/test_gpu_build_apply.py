@@ -226,6 +226,42 @@ def test_crowded_node_is_classified_exactly():
     assert np.array_equal(ex["off"], ora["off"]) and np.array_equal(ex["idx"], ora["idx"])
 
 
+@pytest.mark.parametrize("d", [2, 3])
+def test_cross_test_at_the_tolerance_edge(d):
+    # a lattice (off the origin, so cell edges fall anywhere) whose nodes are
+    # moved along one axis by 0.5, 0.999, 1.001 or 2 times the cross tolerance
+    # (1e-6 h_r), plus a few near-twins of cross points: regular and scattered
+    # nodes on both sides of the rule, classes and stencils against the oracle
+    hsm = _hsm()
+    h = 0.1
+    nl = 20 if d == 2 else 8
+    g = 0.1234 + np.arange(nl) * h
+    xx = np.stack(np.meshgrid(*([g] * d), indexing="ij")).reshape(d, -1).copy()
+    rng = np.random.default_rng(40 + d)
+    tol = 1e-6 * h
+    n0 = xx.shape[1]
+    moved = rng.choice(n0, n0 // 3, replace=False)
+    ax = rng.integers(0, d, moved.size)
+    fac = rng.choice([0.5, 0.999, 1.001, 2.0], moved.size) * rng.choice([-1.0, 1.0], moved.size)
+    xx[ax, moved] += fac * tol
+    twins = rng.choice(n0, 6, replace=False)
+    extra = xx[:, twins] + 0.5 * tol * rng.choice([-1.0, 1.0], (d, 6))
+    xx = np.concatenate([xx, extra], axis=1)
+    n = xx.shape[1]
+    kind = np.zeros(n, np.uint8)
+    dev = torch.device("cuda")
+    st = hsm.build_stencils(torch.tensor(xx, device=dev), torch.tensor(kind, device=dev),
+                            torch.zeros((d, n), dtype=torch.float64, device=dev), h, 2 if d == 2 else 1)
+    ex = st.export()
+    ora = O.to_csr(O.build(xx, kind, np.zeros((d, n)), h, 2 if d == 2 else 1))
+    np.testing.assert_array_equal(ex["cls"], ora["cls"])
+    np.testing.assert_array_equal(ex["off"], ora["off"])
+    np.testing.assert_array_equal(ex["idx"], ora["idx"])
+    nreg = int((ex["cls"] == 0).sum())
+    print(f"d={d}: N={n}, regular {nreg}, scattered {n - nreg}")
+    assert 0 < nreg < n
+
+
 def test_ragged_tiny_domain_builds():
     # a domain just above the stencil size, node count not a multiple of any block size
     s = ng.random_cloud(13, 2, seed=3)
