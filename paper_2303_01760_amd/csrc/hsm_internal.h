@@ -342,17 +342,27 @@ template <int W, int K = 12, class FW, class FV, class FU, class FS>
 __device__ __forceinline__ void gather_chunks(const void *idx, uint32_t cnt, uint32_t t, FW &&wload, FV &&vload,
                                               FU &&use, FS &&settle) {
   constexpr int C = chunk_of(W, K);
+  // with two chunks, both chunks' indices in one round of loads: the second
+  // chunk then waits for its values (and weights) only, not for its indices
+  // first (more chunks would hold too many registers)
+  constexpr bool pre = (W / C == 2);
+  int32_t nb[pre ? W : C];
+  if (pre) {
+#pragma unroll
+    for (int j = 0; j < (pre ? W : C); ++j) nb[j] = ld_soa<int32_t>(idx, cnt, j, t);
+  }
 #pragma unroll
   for (int j0 = 0; j0 < W; j0 += C) {
-    int32_t nb[C];
     decltype(wload(0)) wv[C];
     decltype(vload(0)) vv[C];
+    if (!pre) {
 #pragma unroll
-    for (int c = 0; c < C; ++c) nb[c] = ld_soa<int32_t>(idx, cnt, j0 + c, t);
+      for (int c = 0; c < C; ++c) nb[c] = ld_soa<int32_t>(idx, cnt, j0 + c, t);
+    }
 #pragma unroll
     for (int c = 0; c < C; ++c) wv[c] = wload(j0 + c);
 #pragma unroll
-    for (int c = 0; c < C; ++c) vv[c] = vload(nb[c]);
+    for (int c = 0; c < C; ++c) vv[c] = vload(nb[(pre ? j0 : 0) + c]);
 #pragma unroll
     for (int c = 0; c < C; ++c) use(j0 + c, wv[c], vv[c]);
     if (j0 + C < W) {
