@@ -262,6 +262,26 @@ def test_cross_test_at_the_tolerance_edge(d):
     assert 0 < nreg < n
 
 
+def test_builds_reuse_scratch_and_repeat_bitwise():
+    # the build's temporaries come from a pool that keeps released memory:
+    # a build, a larger one in between (on another stream), and the first
+    # again must give bit-identical classes, stencils and weights
+    hsm = _hsm()
+    a = ng.obstacles2d(h=0.01, n_obst=6, seed=11)
+    b = ng.obstacles3d(h=0.04, n_obst=3, seed=5)
+    xa, ka, na = _dev(a)
+    first = hsm.build_stencils(xa, ka, na, a.h, 2).export()
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        xb, kb, nb = _dev(b)
+        mid = hsm.build_stencils(xb, kb, nb, b.h, 2)
+    torch.cuda.synchronize()
+    assert mid.info()["n_regular"] > 0
+    again = hsm.build_stencils(xa, ka, na, a.h, 2).export()
+    for key in ("cls", "off", "idx", "w"):
+        assert np.array_equal(first[key], again[key]), key
+
+
 def test_ragged_tiny_domain_builds():
     # a domain just above the stencil size, node count not a multiple of any block size
     s = ng.random_cloud(13, 2, seed=3)
