@@ -242,7 +242,11 @@ def batch2d(n_domains: int = 512, nmin: int = 1000, nmax: int = 50000, n_obst: i
     """Many independent 2D obstacle domains of uneven size: domain k draws, from
     seed seed_base + k, a node count log-uniform in [nmin, nmax] (which sets its
     lattice spacing h = 1/round(sqrt(count / 0.8))), a scattered degree m in
-    {2, 4}, and n_obst circles of radius 0.04-0.1 with a band max(0.05, 3h)."""
+    {2, 4}, and n_obst circles of radius max(0.04, 3.5h) to max(0.1, 5h) with a
+    band max(0.05, 3h).  Every circle spans at least 3.5 node spacings in
+    radius: circles of 1.6h make the explicit projection grow without bound
+    (with m = 2 and m = 4 alike), circles of 3h stay stable.  Where n_obst such
+    circles do not fit, the domain takes one fewer until they do."""
     sets, hs, ms = [], [], []
     for k in range(n_domains):
         rng = np.random.default_rng(seed_base + k)
@@ -250,8 +254,15 @@ def batch2d(n_domains: int = 512, nmin: int = 1000, nmax: int = 50000, n_obst: i
         m = int(rng.choice([2, 4]))
         h = 1.0 / max(8, int(round(np.sqrt(target / 0.8))))   # the lattice must divide the unit box
         band = max(0.05, 3.0 * h)
-        s = generate(2, h, obst_band=band, n_obst=n_obst, rmin=0.04, rmax=0.1,
-                     wall_kind=[KIND_NEUMANN] * 4, seed=seed_base + k, name=f"batch_{k}")
+        s = None
+        for no in range(n_obst, 0, -1):
+            try:
+                s = generate(2, h, obst_band=band, n_obst=no, rmin=max(0.04, 3.5 * h), rmax=max(0.1, 5.0 * h),
+                             wall_kind=[KIND_NEUMANN] * 4, seed=seed_base + k, name=f"batch_{k}")
+                break
+            except ValueError:
+                if no == 1:
+                    raise
         sets.append(s)
         hs.append(h)
         ms.append(m)
