@@ -541,6 +541,18 @@ def main():
     if stepping:
         out["krylov_iters_per_time_step"] = hy["krylov_iters"] / (args.steps * args.time_steps)
         out["phase_mean_ms"] = {k: v[0] for k, v in pt.items()}
+        # physical sanity of the last timed step's fields (from rest, |v| stays well below 1 over these few
+        # steps; a node set the explicit scheme cannot handle shows up here as growth by orders of magnitude)
+        if "final" in hy:
+            vf, Tf = hy["final"][0], hy["final"][1]
+            vmag = np.abs(vf).max(axis=0)
+            fields = dict(max_abs_v=float(vmag.max()), max_abs_T=float(np.abs(Tf).max()),
+                          finite=bool(np.isfinite(vf).all() and np.isfinite(Tf).all()))
+            if multi:
+                per_dom = np.maximum.reduceat(vmag, s.off[:-1])
+                fields.update(worst_domain=int(np.argmax(per_dom)), domains_max_abs_v_above_1=int((per_dom > 1).sum()),
+                              median_domain_max_abs_v=float(np.median(per_dom)))
+            out["fields_after_time_steps"] = fields
     if "all_scattered" in results:
         a = results["all_scattered"]
         out["all_scattered"] = dict(value=a["applies"] / a["elapsed_s"], ms_per_step=a["elapsed_s"] / args.steps * 1e3,
