@@ -1,0 +1,28 @@
+"""Checks of the seeded input generators (CPU only).
+
+The 512-domain batch must hold node sets the explicit scheme can step: its
+smallest domains (the coarsest, whose circles span the fewest node spacings)
+are stepped by the oracle from rest and must stay physical.
+"""
+import numpy as np
+
+from oracle import oracle as O
+from paper_2303_01760_amd import nodegen as ng
+
+
+def test_smallest_batch_domains_step_stably():
+    b = ng.batch2d()
+    counts = np.diff(b.off)
+    dt = 0.1 * float(np.min(b.h)) ** 2 / 2          # the batch's common time step
+    for k in np.argsort(counts)[:3]:
+        a, e = int(b.off[k]), int(b.off[k + 1])
+        x, kind, nrm = b.x[:, a:e].copy(), b.kind[a:e].copy(), b.normal[:, a:e].copy()
+        csr = O.to_csr(O.build(x, kind, nrm, float(b.h[k]), int(b.m[k])))
+        v = np.zeros((2, e - a))
+        T = np.where(kind == 1, b.tbc[a:e], 0.0)
+        p = np.zeros(e - a + 1)
+        sim = O.Sim(csr, kind, solver=1)
+        sim.step(v, T, p, 5, 1e5, 0.71, dt, 0.5, tol=1e-10, maxiter=200000)
+        # buoyancy alone from rest: |v| ~ Ra Pr |T - T_ref| t = 0.14 after five steps
+        assert np.isfinite(v).all() and np.abs(v).max() < 1.0, (int(k), float(np.abs(v).max()))
+        assert np.abs(T).max() <= 1.0 + 1e-9
