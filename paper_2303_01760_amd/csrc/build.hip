@@ -1,6 +1,7 @@
-// Stencil construction on the GPU: per-domain cell grids, exact k-nearest-
-// neighbour search, the regular/scattered classifier, the width-bucketed
-// internal node order, and the per-bucket stencil index arrays.
+// Stencil construction on the GPU: per-domain cell grids, the
+// regular/scattered classifier, exact k-nearest-neighbour search for the
+// nodes that take RBF-FD stencils, the width-bucketed internal node order,
+// and the per-bucket stencil index arrays.
 //
 // Compiled with -ffp-contract=off: squared distances and the axis-cross test
 // are rounded step by step exactly as written, so neighbour lists and classes
