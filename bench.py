@@ -367,15 +367,19 @@ def main():
         return st
 
     def apply_timing(st, dtype, reps=20, bucket_mask=None):
-        """Mean device time of one fused 3-operator apply to one field (events on the launch stream);
-        with bucket_mask, of the apply restricted to those width buckets."""
+        """Mean device time of one fused 3-operator apply to one field; with bucket_mask, of the apply
+        restricted to those width buckets.  Timed two ways, both between events on the launch stream:
+        reps eager launches back to back, and the same reps launches captured in a graph and replayed.
+        From Python an eager launch costs the host about 8 us, which exceeds a short launch's device time;
+        a graph node adds its own per-kernel overhead instead.  Returns (the faster mean, eager mean,
+        replay mean); the replay's result must equal the eager one."""
         u = st.to_internal(fields[0])
         if dtype != hsm.F64:
             u = u.float()
-        out = torch.empty((3, s.n), dtype=u.dtype, device=dev)
+        out = torch.zeros((3, s.n), dtype=u.dtype, device=dev)   # a bucket-masked apply leaves other rows as they are
         run = ((lambda: st.apply(u, ops, dtype, out=out)) if bucket_mask is None
                else (lambda: st.apply_buckets(u, ops, bucket_mask, dtype, out=out)))
-        for _ in range(3):
+        for _ in range(3):          # also builds and uploads the launch tables
             run()
         torch.cuda.synchronize()
         a0, a1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -384,7 +388,29 @@ def main():
             run()
         a1.record()
         torch.cuda.synchronize()
-        return a0.elapsed_time(a1) / reps
+        eager_ms = a0.elapsed_time(a1) / reps
+        eager = out.clone()
+        g = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            with torch.cuda.graph(g, stream=side):
+                for _ in range(reps):
+                    run()
+        torch.cuda.synchronize()
+        graph_ms = None
+        for _ in range(2):          # the first replay warms up, the second is timed
+            out.zero_()
+            torch.cuda.synchronize()
+            a0.record()
+            g.replay()
+            a1.record()
+            torch.cuda.synchronize()
+            graph_ms = a0.elapsed_time(a1) / reps
+            if not torch.equal(out, eager):
+                raise RuntimeError("graph replay of the apply differs from the eager apply")
+        del g
+        return min(eager_ms, graph_ms), eager_ms, graph_ms
 
     fresh = lambda: dict(build_s=0.0, build_dev_ms=0.0, solve_dev_ms=0.0, applies=0, krylov_iters=0, solves=0,
                          ptimes={})
@@ -407,11 +433,11 @@ def main():
         bk = rec["info"]["buckets"]
         am = {}
         for lbl, dtp, fs in (("f64", hsm.F64, 8), ("f32_dot2", hsm.F32_COMP, 4)):
-            ms = apply_timing(st_last, dtp)
+            ms, ms_eager, ms_graph = apply_timing(st_last, dtp)
             by = apply_bytes(bk, s.n, nops, fs)
             am[lbl] = dict(mean_launch_ms=ms, bytes_per_launch=by, achieved_gbs=by / (ms * 1e-3) / 1e9,
                            frac=by / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                           node_applies_per_s=nops * s.n / (ms * 1e-3))
+                           node_applies_per_s=nops * s.n / (ms * 1e-3), eager_ms=ms_eager, graph_replay_ms=ms_graph)
         # FP32 and FP32+Dot2 applies against FP64 applies (one smooth field): against the FP64 apply of
         # the FP64 field (everything FP32 storage costs), and against the FP64 apply of the same
         # FP32-rounded field (the weights' rounding and the sums alone)
@@ -431,13 +457,14 @@ def main():
         for kb, (bt, bw, bc) in enumerate(info_last["buckets"]):
             if bc == 0:
                 continue
-            ms = apply_timing(st_last, hsm.F64, bucket_mask=1 << kb)
+            ms, ms_eager, ms_graph = apply_timing(st_last, hsm.F64, bucket_mask=1 << kb)
             by = apply_bytes([(bt, bw, bc)], bc, nops, 8)
             S = bw + (0 if bt == 0 else comb(bw_m(bw, D) + D, D))
             flops = (2.0 / 3.0) * S ** 3 + 2.0 * S * S * (D + 1)   # LU and d+1 solves per system
             sms = info_last["bucket_solve_ms"][kb] if kb < 16 else float("nan")
             per.append(dict(type=["regular", "scattered", "dirichlet_wall", "neumann_wall"][bt], width=bw, nodes=bc,
-                            apply_ms=ms, apply_node_applies_per_s=nops * bc / (ms * 1e-3),
+                            apply_ms=ms, apply_eager_ms=ms_eager, apply_graph_replay_ms=ms_graph,
+                            apply_node_applies_per_s=nops * bc / (ms * 1e-3),
                             apply_gbs=by / (ms * 1e-3) / 1e9, apply_frac=by / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                             solve_ms=sms, solves_per_s=bc / (sms * 1e-3) if sms > 0 else None,
                             solve_fp64_tflops=(bc * flops / (sms * 1e-3) / 1e12) if sms > 0 else None))

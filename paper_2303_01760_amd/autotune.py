@@ -6,8 +6,8 @@ in the order of the neighbour-search cells, numbered tile by tile (tiles of
 256 consecutive nodes is in space, and so how many of the values its stencils
 gather are already in the L2 cache of the XCD that runs it.  tune_tile builds
 the stencils once per candidate L and times the fused apply of d/dx, d/dy
-(, d/dz) and the Laplacian to one field (mean of `reps` launches between
-events on the launch stream, after warm-up).  It leaves the default only for
+(, d/dz) and the Laplacian to one field (mean of `reps` launches replayed
+from a graph between events, after warm-up).  It leaves the default only for
 a candidate faster by more than `margin`: differences within the noise of
 the timing would otherwise pick at random, and the pressure iteration, which
 gathers other vectors through the same order, need not follow the apply's
@@ -25,21 +25,33 @@ DEFAULT_TILE = {2: 3, 3: 2}
 
 
 def _time_apply(st: hsm.Stencils, d: int, reps: int) -> float:
+    """Mean time of one fused apply: reps launches captured in a graph and replayed between events, so the
+    host's per-launch cost does not leave the device idle between short launches."""
     ops = hsm.OP_DX | hsm.OP_DY | hsm.OP_LAP | (hsm.OP_DZ if d == 3 else 0)
     nops = bin(ops).count("1")
     dev = torch.device("cuda")
-    g = torch.Generator(device="cpu").manual_seed(2303017600)
-    u = torch.rand(st.n, generator=g, dtype=torch.float64).to(dev)
+    gen = torch.Generator(device="cpu").manual_seed(2303017600)
+    u = torch.rand(st.n, generator=gen, dtype=torch.float64).to(dev)
     out = torch.empty((nops, st.n), dtype=torch.float64, device=dev)
-    for _ in range(3):
+    for _ in range(3):              # also uploads the launch tables before the capture
         st.apply(u, ops, hsm.F64, out=out)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(graph, stream=side):
+            for _ in range(reps):
+                st.apply(u, ops, hsm.F64, out=out)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    graph.replay()
+    torch.cuda.synchronize()
     e0.record()
-    for _ in range(reps):
-        st.apply(u, ops, hsm.F64, out=out)
+    graph.replay()
     e1.record()
     torch.cuda.synchronize()
+    del graph
     return e0.elapsed_time(e1) / reps
 
 
