@@ -346,6 +346,14 @@ void *ng_generate(const ng_params *P, int64_t *n_out) {
       }
       (void)s;
       if (!inside) continue;
+      /* at least half the local spacing from every box face: the face lattice
+         keeps the fill away from the faces, but not along the edges where two
+         faces meet (their edge nodes are left out), nor between face nodes
+         where the local spacing is below the lattice spacing */
+      const double rp0 = spacing(P, S, p);
+      for (int a = 0; a < d; ++a)
+        if (p[a] < 0.5 * rp0 || p[a] > 1.0 - 0.5 * rp0) inside = 0;
+      if (!inside) continue;
       /* inside one of the scattered bands? */
       int inband = 0;
       for (int a = 0; a < d; ++a)
