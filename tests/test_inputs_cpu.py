@@ -26,3 +26,15 @@ def test_smallest_batch_domains_step_stably():
         # buoyancy alone from rest: |v| ~ Ra Pr |T - T_ref| t = 0.14 after five steps
         assert np.isfinite(v).all() and np.abs(v).max() < 1.0, (int(k), float(np.abs(v).max()))
         assert np.abs(T).max() <= 1.0 + 1e-9
+
+
+def test_fill_keeps_half_a_spacing_from_the_box():
+    # interior fill nodes stay at least half the local spacing (>= h_s / 2)
+    # from every box face, also along the 3D box edges where no wall nodes are
+    from paper_2303_01760_amd.irregular import node_set
+    for dim, ratio in ((3, 2.0), (2, 3.0)):
+        q = node_set(dim, "scattered", 4.0)
+        h_s = q.h / ratio
+        fill = q.kind == 0
+        gap = np.minimum(q.x[:, fill], 1.0 - q.x[:, fill]).min()
+        assert gap >= 0.5 * h_s * (1 - 1e-12), (dim, float(gap), h_s)
