@@ -78,3 +78,15 @@ def test_size_limits_and_empty_selections_are_rejected_on_the_host():
     assert L.hsm_apply_operator_buckets(None, 1, 0, 0, None, None, None) == hsm.E_INVALID
     assert b"no bucket" in L.hsm_last_error()
     assert L.hsm_stencils_condition(None, None, None) == hsm.E_INVALID
+
+
+def test_bench_refuses_more_than_one_gpu():
+    # the library has no multi-GPU path: bench.py says so and exits non-zero before touching a device
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=300)
+    assert r.returncode != 0
+    assert "one GPU" in r.stderr
+    assert r.stdout.strip() == ""
