@@ -63,12 +63,31 @@ __device__ __forceinline__ double wave_max(double v) {
   return v;
 }
 
-// maximum over each group of 64 / G consecutive lanes (G = 1 or 2)
+// Lanes per group when a wave holds G systems: 64, 32 or 21 (lane 63 idles
+// with G = 3, counted in the last group).
 template <int G>
-__device__ __forceinline__ double group_max(double v) {
+constexpr int group_lanes() { return G == 3 ? 21 : 64 / G; }
+
+// Maximum over the lanes of each group.  G = 1, 2: butterfly over aligned
+// lane blocks.  G = 3: cyclic doubling inside the group of 21 (each lane
+// ends with the maximum over 32 cyclically consecutive lanes, which covers
+// the group); `lane` counts in the group, `base` is its first lane.
+template <int G>
+__device__ __forceinline__ double group_max(double v, int lane = 0, int base = 0) {
+  if constexpr (G == 3) {
+    constexpr int GL = group_lanes<3>();
 #pragma unroll
-  for (int o = 32 / G; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-  return v;
+    for (int o = 1; o < 32; o <<= 1) {
+      int l = lane + o;
+      l = (l >= 2 * GL) ? l - 2 * GL : ((l >= GL) ? l - GL : l);
+      v = fmax(v, __shfl(v, base + l, 64));
+    }
+    return v;
+  } else {
+#pragma unroll
+    for (int o = 32 / G; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+  }
 }
 
 struct SolveArgs {
@@ -122,7 +141,7 @@ __device__ __forceinline__ void rbffd_rows(const SolveArgs &a, int64_t t, int la
     }
     r = sqrt(sq);
   }
-  s = group_max<G>(r);
+  s = group_max<G>(r, lane, grp * group_lanes<G>());
   double y[D];
 #pragma unroll
   for (int q = 0; q < D; ++q) y[q] = dxv[q] / s;
@@ -188,18 +207,19 @@ __device__ __forceinline__ void rbffd_rows(const SolveArgs &a, int64_t t, int la
 
 }
 
-// G systems per wave (G = 2 when S <= 32): lanes 32 g .. 32 g + 31 hold
-// system 2 b + g of block b.  Every system takes exactly the operations of
-// the one-system form; the pivot row reaches its group by lane permutes.
+// G systems per wave (G = 3 when S <= 21, 2 when S <= 32): lanes
+// GL g .. GL g + GL - 1 hold system G b + g of block b (GL = 21, 32).  Every
+// system takes exactly the operations of the one-system form; the pivot row
+// reaches its group by lane permutes.
 template <int D, int M, int NS, int G>
 __global__ __launch_bounds__(64) void k_rbffd(SolveArgs a) {
   constexpr int Q = Monos<D, M>::Q;
   constexpr int S = NS + Q;
   constexpr int R = D + 1;
-  constexpr int GL = 64 / G;          // lanes per group
+  constexpr int GL = group_lanes<G>();
   static_assert(S <= GL, "one system row per lane");
-  const int grp = (G == 1) ? 0 : (int)threadIdx.x / GL;
-  const int lane = (int)threadIdx.x - grp * GL;
+  const int grp = (G == 1) ? 0 : min((int)threadIdx.x / GL, G - 1);
+  const int lane = (int)threadIdx.x - grp * GL;      // lane 63 of G = 3: 21, past every row
   const int base = grp * GL;
   int64_t t;
   bool live = true;
@@ -223,7 +243,7 @@ __global__ __launch_bounds__(64) void k_rbffd(SolveArgs a) {
   double amax = 0.0;
 #pragma unroll
   for (int k = 0; k < S; ++k) amax = fmax(amax, fabs(Rw[k]));
-  amax = group_max<G>(amax);
+  amax = group_max<G>(amax, lane, base);
   const double thr = kPivotRel * amax;
   bool used = lane >= S;
   int pstep = used ? S : -1;
@@ -232,11 +252,11 @@ __global__ __launch_bounds__(64) void k_rbffd(SolveArgs a) {
 #pragma unroll
   for (int k = 0; k < S; ++k) {
     const double cand = used ? -1.0 : fabs(Rw[k]);
-    const double best = group_max<G>(cand);
+    const double best = group_max<G>(cand, lane, base);
     if (!(best > thr)) singular = true;
     if (G == 1 && singular) break;
     const unsigned long long mask = __ballot(!used && cand == best);
-    const unsigned long long gm = (G == 1) ? mask : ((mask >> base) & 0xffffffffull);
+    const unsigned long long gm = (G == 1) ? mask : ((mask >> base) & ((1ull << GL) - 1ull));
     const int p = gm ? __ffsll((long long)gm) - 1 : 0;
     piv[k] = p;
     double pk, pr[S], pb[R];
@@ -457,7 +477,12 @@ __global__ __launch_bounds__(128) void k_mon(SolveArgs a) {
 template <int D, int M, int NS>
 void launch_rbffd(const SolveArgs &a, hipStream_t s, int64_t nlist = -1) {
   constexpr int S = NS + Monos<D, M>::Q;
-  if constexpr (S <= 32) {
+  if constexpr (S <= 21) {
+    if (nlist < 0) {
+      hipLaunchKernelGGL((k_rbffd<D, M, NS, 3>), dim3((unsigned)((a.count + 2) / 3)), dim3(64), 0, s, a);
+      return;
+    }
+  } else if constexpr (S <= 32) {
     if (nlist < 0) {
       hipLaunchKernelGGL((k_rbffd<D, M, NS, 2>), dim3((unsigned)((a.count + 1) / 2)), dim3(64), 0, s, a);
       return;
