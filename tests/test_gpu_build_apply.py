@@ -282,9 +282,11 @@ def test_builds_reuse_scratch_and_repeat_bitwise():
         assert np.array_equal(first[key], again[key]), key
 
 
-def test_ragged_tiny_domain_builds():
-    # a domain just above the stencil size, node count not a multiple of any block size
-    s = ng.random_cloud(13, 2, seed=3)
+@pytest.mark.parametrize("n", [13, 14, 15])
+def test_ragged_tiny_domain_builds(n):
+    # a domain just above the stencil size, node count not a multiple of any block size; 13, 14, 15 systems
+    # leave one, two and no groups idle in the last wave of the three-systems-per-wave solve
+    s = ng.random_cloud(n, 2, seed=3)
     _compare_full(s, 2, O.ALL_SCATTERED)
 
 
