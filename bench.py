@@ -30,7 +30,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "stencil node-applies/s + weight solves/s, hybrid vs all-scattered, 1 GPU"
 HBM_PEAK_GBS = 8000.0
-KRYLOV_CHUNK = 16      # BiCGSTAB iterations per queued batch
+KRYLOV_CHUNK = 32      # BiCGSTAB iterations per queued batch
 PMC_COMMAND = ('rocprofv3 --pmc {} --kernel-include-regex "k_bicg_pv|k_bicg_st|k_stream_copy" --output-format csv '
                '-d <dir> -o run -- python3 bench.py --steps 1 --warmup 0 --time-steps 1 --no-cpu-baseline '
                '--skip-all-scattered --skip-fp32-form')

@@ -207,7 +207,7 @@ typedef struct {
   double krylov_tol;       /* relative residual of the pressure solve, e.g. 1e-12 */
   int32_t krylov_maxiter;  /* iteration cap per step */
   int32_t field_dtype;     /* HSM_F64, or HSM_F32_COMP: see below */
-  int32_t krylov_chunk;    /* iterations per device-side batch between convergence checks (0 = default) */
+  int32_t krylov_chunk;    /* iterations per device-side batch between convergence checks (0 = 32) */
   int32_t launch_mode;     /* 0: replay captured HIP graphs, 1: launch kernels directly (same kernels) */
   int32_t profile;         /* 1: bracket each phase (pre, Krylov batch, post) with HIP events; see hsm_sim_phase_times */
   int32_t reduce_mode;     /* Krylov dot products: 0 auto, 1 each block reduces all partials, 2 one-block kernel */

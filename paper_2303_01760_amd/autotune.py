@@ -7,7 +7,7 @@ in the order of the neighbour-search cells, numbered tile by tile (tiles of
 gather are already in the L2 cache of the XCD that runs it.  tune_tile builds
 the stencils once per candidate L and times the fused apply of d/dx, d/dy
 (, d/dz) and the Laplacian to one field (mean of `reps` launches replayed
-from a graph between events, after warm-up).  It leaves the default only for
+from a graph between events, after warm-up; the median of five replays).  It leaves the default only for
 a candidate faster by more than `margin`: differences within the noise of
 the timing would otherwise pick at random, and the pressure iteration, which
 gathers other vectors through the same order, need not follow the apply's
@@ -47,12 +47,15 @@ def _time_apply(st: hsm.Stencils, d: int, reps: int) -> float:
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     graph.replay()
     torch.cuda.synchronize()
-    e0.record()
-    graph.replay()
-    e1.record()
-    torch.cuda.synchronize()
+    times = []
+    for _ in range(5):              # the median of five replays: one disturbed replay does not decide
+        e0.record()
+        graph.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1) / reps)
     del graph
-    return e0.elapsed_time(e1) / reps
+    return sorted(times)[len(times) // 2]
 
 
 def tune_tile(x: torch.Tensor, kind: torch.Tensor, normal: torch.Tensor, h, m, mode=hsm.MODE_HYBRID,

@@ -36,7 +36,7 @@ struct hsm_sim {
   hsm_sim_params prm{};
   int d = 0;
   int64_t N = 0;
-  int chunk = 16;
+  int chunk = 32;
   DBuf v, vs, T[2], vec[2], pairs[4], partR, partA, partB, sc, wP[kMaxBuckets];
   double *x = nullptr, *rh = nullptr;
   double2 *ST = nullptr, *PV[2] = {nullptr, nullptr}, *RV = nullptr;
@@ -339,7 +339,7 @@ hsm_status hsm_sim_create(const hsm_stencils *st, const hsm_sim_params *prm, con
   }
   auto m = std::make_unique<hsm_sim>();
   m->st = st; m->prm = *prm; m->d = st->d; m->N = st->N;
-  m->chunk = prm->krylov_chunk ? prm->krylov_chunk : 16;
+  m->chunk = prm->krylov_chunk ? prm->krylov_chunk : 32;
   if (m->chunk & 1) m->chunk += 1;   // even: ping-pong buffers line up across batches
   const int64_t N = st->N, d = st->d;
   hipStream_t us = (hipStream_t)stream;
