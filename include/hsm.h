@@ -149,7 +149,7 @@ hsm_status hsm_stencils_export(const hsm_stencils *st, uint8_t *host_class, int6
                                int32_t *host_idx, double *host_w, void *stream);
 
 /*
- * hsm_stencils_condition -- the stability diagnostic of Section 2.2 (Fig. 2):
+ * hsm_stencils_condition -- the stability diagnostic of Section 2.1 (Fig. 2):
  * for every node, the 2-norm condition number kappa(M) = |M|_2 |M^-1|_2 =
  * sigma_max / sigma_min of the local system solved for its weights (the
  * matrix is shared by every operator of the node): the RBF-FD matrix

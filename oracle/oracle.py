@@ -209,7 +209,7 @@ def build(x, kind, normal, h, m, mode=HYBRID, dom_off=None, queries=None, n=None
 
 
 def local_matrix(xs, m=None):
-    """The matrix M of a node's local system M w = l (Section 2.2) for stencil
+    """The matrix M of a node's local system M w = l (Section 2.1) for stencil
     positions xs [n, d], centre first, in the solve's local coordinates
     y = (x - x_c) / s, s = max_j |x_j - x_c| (reading R5).  m=None: the MON
     matrix of a regular node (rows: the basis 1, y_a, y_a^2; columns: the
@@ -232,7 +232,7 @@ def local_matrix(xs, m=None):
 
 def condition(x, kind, normal, h, m, mode=HYBRID, dom_off=None, queries=None, n=None):
     """kappa(M) = |M|_2 |M^-1|_2 = sigma_max / sigma_min of each query node's
-    local system (Section 2.2, Fig. 2), singular values by LAPACK.  The system
+    local system (Section 2.1, Fig. 2), singular values by LAPACK.  The system
     is the one solved for the node's weights: MON at regular nodes, RBF-FD at
     scattered ones, with degree m-1 at a wall node whose degree-m system is
     singular (reading R17)."""

@@ -10,9 +10,14 @@
 // Precisions: FP64 (fused multiply-add accumulation); FP32; FP32 with
 // compensated products and sums (Ogita, Rump, Oishi 2005, "Dot2": TwoProduct
 // by FMA, Knuth's TwoSum), which evaluates the FP32 dot product as if in
-// twice the working precision.  Built with -ffp-contract=off; every FMA below
-// is written out.
+// twice the working precision.  Both FP32 forms sum w_j (u_j - u_c) over the
+// non-centre entries (equal to Eq. (1): the weights of every operator sum to
+// zero), so the error of each rounded weight scales with a difference of
+// nearby values, not with the field's magnitude.  Built with
+// -ffp-contract=off; every FMA below is written out.
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 
 #include "hsm_internal.h"
 
@@ -49,20 +54,32 @@ __device__ __forceinline__ void apply_node(const ApplyArgs &a, const BucketDesc 
     live[k] = !a.ld_wall_only[k] || wall;
     row0[k] = (uint32_t)((live[k] ? a.ld_slot[k] : 0) * width);   // a present row keeps every load valid
   }
+  // FP32: the difference form sum_{j>=1} w_j (u_j - u_c), u_c the centre
+  // value (stencil entry 0).  Every operator annihilates constants, so its
+  // weights sum to zero and this equals Eq. (1); but the rounding of each
+  // FP32 weight then multiplies a difference of nearby values instead of the
+  // value itself, and the centre weight is not read.
+  constexpr bool kDiff = std::is_same<T, float>::value;
   A acc[NL];
 #pragma unroll
   for (int k = 0; k < NL; ++k) acc[k].init();
+  T uc = T(0);
   const Buf ub = plane(static_cast<const T *>(a.u), a.N, 0);
   const auto wl = [&](int j) __attribute__((always_inline)) {
     Pack<T, NL> r;
 #pragma unroll
-    for (int k = 0; k < NL; ++k) r.v[k] = ld_soa<T>(b.w, cnt, row0[k] + j, t32);
+    for (int k = 0; k < NL; ++k) r.v[k] = (kDiff && j == 0) ? T(0) : ld_soa<T>(b.w, cnt, row0[k] + j, t32);
     return r;
   };
   const auto vl = [&](int32_t nb) __attribute__((always_inline)) { return ld_at<T>(ub, nb); };
-  const auto use = [&](int, const Pack<T, NL> &wv, T uv) __attribute__((always_inline)) {
+  const auto use = [&](int j, const Pack<T, NL> &wv, T uv) __attribute__((always_inline)) {
+    if (kDiff && j == 0) {
+      uc = uv;
+      return;
+    }
+    const T du = kDiff ? T(uv - uc) : uv;
 #pragma unroll
-    for (int k = 0; k < NL; ++k) acc[k].add(wv.v[k], uv);
+    for (int k = 0; k < NL; ++k) acc[k].add(wv.v[k], du);
   };
   if constexpr (W > 0) {
     gather_chunks<W, 8>(b.idx, cnt, t32, wl, vl, use, [&]() __attribute__((always_inline)) {

@@ -127,6 +127,17 @@ __device__ __forceinline__ void with_width(int w, F &&f) {
   else with_width3(w, f);
 }
 
+// Field operators of the FP32 form act on differences from the centre value,
+// sum_{j>=1} w_j (u_j - u_c): equal to Eq. (1), because the weights of every
+// operator (each annihilates constants) sum to zero, but the rounding of an
+// FP32 weight then scales with a difference of nearby values rather than with
+// the value itself.  That matters where a field is a large smooth part plus a
+// small one: the pressure is nearly hydrostatic (its gradient balances the
+// buoyancy), and the velocity is what is left after the projection removes
+// that balance.  The FP64 form keeps Eq. (1) as written.
+template <class FT>
+constexpr bool kDiffForm = std::is_same<FT, float>::value;
+
 // Cross-lane moves by DPP (data-parallel primitives: a VALU operand read
 // from another lane of the same row of 16), on the two halves of a double.
 template <int CTRL>
@@ -587,12 +598,15 @@ __global__ __launch_bounds__(kBS) void k_predict(SimArgs a) {
   for (int c = 0; c < D; ++c) vb[c] = plane(v, N, c);
   const double Ti = (double)static_cast<const FT *>(a.T)[i], Tref = a.T_ref, Ra = a.Ra, Pr = a.Pr, dt = a.dt;
   using AccT = FieldAcc<FT>;
+  constexpr bool kDiff = kDiffForm<FT>;
   with_width<D>(b.width, [&](auto wc) __attribute__((always_inline)) {
     constexpr int W = decltype(wc)::value;
     AccT g[D][D], L[D];
+    FT uc[D];
 #pragma unroll
     for (int c = 0; c < D; ++c) {
       L[c].init();
+      uc[c] = FT(0);
 #pragma unroll
       for (int q = 0; q < D; ++q) g[c][q].init();
     }
@@ -601,7 +615,7 @@ __global__ __launch_bounds__(kBS) void k_predict(SimArgs a) {
         [&](int j) __attribute__((always_inline)) {
           Pack<FT, D + 1> r;
 #pragma unroll
-          for (int q = 0; q <= D; ++q) r.v[q] = ld_soa<FT>(b.w, cnt32, q * W + j, t32);
+          for (int q = 0; q <= D; ++q) r.v[q] = (kDiff && j == 0) ? FT(0) : ld_soa<FT>(b.w, cnt32, q * W + j, t32);
           return r;
         },
         [&](int32_t nb) __attribute__((always_inline)) {
@@ -610,12 +624,18 @@ __global__ __launch_bounds__(kBS) void k_predict(SimArgs a) {
           for (int c = 0; c < D; ++c) r.v[c] = ld_at<FT>(vb[c], nb);
           return r;
         },
-        [&](int, const Pack<FT, D + 1> &wq, const Pack<FT, D> &u) __attribute__((always_inline)) {
+        [&](int j, const Pack<FT, D + 1> &wq, const Pack<FT, D> &u) __attribute__((always_inline)) {
+          if (kDiff && j == 0) {
+#pragma unroll
+            for (int c = 0; c < D; ++c) uc[c] = u.v[c];
+            return;
+          }
 #pragma unroll
           for (int c = 0; c < D; ++c) {
+            const FT du = kDiff ? FT(u.v[c] - uc[c]) : u.v[c];
 #pragma unroll
-            for (int q = 0; q < D; ++q) g[c][q].add(wq.v[q], u.v[c]);
-            L[c].add(wq.v[D], u.v[c]);
+            for (int q = 0; q < D; ++q) g[c][q].add(wq.v[q], du);
+            L[c].add(wq.v[D], du);
           }
         },
         [&]() __attribute__((always_inline)) {
@@ -672,11 +692,15 @@ __global__ __launch_bounds__(kBS) void k_rhs(SimArgs a) {
     const double dt = a.dt;
     double r = 0.0, rhs = 0.0;
     using AccT = FieldAcc<FT>;
+    constexpr bool kDiff = kDiffForm<FT>;
     with_width<D>(b.width, [&](auto wc) __attribute__((always_inline)) {
       constexpr int W = decltype(wc)::value;
       double Ap = 0.0;
       AccT div;
       div.init();
+      FT uc[D];
+#pragma unroll
+      for (int q = 0; q < D; ++q) uc[q] = FT(0);
       gather_chunks<W>(
           b.idx, cnt32, t32,
           [&](int j) __attribute__((always_inline)) {
@@ -684,7 +708,8 @@ __global__ __launch_bounds__(kBS) void k_rhs(SimArgs a) {
             wp.v[0] = ld_soa<double>(b.wP, cnt32, j, t32);
             Pack<FT, D> wd;
 #pragma unroll
-            for (int q = 0; q < D; ++q) wd.v[q] = ld_soa<FT>(b.w, cnt32, q * W + j, t32);   // unused at walls
+            for (int q = 0; q < D; ++q)   // unused at walls
+              wd.v[q] = (kDiff && j == 0) ? FT(0) : ld_soa<FT>(b.w, cnt32, q * W + j, t32);
             return Pack2<double, 1, FT, D>{wp, wd};
           },
           [&](int32_t nb) __attribute__((always_inline)) {
@@ -695,12 +720,16 @@ __global__ __launch_bounds__(kBS) void k_rhs(SimArgs a) {
             for (int q = 0; q < D; ++q) u.v[q] = ld_at<FT>(vsb[q], nb);
             return Pack2<double, 1, FT, D>{xp, u};
           },
-          [&](int, const Pack2<double, 1, FT, D> &wq, const Pack2<double, 1, FT, D> &u)
+          [&](int j, const Pack2<double, 1, FT, D> &wq, const Pack2<double, 1, FT, D> &u)
               __attribute__((always_inline)) {
                 Ap = fma(wq.a.v[0], u.a.v[0], Ap);
-                if (!wall)
+                if (kDiff && j == 0) {
 #pragma unroll
-                  for (int q = 0; q < D; ++q) div.add(wq.b.v[q], u.b.v[q]);
+                  for (int q = 0; q < D; ++q) uc[q] = u.b.v[q];
+                } else if (!wall) {
+#pragma unroll
+                  for (int q = 0; q < D; ++q) div.add(wq.b.v[q], kDiff ? FT(u.b.v[q] - uc[q]) : u.b.v[q]);
+                }
               },
           [&]() __attribute__((always_inline)) { pin(Ap); div.settle(); });
       if (!wall) rhs = (div.get_d() / dt) / (double)ld_soa<FT>(b.w, cnt32, D * W, t32);
@@ -1019,7 +1048,8 @@ __global__ __launch_bounds__(kRedThreads) void k_chunk_end(SimArgs a) {
 // -------------------------------------------- projection + heat transport --
 // v = v* - dt grad p at interior nodes (0 at walls); T' = T + dt (lap T -
 // v.grad T) with the new velocity (Eq. (4)); Dirichlet walls keep T.  The
-// pressure gradient reads FP64 p with FT weights, accumulated in FP64.
+// pressure gradient reads FP64 p with FT weights, accumulated in FP64 (in
+// the FP32 form over FP64 differences p_j - p_c).
 template <int D, class FT>
 __global__ __launch_bounds__(kBS) void k_correct_heat(SimArgs a) {
   const BlockDesc b = a.blk[blockIdx.x];
@@ -1049,10 +1079,13 @@ __global__ __launch_bounds__(kBS) void k_correct_heat(SimArgs a) {
   const FT *__restrict__ vs = static_cast<const FT *>(a.vs);
   const double dt = a.dt;
   using AccT = FieldAcc<FT>;
+  constexpr bool kDiff = kDiffForm<FT>;
   with_width<D>(b.width, [&](auto wc) __attribute__((always_inline)) {
     constexpr int W = decltype(wc)::value;
     double gp[D];
     AccT gT[D], LT;
+    double pc = 0.0;
+    FT Tc = FT(0);
     LT.init();
 #pragma unroll
     for (int q = 0; q < D; ++q) { gp[q] = 0.0; gT[q].init(); }
@@ -1061,7 +1094,7 @@ __global__ __launch_bounds__(kBS) void k_correct_heat(SimArgs a) {
         [&](int j) __attribute__((always_inline)) {
           Pack<FT, D + 1> r;
 #pragma unroll
-          for (int q = 0; q <= D; ++q) r.v[q] = ld_soa<FT>(b.w, cnt32, q * W + j, t32);
+          for (int q = 0; q <= D; ++q) r.v[q] = (kDiff && j == 0) ? FT(0) : ld_soa<FT>(b.w, cnt32, q * W + j, t32);
           return r;
         },
         [&](int32_t nb) __attribute__((always_inline)) {
@@ -1071,13 +1104,21 @@ __global__ __launch_bounds__(kBS) void k_correct_heat(SimArgs a) {
           r.b.v[0] = ld_at<FT>(Tb, nb);
           return r;
         },
-        [&](int, const Pack<FT, D + 1> &wq, const Pack2<double, 1, FT, 1> &u) __attribute__((always_inline)) {
+        [&](int j, const Pack<FT, D + 1> &wq, const Pack2<double, 1, FT, 1> &u) __attribute__((always_inline)) {
+          if (kDiff && j == 0) {
+            pc = u.a.v[0];
+            Tc = u.b.v[0];
+            return;
+          }
+          // FP32 form: the pressure difference is taken in FP64, then weighted
+          const double pj = kDiff ? u.a.v[0] - pc : u.a.v[0];
+          const FT Tj = kDiff ? FT(u.b.v[0] - Tc) : u.b.v[0];
 #pragma unroll
           for (int q = 0; q < D; ++q) {
-            gp[q] = fma((double)wq.v[q], u.a.v[0], gp[q]);
-            gT[q].add(wq.v[q], u.b.v[0]);
+            gp[q] = fma((double)wq.v[q], pj, gp[q]);
+            gT[q].add(wq.v[q], Tj);
           }
-          LT.add(wq.v[D], u.b.v[0]);
+          LT.add(wq.v[D], Tj);
         },
         [&]() __attribute__((always_inline)) {
           LT.settle();
@@ -1118,19 +1159,27 @@ __global__ __launch_bounds__(kBS) void k_neumann(SimArgs a) {
   const Buf Tnb = plane(Tn, N, 0);
   Scalars *sc = a.sc;
   using AccT = FieldAcc<FT>;
+  constexpr bool kDiff = kDiffForm<FT>;
   with_width<D>(b.width, [&](auto wc) __attribute__((always_inline)) {
     constexpr int W = decltype(wc)::value;
     AccT acc;
     acc.init();
+    FT T1 = FT(0);
     gather_chunks<W>(
         b.idx, cnt32, t32,
-        [&](int j) __attribute__((always_inline)) { return ld_soa<FT>(b.w, cnt32, (D + 1) * W + j, t32); },
+        [&](int j) __attribute__((always_inline)) {
+          return (kDiff && j == 1) ? FT(0) : ld_soa<FT>(b.w, cnt32, (D + 1) * W + j, t32);
+        },
         [&](int32_t nb) __attribute__((always_inline)) { return ld_at<FT>(Tnb, nb); },
         [&](int j, FT wj, FT Tj) __attribute__((always_inline)) {
-          if (j > 0) acc.add(wj, Tj);                  // the wall node's own entry is the unknown
+          // the wall node's own entry (j = 0) is the unknown
+          if (kDiff && j == 1) T1 = Tj;
+          else if (j > 0) acc.add(wj, kDiff ? FT(Tj - T1) : Tj);
         },
         [&]() __attribute__((always_inline)) { acc.settle(); });
-    const double Tb = -acc.get_d() / (double)ld_soa<FT>(b.w, cnt32, (D + 1) * W, t32);
+    // FP32 form: the weights sum to zero, so sum_{j>=1} w_j (T_j - T_1) + w_0 (T_b - T_1) = 0
+    const double w0 = (double)ld_soa<FT>(b.w, cnt32, (D + 1) * W, t32);
+    const double Tb = kDiff ? (double)T1 - acc.get_d() / w0 : -acc.get_d() / w0;
     Tn[i] = (FT)Tb;
     if (!isfinite(Tb)) atomicOr(&sc->nonfinite, 1);
   });

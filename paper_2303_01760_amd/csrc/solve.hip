@@ -494,7 +494,7 @@ void launch_rbffd(const SolveArgs &a, hipStream_t s, int64_t nlist = -1) {
 
 // ------------------------------------------------- condition numbers --
 // kappa(M) = |M|_2 |M^-1|_2 = sigma_max / sigma_min of a node's local system
-// (Section 2.2, Fig. 2).  The singular values come from one-sided Jacobi
+// (Section 2.1, Fig. 2).  The singular values come from one-sided Jacobi
 // (Hestenes 1958): plane rotations of column pairs until every pair is
 // orthogonal to working precision; the column norms are then the singular
 // values.  One wave per system, one column per lane; the S/2 disjoint pairs

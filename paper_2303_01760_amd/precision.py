@@ -85,10 +85,11 @@ def main(argv=None):
     ap.add_argument("--Ra", type=float, default=1e6)
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--report", type=int, default=50)
+    ap.add_argument("--tol", type=float, default=1e-10, help="relative residual of the pressure solves")
     ap.add_argument("--budget-s", type=float, default=1e30, help="stop (and say so) after this much stepping time")
     ap.add_argument("--out", default=None)
     a = ap.parse_args(argv)
-    r = compare(h=a.h, m=a.m, Ra=a.Ra, steps=a.steps, report=a.report, budget_s=a.budget_s,
+    r = compare(h=a.h, m=a.m, Ra=a.Ra, steps=a.steps, report=a.report, tol=a.tol, budget_s=a.budget_s,
                 progress=lambda s: print(s, file=sys.stderr, flush=True))
     print(json.dumps(dict(N=r["N"], steps=r["steps"], status=r["status"], final=r["final"])), flush=True)
     if a.out:

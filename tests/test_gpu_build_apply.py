@@ -285,7 +285,7 @@ def test_builds_reuse_scratch_and_repeat_bitwise():
 @pytest.mark.parametrize("n", [13, 14, 15])
 def test_ragged_tiny_domain_builds(n):
     # a domain just above the stencil size, node count not a multiple of any block size; 13, 14, 15 systems
-    # leave one, two and no groups idle in the last wave of the three-systems-per-wave solve
+    # leave two, one and no groups idle in the last wave of the three-systems-per-wave solve
     s = ng.random_cloud(n, 2, seed=3)
     _compare_full(s, 2, O.ALL_SCATTERED)
 
@@ -293,6 +293,27 @@ def test_ragged_tiny_domain_builds(n):
 # ------------------------------------------------------------------ apply --
 def _abs_bound(csr, wrow, u):
     return O.apply(dict(off=csr["off"], idx=csr["idx"]), np.abs(wrow), np.abs(u))
+
+
+def _diff_bound(csr, wrow, u):
+    """sum_j |w_ij| |u_j - u_i|: the scale of the FP32 applies' rounding errors
+    (they weight differences from the centre value)."""
+    n = len(csr["off"]) - 1
+    rows = np.repeat(np.arange(n), np.diff(csr["off"]))
+    return np.bincount(rows, weights=np.abs(wrow) * np.abs(u[csr["idx"]] - u[rows]), minlength=n)
+
+
+def _f32(a):
+    return np.asarray(a, np.float64).astype(np.float32).astype(np.float64)
+
+
+def _f32_bound(csr, wrow, u32, ref):
+    """Error scale of an FP32 apply against the oracle's FP64 apply of the same
+    FP32 field: sum_j |w_ij| |u_j - u_i| + |result|, plus 1e-7 sum_j |w_ij u_j|
+    for the oracle's own FP64 rounding (its Eq. (1) sum carries
+    u_i sum_j w_ij, zero only in exact arithmetic): about 1e-6 of the
+    sum_j |w_ij u_j| scale that FP32 weight rounding on the values would give."""
+    return _diff_bound(csr, wrow, u32) + np.abs(ref) + 1e-7 * _abs_bound(csr, wrow, u32)
 
 
 @pytest.mark.parametrize("mode", [O.HYBRID, O.ALL_SCATTERED])
@@ -305,17 +326,55 @@ def test_apply_parity_fp64_fp32(mode):
     rng = np.random.default_rng(0)
     u = np.sin(4 * s.x[0]) * np.cos(3 * s.x[1]) + 0.1 * rng.standard_normal(s.n)
     ops = hsm.OP_DX | hsm.OP_DY | hsm.OP_LAP | hsm.OP_DN
-    ref = [O.apply(ora, ora["w"][k], u) for k in range(3)] + [O.apply(ora, ora["wn"], u)]
-    bnd = [_abs_bound(ora, ora["w"][k], u) for k in range(3)] + [_abs_bound(ora, ora["wn"], u)]
+    wrows = [ora["w"][k] for k in range(3)] + [ora["wn"]]
+    ref = [O.apply(ora, w, u) for w in wrows]
+    bnd = [_abs_bound(ora, w, u) for w in wrows]
+    # FP32: against the oracle on the FP32-rounded field; the error scale is
+    # sum_j |w_ij| |u_j - u_i| (+ |result|), not sum_j |w_ij u_j|
+    u32 = _f32(u)
+    ref32 = [O.apply(ora, w, u32) for w in wrows]
+    bnd32 = [_f32_bound(ora, w, u32, r) for w, r in zip(wrows, ref32)]
     ut = torch.tensor(u, device="cuda")
     for dtype, tol in ((hsm.F64, 1e-12), (hsm.F32, 4e-6), (hsm.F32_COMP, 3e-7)):
         ui = st.to_internal(ut if dtype == hsm.F64 else ut.float())
         out = st.apply(ui, ops, dtype)
         for k in range(4):
             got = st.to_caller(out[k]).double().cpu().numpy()
-            err = np.abs(got - ref[k])
-            assert np.all(err <= tol * bnd[k] + 1e-300), (dtype, k, float((err / (bnd[k] + 1e-300)).max()))
+            r, b = (ref[k], bnd[k]) if dtype == hsm.F64 else (ref32[k], bnd32[k])
+            err = np.abs(got - r)
+            assert np.all(err <= tol * b + 1e-300), (dtype, k, float((err / (b + 1e-300)).max()))
     assert st.node_count(ops) == 3 * s.n + int((s.kind != 0).sum())
+
+
+def test_fp32_apply_error_follows_differences_not_magnitude():
+    """A field with a large constant part (as the nearly hydrostatic pressure
+    is): the FP32 applies' error must not grow with the constant."""
+    hsm = _hsm()
+    s = ng.obstacles2d(h=0.004, n_obst=8, seed=33)
+    x, kind, nrm = _dev(s)
+    st = hsm.build_stencils(x, kind, nrm, s.h, 4)
+    ora = O.to_csr(O.build(s.x, s.kind, s.normal, s.h, 4))
+    base = np.sin(3 * s.x[0]) * np.cos(2 * s.x[1])
+    ops = hsm.OP_DX | hsm.OP_DY | hsm.OP_LAP
+    errs = {}
+    for shift in (0.0, 1e3):
+        u32 = _f32(base + shift)
+        ui = st.to_internal(torch.tensor(u32, device="cuda").float())
+        for dtype in (hsm.F32, hsm.F32_COMP):
+            out = st.apply(ui, ops, dtype)
+            for k in range(3):
+                got = st.to_caller(out[k]).double().cpu().numpy()
+                ref = O.apply(ora, ora["w"][k], u32)
+                bnd = _f32_bound(ora, ora["w"][k], u32, ref)
+                tol = 4e-6 if dtype == hsm.F32 else 3e-7
+                err = np.abs(got - ref)
+                assert np.all(err <= tol * bnd), (shift, dtype, k, float((err / bnd).max()))
+                errs[(shift, dtype, k)] = float(np.linalg.norm(err) / np.linalg.norm(ref))
+    # the shifted field's differences carry the FP32 rounding of u + 1e3 (about
+    # 1e3 * 2^-24 each), so its error grows by that, not by the 1e3 x |w| of
+    # weight rounding on the values themselves
+    print({k: f"{v:.2e}" for k, v in errs.items()})
+    assert errs[(1e3, hsm.F32_COMP, 2)] < 1e-2
 
 
 def test_apply_compensated_beats_plain_fp32():
@@ -324,11 +383,17 @@ def test_apply_compensated_beats_plain_fp32():
     x, kind, nrm = _dev(s)
     st = hsm.build_stencils(x, kind, nrm, s.h, 4)
     ora = O.to_csr(O.build(s.x, s.kind, s.normal, s.h, 4))
-    # reference: the FP32-rounded oracle weights and field, summed by the oracle in FP64
+    # reference: the FP32-rounded oracle weights and field in the difference
+    # form the FP32 applies use, sum_{j>=1} w32_ij fl32(u32_j - u32_i), summed
+    # in FP64 (each product of two FP32 values is exact in FP64)
     u = np.cos(5 * s.x[0]) * np.sin(2 * s.x[1])
-    u32 = u.astype(np.float32).astype(np.float64)
-    w32 = ora["w"][2].astype(np.float32).astype(np.float64)
-    ref = O.apply(ora, w32, u32)
+    u32 = _f32(u)
+    w32 = _f32(ora["w"][2])
+    rows = np.repeat(np.arange(s.n), np.diff(ora["off"]))
+    du = _f32(u32[ora["idx"]] - u32[rows])
+    centre = np.zeros(len(rows), bool)
+    centre[ora["off"][:-1]] = True
+    ref = np.bincount(rows, weights=np.where(centre, 0.0, w32 * du), minlength=s.n)
     ui = st.to_internal(torch.tensor(u, device="cuda").float())
     plain = st.to_caller(st.apply(ui, hsm.OP_LAP, hsm.F32)[0]).double().cpu().numpy()
     comp = st.to_caller(st.apply(ui, hsm.OP_LAP, hsm.F32_COMP)[0]).double().cpu().numpy()
@@ -358,7 +423,7 @@ def _kappa_tol(k):
 
 @pytest.mark.parametrize("case", ["cavity_m2", "obstacles_m4", "cavity_all_scattered", "3d_m2"])
 def test_condition_numbers_match_oracle(case):
-    # Section 2.2 / Fig. 2: kappa(M) of every node's local system (MON at
+    # Section 2.1 / Fig. 2: kappa(M) of every node's local system (MON at
     # regular nodes, RBF-FD at scattered ones) against LAPACK's SVD of the
     # oracle's matrices
     hsm = _hsm()

@@ -640,7 +640,7 @@ def test_dvd_quarters_layout_and_conduction_nusselt():
 
 
 def test_condition_number_of_mon_cross_closed_form():
-    # Section 2.2: kappa(M) = sigma_max / sigma_min.  On a lattice cross, in
+    # Section 2.1: kappa(M) = sigma_max / sigma_min.  On a lattice cross, in
     # coordinates scaled by h, M M^T splits into the x_a rows (eigenvalue 2)
     # and the x_a^2 rows, whose span holds 1 and u = sum_a x_a^2 / sqrt(d) with
     # Gram block [[2d+1, 2 sqrt d], [2 sqrt d, 2]] (eigenvalues
