@@ -149,6 +149,24 @@ hsm_status hsm_stencils_export(const hsm_stencils *st, uint8_t *host_class, int6
                                int32_t *host_idx, double *host_w, void *stream);
 
 /*
+ * hsm_stencils_export_noalloc -- hsm_stencils_export with no device
+ * allocation, for callers that cannot allocate (code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc).  Its device
+ * temporaries (widths [N], offsets [N+1], indices [nnz], weights
+ * [d+2][nnz], prefix-sum workspace; about 4N + 8N + 4 nnz + 8 (d+2) nnz
+ * bytes) come from one fixed device array of
+ * HSM_EXPORT_NOALLOC_SCRATCH_BYTES that every GPU using the library holds
+ * until the process ends; a set needing more (about 1.8M stencil entries in
+ * 2D, 1.4M in 3D) is HSM_E_INVALID.  All calls on one GPU share that GPU's
+ * array: calls that overlap in time on the same GPU (several host threads
+ * or streams) race, and the caller must serialise them.  Same arguments,
+ * outputs, synchronisation and other errors as hsm_stencils_export.
+ */
+#define HSM_EXPORT_NOALLOC_SCRATCH_BYTES (64LL << 20)
+hsm_status hsm_stencils_export_noalloc(const hsm_stencils *st, uint8_t *host_class, int64_t *host_offsets,
+                                       int32_t *host_idx, double *host_w, void *stream);
+
+/*
  * hsm_stencils_condition -- the stability diagnostic of Section 2.1 (Fig. 2):
  * for every node, the 2-norm condition number kappa(M) = |M|_2 |M^-1|_2 =
  * sigma_max / sigma_min of the local system solved for its weights (the

@@ -4,6 +4,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -88,6 +89,114 @@ bool check_ptr(const void *p, const char *name) {
   return true;
 }
 
+// The fixed scratch array of hsm_stencils_export_noalloc.  Each GPU that
+// loads the library holds its own copy until the process ends.  In host code
+// `scratch` names a host-side stand-in, not device memory: kernels and copies
+// take the device address that hipGetSymbolAddress returns for the current
+// device (static_scratch), never the array's name.
+constexpr size_t kStaticScratchBytes = (size_t)HSM_EXPORT_NOALLOC_SCRATCH_BYTES;
+__device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per device.
+hsm_status static_scratch(void **out) {
+  int dev = -1;
+  HSM_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) {
+    set_error(HSM_E_HIP, "device index out of range");
+    return HSM_E_HIP;
+  }
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!p) {
+      set_error(HSM_E_HIP, "hipGetSymbolAddress(scratch) returned NULL");
+      return HSM_E_HIP;
+    }
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return HSM_OK;
+}
+
+// Device temporaries of an export: widths [N], offsets [N+1], indices
+// [nnz], weights [d+2][nnz] and the prefix-sum workspace, each 256-byte aligned.
+struct ExportScratch {
+  int32_t *width;
+  int64_t *off;
+  int32_t *idx;
+  double *w;
+  int64_t *ws;
+};
+size_t export_scratch_bytes(const hsm_stencils *st) {
+  const int64_t N = st->N, nnz = st->nnz;
+  return round256(sizeof(int32_t) * N) + round256(sizeof(int64_t) * (N + 1)) + round256(sizeof(int32_t) * nnz) +
+         round256(sizeof(double) * (st->d + 2) * nnz) + round256(sizeof(int64_t) * scan_i32_to_i64_ws(N));
+}
+ExportScratch carve_export_scratch(const hsm_stencils *st, void *base) {
+  const int64_t N = st->N, nnz = st->nnz;
+  char *p = static_cast<char *>(base);
+  ExportScratch e;
+  e.width = reinterpret_cast<int32_t *>(p); p += round256(sizeof(int32_t) * N);
+  e.off = reinterpret_cast<int64_t *>(p); p += round256(sizeof(int64_t) * (N + 1));
+  e.idx = reinterpret_cast<int32_t *>(p); p += round256(sizeof(int32_t) * nnz);
+  e.w = reinterpret_cast<double *>(p); p += round256(sizeof(double) * (st->d + 2) * nnz);
+  e.ws = reinterpret_cast<int64_t *>(p);
+  return e;
+}
+
+// Stencils in the caller's numbering, copied to host memory.  scr: device
+// scratch of export_scratch_bytes(st) bytes, or NULL to allocate it (device
+// buffers for the arrays, the scratch pool for the prefix sum).  Every byte of
+// scratch that is read is first written by this call.
+hsm_status export_impl(const hsm_stencils *st, uint8_t *host_class, int64_t *host_offsets, int32_t *host_idx,
+                       double *host_w, hipStream_t s, void *scr) {
+  if (!check_ptr(st, "stencils")) return HSM_E_INVALID;
+  const int64_t N = st->N;
+  if (host_class && N > 0) HSM_HIP(hipMemcpyAsync(host_class, st->cls.p, N, hipMemcpyDeviceToHost, s));
+  if (host_offsets || host_idx || host_w) {
+    ExportArgs a;
+    make_table(st, a.tab, 256, 0xFu, false);
+    int k = 0;
+    for (const Bucket &B : st->buckets)
+      if (B.count) a.wptr[k++] = B.w.p;
+    a.perm = st->perm.as<int32_t>(); a.iperm = st->iperm.as<int32_t>(); a.N = N; a.d = st->d; a.nnz = st->nnz;
+    DBuf width, offs, idx, w;
+    ExportScratch e{};
+    hsm_status rc;
+    if (scr) {
+      e = carve_export_scratch(st, scr);
+    } else {
+      if ((rc = width.alloc(sizeof(int32_t) * N)) || (rc = offs.alloc(sizeof(int64_t) * (N + 1))) ||
+          (rc = idx.alloc(sizeof(int32_t) * st->nnz)) || (rc = w.alloc(sizeof(double) * (st->d + 2) * st->nnz)))
+        return rc;
+      e = ExportScratch{width.as<int32_t>(), offs.as<int64_t>(), idx.as<int32_t>(), w.as<double>(), nullptr};
+    }
+    a.width = e.width; a.off = e.off; a.idx = e.idx; a.w = e.w;
+    if (N > 0) {
+      hipLaunchKernelGGL(k_export_width, dim3(nblk(N, 256)), dim3(256), 0, s, a);
+      HSM_HIP(hipGetLastError());
+    }
+    if ((rc = scan_i32_to_i64(e.width, e.off, N, s, e.ws))) return rc;
+    if (N > 0) {
+      hipLaunchKernelGGL(k_export_fill, dim3(nblk(N, 256)), dim3(256), 0, s, a);
+      HSM_HIP(hipGetLastError());
+    }
+    if (host_offsets) HSM_HIP(hipMemcpyAsync(host_offsets, e.off, sizeof(int64_t) * (N + 1), hipMemcpyDeviceToHost, s));
+    if (host_idx) HSM_HIP(hipMemcpyAsync(host_idx, e.idx, sizeof(int32_t) * st->nnz, hipMemcpyDeviceToHost, s));
+    if (host_w)
+      HSM_HIP(hipMemcpyAsync(host_w, e.w, sizeof(double) * (st->d + 2) * st->nnz, hipMemcpyDeviceToHost, s));
+    HSM_HIP(hipStreamSynchronize(s));
+    return HSM_OK;
+  }
+  HSM_HIP(hipStreamSynchronize(s));
+  return HSM_OK;
+}
+
 }  // namespace
 }  // namespace hsm
 
@@ -161,41 +270,23 @@ hsm_status hsm_stencils_get_info(const hsm_stencils *st, hsm_stencils_info *o) {
 
 hsm_status hsm_stencils_export(const hsm_stencils *st, uint8_t *host_class, int64_t *host_offsets, int32_t *host_idx,
                                double *host_w, void *stream) {
+  return export_impl(st, host_class, host_offsets, host_idx, host_w, (hipStream_t)stream, nullptr);
+}
+
+hsm_status hsm_stencils_export_noalloc(const hsm_stencils *st, uint8_t *host_class, int64_t *host_offsets,
+                                       int32_t *host_idx, double *host_w, void *stream) {
   if (!check_ptr(st, "stencils")) return HSM_E_INVALID;
-  hipStream_t s = (hipStream_t)stream;
-  const int64_t N = st->N;
-  if (host_class && N > 0) HSM_HIP(hipMemcpyAsync(host_class, st->cls.p, N, hipMemcpyDeviceToHost, s));
-  if (host_offsets || host_idx || host_w) {
-    ExportArgs a;
-    make_table(st, a.tab, 256, 0xFu, false);
-    int k = 0;
-    for (const Bucket &B : st->buckets)
-      if (B.count) a.wptr[k++] = B.w.p;
-    a.perm = st->perm.as<int32_t>(); a.iperm = st->iperm.as<int32_t>(); a.N = N; a.d = st->d; a.nnz = st->nnz;
-    DBuf width, offs, idx, w;
-    hsm_status rc;
-    if ((rc = width.alloc(sizeof(int32_t) * N)) || (rc = offs.alloc(sizeof(int64_t) * (N + 1))) ||
-        (rc = idx.alloc(sizeof(int32_t) * st->nnz)) || (rc = w.alloc(sizeof(double) * (st->d + 2) * st->nnz)))
-      return rc;
-    a.width = width.as<int32_t>(); a.off = offs.as<int64_t>(); a.idx = idx.as<int32_t>(); a.w = w.as<double>();
-    if (N > 0) {
-      hipLaunchKernelGGL(k_export_width, dim3(nblk(N, 256)), dim3(256), 0, s, a);
-      HSM_HIP(hipGetLastError());
-    }
-    if ((rc = scan_i32_to_i64(width.as<int32_t>(), offs.as<int64_t>(), N, s))) return rc;
-    if (N > 0) {
-      hipLaunchKernelGGL(k_export_fill, dim3(nblk(N, 256)), dim3(256), 0, s, a);
-      HSM_HIP(hipGetLastError());
-    }
-    if (host_offsets) HSM_HIP(hipMemcpyAsync(host_offsets, offs.p, sizeof(int64_t) * (N + 1), hipMemcpyDeviceToHost, s));
-    if (host_idx) HSM_HIP(hipMemcpyAsync(host_idx, idx.p, sizeof(int32_t) * st->nnz, hipMemcpyDeviceToHost, s));
-    if (host_w)
-      HSM_HIP(hipMemcpyAsync(host_w, w.p, sizeof(double) * (st->d + 2) * st->nnz, hipMemcpyDeviceToHost, s));
-    HSM_HIP(hipStreamSynchronize(s));
-    return HSM_OK;
+  const size_t need = export_scratch_bytes(st);
+  if (need > kStaticScratchBytes) {
+    set_error(HSM_E_INVALID, "hsm_stencils_export_noalloc needs " + std::to_string(need) +
+                                 " bytes of scratch; its fixed device array holds " +
+                                 std::to_string(kStaticScratchBytes) + " (use hsm_stencils_export)");
+    return HSM_E_INVALID;
   }
-  HSM_HIP(hipStreamSynchronize(s));
-  return HSM_OK;
+  void *scr = nullptr;
+  hsm_status rc = static_scratch(&scr);
+  if (rc != HSM_OK) return rc;
+  return export_impl(st, host_class, host_offsets, host_idx, host_w, (hipStream_t)stream, scr);
 }
 
 hsm_status hsm_permute(const hsm_stencils *st, int32_t direction, int32_t dtype, const void *src, void *dst,

@@ -61,7 +61,7 @@ SYMBOLS = ["hsm_build_stencils", "hsm_stencils_get_info", "hsm_stencils_export",
            "hsm_apply_operator", "hsm_apply_node_count", "hsm_sim_create", "hsm_step", "hsm_sim_get_stats",
            "hsm_sim_read", "hsm_sim_destroy", "hsm_stencils_destroy", "hsm_last_error", "hsm_last_error_node",
            "hsm_version", "hsm_sim_phase_times", "hsm_sim_sizes", "hsm_stream_copy", "hsm_stencils_condition",
-           "hsm_apply_operator_buckets"]
+           "hsm_apply_operator_buckets", "hsm_stencils_export_noalloc"]
 PHASES = ["pre", "krylov_iter", "post", "krylov_batch"]
 
 
@@ -79,6 +79,8 @@ def lib():
         L.hsm_stencils_get_info.argtypes = [_p, ctypes.POINTER(StencilsInfoC)]
         L.hsm_stencils_export.restype = st
         L.hsm_stencils_export.argtypes = [_p, _p, _p, _p, _p, _p]
+        L.hsm_stencils_export_noalloc.restype = st
+        L.hsm_stencils_export_noalloc.argtypes = [_p, _p, _p, _p, _p, _p]
         L.hsm_permute.restype = st
         L.hsm_permute.argtypes = [_p, ctypes.c_int32, ctypes.c_int32, _p, _p, _p]
         L.hsm_apply_operator.restype = st
@@ -163,16 +165,17 @@ class Stencils:
                     buckets=[(o.bucket_type[k], o.bucket_width[k], o.bucket_count[k]) for k in range(nb)],
                     build_ms=list(o.build_ms), bucket_solve_ms=list(o.bucket_solve_ms[:nb]))
 
-    def export(self, stream=None) -> dict:
-        """Classes, CSR stencils (caller numbering) and weights [d+2, nnz] as numpy arrays."""
+    def export(self, stream=None, noalloc: bool = False) -> dict:
+        """Classes, CSR stencils (caller numbering) and weights [d+2, nnz] as numpy arrays.
+        noalloc: through hsm_stencils_export_noalloc (device temporaries from the library's fixed array)."""
         info = self.info()
         N, nnz, d = info["n_nodes"], info["nnz"], info["d"]
         cls = np.empty(N, np.uint8)
         off = np.empty(N + 1, np.int64)
         idx = np.empty(max(nnz, 1), np.int32)
         w = np.empty((d + 2, max(nnz, 1)), np.float64)
-        _check(lib().hsm_stencils_export(self._h, cls.ctypes.data, off.ctypes.data, idx.ctypes.data,
-                                         w.ctypes.data, _stream(stream)))
+        fn = lib().hsm_stencils_export_noalloc if noalloc else lib().hsm_stencils_export
+        _check(fn(self._h, cls.ctypes.data, off.ctypes.data, idx.ctypes.data, w.ctypes.data, _stream(stream)))
         return dict(cls=cls, off=off, idx=idx[:nnz], w=w[:, :nnz], d=d)
 
     def permute(self, src: torch.Tensor, direction: int, stream=None) -> torch.Tensor:
