@@ -1,14 +1,18 @@
 #!/usr/bin/env python3
 """Benchmark of the hybrid scattered-regular hot path on one MI355X.
 
-Workload: unit square minus 20 seeded circular obstacles (radii U(0.02, 0.08)),
-lattice spacing h = 0.002, scattered band 0.05 around the obstacles, RBF-FD
-PHS r^3 + m = 2 (n = 12) on scattered nodes, MON on the 5-node cross on
-regular nodes; Ra = 1e5, Pr = 0.71, dt = 0.1 h^2 / 2 (the paper's rule).
+Default workload (--workload c3): 512 independent 2D obstacle domains of 1k-50k
+nodes each (log-uniform; 7 338 215 nodes in all), each the unit square minus
+seeded circles, its lattice spacing set by its node count, with RBF-FD PHS r^3
++ monomials of degree m in {2, 4} (per domain; n = 12 or 30) on scattered nodes
+and MON on the 5-node cross on regular nodes; Ra = 1e5, Pr = 0.71, one
+dt = 0.1 min(h)^2 / 2 for all domains (the paper's rule).  Other workloads: c2
+(20 circles, h = 0.002), c4 (3D, 8 spheres, h = 0.01), c5 (20 circles,
+h = 0.001, m = 4, Ra = 1e6).
 
 One benchmark step is one pass of the whole hot path over the node set:
 build the stencils and weights (neighbour search, classification, local
-solves), apply d/dx, d/dy and the Laplacian to the three fields, then run
+solves), apply d/dx, d/dy and the Laplacian to three fields, then run
 explicit Boussinesq time steps (predictor, BiCGSTAB pressure solve,
 projection, heat transport, wall conditions).  The same steps are timed for
 the hybrid layout and for the all-scattered layout on the same node set.
@@ -30,12 +34,18 @@ sys.path.insert(0, ROOT)
 
 METRIC = "stencil node-applies/s + weight solves/s, hybrid vs all-scattered, 1 GPU"
 HBM_PEAK_GBS = 8000.0
-KRYLOV_CHUNK = 32      # BiCGSTAB iterations per queued batch
-PMC_COMMAND = ('rocprofv3 --pmc {} --kernel-include-regex "k_bicg_pv|k_bicg_st|k_stream_copy" --output-format csv '
-               '-d <dir> -o run -- python3 bench.py --steps 1 --warmup 0 --time-steps 1 --no-cpu-baseline '
-               '--skip-all-scattered --skip-fp32-form')
+PMC_COMMAND = ('rocprofv3 --pmc {counter} --kernel-include-regex "k_bicg_pv|k_bicg_st|k_stream_copy" '
+               '--output-format csv -d <dir> -o run -- python3 bench.py --workload {workload} --steps 1 --warmup 0 '
+               '--time-steps 1 --no-cpu-baseline --skip-all-scattered --skip-fp32-form --no-autotune')
 PROFILES = os.path.join(ROOT, "profiles")
-TRAFFIC_FILE = os.path.join(PROFILES, "traffic_bicg_iteration_obstacles2d_h0.002.json")
+# per workload: the name its profile files carry
+PROFILE_TAG = {"c2": "obstacles2d_h0.002", "c3": "batch512_2d", "c4": "spheres3d_h0.01", "c5": "obstacles2d_h0.001_m4"}
+
+
+def traffic_file(workload):
+    return os.path.join(PROFILES, f"traffic_bicg_iteration_{PROFILE_TAG[workload]}.json")
+
+
 # device code the traffic record was measured on (the kernels and their shared helpers)
 KERNEL_SRCS = [os.path.join(ROOT, "paper_2303_01760_amd", "csrc", f) for f in ("sim_kernels.h", "hsm_internal.h")]
 
@@ -64,21 +74,24 @@ def kernel_bytes(sizes_buckets, N, kernel):
     raise ValueError(kernel)
 
 
-def traffic_record():
+def traffic_record(workload):
     """Counter-measured bytes per launch of the dominant kernel, if taken on the current source."""
-    if not os.path.exists(TRAFFIC_FILE):
+    path = traffic_file(workload)
+    if not os.path.exists(path):
         return None
-    rec = json.load(open(TRAFFIC_FILE))
+    rec = json.load(open(path))
     if rec.get("kernel_source_sha256") != kernel_source_sha():
         return None
     return rec
 
 
-def pmc_summary(fetch_csv, write_csv, out_path):
-    """Turn two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch)
-    into HBM bytes per BiCGSTAB iteration (one launch each of k_bicg_pv and
-    k_bicg_st), scaled by what the same counters read for the plain copy
-    kernel (whose bytes are known exactly)."""
+def pmc_summary(fetch_csv, write_csv, bench_json, workload):
+    """Turn two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch) of PMC_COMMAND into HBM
+    bytes per BiCGSTAB iteration (one launch each of k_bicg_pv and k_bicg_st), scaled by what the same
+    counters read for the plain copy kernel (whose bytes are known exactly).  One domain: the median of the
+    busy launches (launches queued past convergence return at once).  Many domains (each stops on its own):
+    the bytes of every launch over the run's matvec node rows, per 2N rows (one full iteration's worth);
+    bench_json is the JSON line of the FETCH_SIZE run, which holds those counts."""
     import csv
     import statistics
 
@@ -94,22 +107,32 @@ def pmc_summary(fetch_csv, write_csv, out_path):
                 vals.setdefault(key, []).append(float(row["Counter_Value"]) * 1024.0)
         return vals
 
+    line = json.loads(open(bench_json).read().strip().splitlines()[-1])
+    multi = line["config"]["domains"] > 1
     f, w = per_kernel(fetch_csv, "FETCH_SIZE"), per_kernel(write_csv, "WRITE_SIZE")
     copy_bytes = float(1 << 31)            # each copy launch reads and writes 2 GiB
     f_scale = copy_bytes / statistics.median(f["copy"])
     w_scale = copy_bytes / statistics.median(w["copy"])
-    # busy launches only (launches queued past convergence return at once): upper half
-    busy = lambda v: statistics.median(sorted(v)[len(v) // 2:])
-    rec = dict(kernel="BiCGSTAB iteration (k_bicg_pv<2> + k_bicg_st<2>)",
-               workload="2D unit square minus 20 circles, h=0.002, m=2, hybrid",
-               fetch_bytes_pv=busy(f["pv"]) * f_scale, write_bytes_pv=busy(w["pv"]) * w_scale,
-               fetch_bytes_st=busy(f["st"]) * f_scale, write_bytes_st=busy(w["st"]) * w_scale,
+    if multi:
+        # full-iteration equivalents: matvec node rows of the run over 2N (two matvecs per iteration)
+        its = line["roofline"]["node_rows_matvec"] / (2.0 * line["config"]["nodes"])
+        agg = lambda v: sum(v) / its
+        how = (f"sum over all {len(f['pv'])} + {len(f['st'])} launches / {its:.1f} full-iteration equivalents "
+               f"(matvec node rows / 2N)")
+    else:
+        agg = lambda v: statistics.median(sorted(v)[len(v) // 2:])   # busy launches: upper half
+        how = "median of the busy launches (upper half by bytes)"
+    rec = dict(kernel=line["roofline"]["kernel"], workload=line["config"]["workload"],
+               fetch_bytes_pv=agg(f["pv"]) * f_scale, write_bytes_pv=agg(w["pv"]) * w_scale,
+               fetch_bytes_st=agg(f["st"]) * f_scale, write_bytes_st=agg(w["st"]) * w_scale,
                copy_fetch_scale=f_scale, copy_write_scale=w_scale, launches_pv=len(f["pv"]),
-               launches_st=len(f["st"]), kernel_source_sha256=kernel_source_sha(),
-               commands=[PMC_COMMAND.format(c) for c in ("FETCH_SIZE", "WRITE_SIZE")])
+               launches_st=len(f["st"]), per_iteration=how, kernel_source_sha256=kernel_source_sha(),
+               algorithmic_bytes_per_iteration=line["roofline"]["bytes_per_launch"],
+               commands=[PMC_COMMAND.format(counter=c, workload=workload) for c in ("FETCH_SIZE", "WRITE_SIZE")])
     rec["hbm_bytes_per_iteration"] = sum(rec[k] for k in ("fetch_bytes_pv", "write_bytes_pv",
                                                           "fetch_bytes_st", "write_bytes_st"))
-    json.dump(rec, open(out_path, "w"), indent=1)
+    rec["over_algorithmic"] = rec["hbm_bytes_per_iteration"] / rec["algorithmic_bytes_per_iteration"]
+    json.dump(rec, open(traffic_file(workload), "w"), indent=1)
     print(json.dumps(rec))
 
 
@@ -118,11 +141,11 @@ def _kname(n):
     return n.split("(")[0]
 
 
-def trace_summary(trace_csv, stats_csv, warmup, steps, chunk, command, out_path):
-    """Summarise a rocprofv3 --kernel-trace run of this script: the overall
-    per-kernel statistics; per-kernel means inside the timed region of the
-    hybrid layout (delimited by the k_bbox launches that open the stencil
-    builds of the benchmark steps); and, as the stepper's own events measure it, the mean time of one
+def trace_summary(trace_csv, stats_csv, warmup, steps, command, out_path):
+    """Summarise a rocprofv3 --kernel-trace run of this script (with --skip-all-scattered
+    --skip-fp32-form): the overall per-kernel statistics; per-kernel means inside the timed region of the
+    hybrid layout (the last `steps` stencil builds that time steps follow, each opened by k_bbox); and,
+    as the stepper's own events measure it, the mean time of one
     BiCGSTAB iteration: the span between the ends of consecutive k_chunk_end
     launches (one batch of `chunk` iterations) over the batches in which every
     k_bicg_pv launch was busy (at least 3 us; launches queued past
@@ -130,37 +153,55 @@ def trace_summary(trace_csv, stats_csv, warmup, steps, chunk, command, out_path)
     import csv
     rows = list(csv.DictReader(open(trace_csv)))
     rows.sort(key=lambda r: int(r["Start_Timestamp"]))
-    # every stencil build opens with k_bbox; the builds that a time step follows (k_predict before the
-    # next build) are the benchmark steps, the others (the tile autotuner's) are skipped
+    # every stencil build opens with k_bbox; the builds that time steps follow (k_predict before the
+    # next build) are the autotuner's candidates, then the benchmark's warm-up and timed steps: the timed
+    # region is the last `steps` of them (the traced command skips the all-scattered layout and the FP32
+    # form, which would come after)
     bbox = [int(r["Start_Timestamp"]) for r in rows if "k_bbox" in r["Kernel_Name"]]
     pred = [int(r["Start_Timestamp"]) for r in rows if "k_predict" in r["Kernel_Name"]]
     nxt = bbox[1:] + [float("inf")]
     stepping = [b for b, e in zip(bbox, nxt) if any(b <= p < e for p in pred)]
-    end = lambda k: stepping[k] if len(stepping) > k else float("inf")
-    t0, t1 = stepping[warmup], end(warmup + steps)
+    t0, t1 = stepping[-steps], float("inf")
     win = [r for r in rows if t0 <= int(r["Start_Timestamp"]) < t1]
+    # iterations per batch: the most common count of k_bicg_pv launches between k_chunk_end launches
+    counts, npv = {}, 0
+    for r in win:
+        if "k_bicg_pv" in r["Kernel_Name"]:
+            npv += 1
+        elif "k_chunk_end" in r["Kernel_Name"]:
+            counts[npv] = counts.get(npv, 0) + 1
+            npv = 0
+    chunk = max(counts, key=counts.get) if counts else 32
 
     per = {}
+    grid = lambda r: r.get("Grid_Size_X") or r.get("Grid_Size") or "?"
     for r in win:
         d = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3
-        rec = per.setdefault(_kname(r["Kernel_Name"]), [0, 0.0, 0, 0.0])
+        # launches of one kernel with different grids (the full apply against a bucket-restricted one)
+        # are listed apart
+        rec = per.setdefault(f"{_kname(r['Kernel_Name'])} [grid {grid(r)}]", [0, 0.0, 0, 0.0])
         rec[0] += 1
         rec[1] += d
         if d >= 3.0:
             rec[2] += 1
             rec[3] += d
-    spans, prev_end, pv = [], None, []
+    spans, all_spans, prev_end, pv = [], [], None, []
     for r in win:
         nm = r["Kernel_Name"]
         if "k_bicg_pv" in nm:
             pv.append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3)
         elif "k_chunk_end" in nm:
             e = int(r["End_Timestamp"])
-            if prev_end is not None and len(pv) == chunk and min(pv) >= 3.0:
-                spans.append((e - prev_end) * 1e-3 / chunk)
+            if prev_end is not None and len(pv) == chunk:
+                all_spans.append((e - prev_end) * 1e-3)
+                if min(pv) >= 3.0:
+                    spans.append((e - prev_end) * 1e-3 / chunk)
             prev_end, pv = e, []
         elif "k_predict" in nm:
             prev_end, pv = None, []
+        elif "k_rhs" in nm or "k_reduce_r" in nm:
+            # a solve's first batch starts where the right-hand side and initial residual end
+            prev_end, pv = int(r["End_Timestamp"]), []
 
     lines = [f"# command: {command}", "",
              "## all launches of the run (kernel_stats.csv)", "",
@@ -168,48 +209,142 @@ def trace_summary(trace_csv, stats_csv, warmup, steps, chunk, command, out_path)
     for r in list(csv.DictReader(open(stats_csv)))[:14]:
         lines.append(f"{_kname(r['Name'])[:56]:56s} {int(r['Calls']):8d} {float(r['AverageNs']) / 1e3:9.2f} "
                      f"{float(r['Percentage']):6.2f}%")
-    lines += ["", f"## hybrid timed region (stencil builds {warmup + 1}..{warmup + steps})", "",
-              f"{'kernel':56s} {'calls':>8s} {'avg_us':>9s} {'busy':>8s} {'busy_avg_us':>12s}"]
-    for nm, (n, tot, nb, totb) in sorted(per.items(), key=lambda kv: -kv[1][1])[:10]:
-        lines.append(f"{nm[:56]:56s} {n:8d} {tot / n:9.2f} {nb:8d} {(totb / nb if nb else 0.0):12.2f}")
+    lines += ["", f"## hybrid timed region (the last {steps} benchmark steps), by kernel and grid size "
+              "(work-items)", "",
+              f"{'kernel [grid]':72s} {'calls':>8s} {'avg_us':>9s} {'busy':>8s} {'busy_avg_us':>12s}"]
+    for nm, (n, tot, nb, totb) in sorted(per.items(), key=lambda kv: -kv[1][1])[:16]:
+        lines.append(f"{nm[:72]:72s} {n:8d} {tot / n:9.2f} {nb:8d} {(totb / nb if nb else 0.0):12.2f}")
     it_us = sum(spans) / len(spans) if spans else float("nan")
     lines += ["", "## one BiCGSTAB iteration (k_bicg_pv + k_bicg_st), hybrid timed region", "",
               f"full batches of {chunk} iterations: {len(spans)}",
-              f"mean iteration time (chunk_end-to-chunk_end span / {chunk}): {it_us:.2f} us"]
+              f"mean iteration time (chunk_end-to-chunk_end span / {chunk}): {it_us:.2f} us",
+              f"all batches (the last of each solve partly idle; with many domains, each domain stops on its own): "
+              f"{len(all_spans)}, total {sum(all_spans) * 1e-3:.3f} ms, mean {sum(all_spans) / max(len(all_spans), 1):.2f} us"]
     open(out_path, "w").write("\n".join(lines) + "\n")
     print("\n".join(lines))
 
 
-def cpu_baseline(s, m, budget_s=12.0):
-    """The FP64 oracle, single-threaded, on a seeded sample of the same node set."""
+def _oracle_domain_job(job):
+    """One domain through the FP64 oracle, as one benchmark step does it on the GPU: stencils and weights
+    (brute-force neighbour search and classification, then the local solves), d/dx, d/dy and the Laplacian
+    applied to three fields, and `nsteps` explicit time steps (BiCGSTAB pressure solves).  The local solves
+    are also timed on their own (same stencils, no search).  Counts node-applies the way the GPU stepper
+    does."""
     import numpy as np
     from oracle import oracle as O
-    rng = np.random.default_rng(2303017602)
-    q = np.sort(rng.choice(s.n, 400, replace=False))
+    x, kind, normal, tbc, h, m, Ra, dt, tol, nsteps = job
+    d, n = x.shape
     t0 = time.perf_counter()
-    st = O.build(s.x, s.kind, s.normal, s.h, m, queries=q)
+    csr = O.to_csr(O.build(x, kind, normal, h, m))
     t_build = time.perf_counter() - t0
-    width = st["width"].astype(np.int64)
-    off = np.zeros(len(q) + 1, np.int64)
-    np.cumsum(width, out=off[1:])
-    mask = np.arange(st["idx"].shape[1])[None, :] < width[:, None]
-    csr = dict(off=off, idx=st["idx"][mask].astype(np.int32))
-    ws = [st["w"][:, r, :][mask] for r in range(3)]
-    fields = [np.sin(3 * s.x[0]), np.cos(2 * s.x[1]), s.x[0] * s.x[1]]
-    reps, applies, t_apply = 0, 0, 0.0
-    while t_apply < budget_s and reps < 10000000:
-        t1 = time.perf_counter()
-        for u in fields:
-            for w in ws:
-                O.apply(csr, w, u)
-        t_apply += time.perf_counter() - t1
-        reps += 1
-        applies += 9 * len(q)
-    return dict(value=applies / t_apply, unit="node-applies/s", cores=1, kind="oracle",
-                sample=f"{len(q)} seeded nodes of the same node set: stencils and weights built by the oracle "
-                       f"(brute-force neighbour search over all {s.n} nodes), then d/dx, d/dy, Laplacian applied "
-                       f"to 3 fields {reps} times ({t_apply:.1f} s)",
-                solves_per_s=len(q) / t_build, build_s=t_build)
+    t0 = time.perf_counter()
+    O.weights_csr(x, kind, csr, m)
+    t_solve = time.perf_counter() - t0
+    fields = [np.sin(3 * x[0]), np.cos(2 * x[1]), np.where(kind == 1, tbc, 0.0)]
+    t0 = time.perf_counter()
+    for u in fields:
+        for k in range(3):
+            O.apply(csr, csr["w"][k], u)
+    t_apply = time.perf_counter() - t0
+    sim = O.Sim(csr, kind)
+    v = np.zeros((d, n))
+    T = np.where(kind == 1, tbc, 0.0)
+    p = np.zeros(n + 1)
+    t0 = time.perf_counter()
+    its = sim.step(v, T, p, nsteps, Ra=Ra, Pr=0.71, dt=dt, T_ref=0.5, tol=tol, maxiter=200000)
+    t_step = time.perf_counter() - t0
+    sim.close()
+    n_int, n_neu = int((kind == 0).sum()), int((kind == 2).sum())
+    step_applies = nsteps * (n_int * (d * (d + 1) + d + 2 * d + 1) + n + n_neu) + 2 * n * int(its.sum())
+    return dict(n=n, t_build=t_build, t_solve=t_solve, t_apply=t_apply, t_step=t_step, iters=int(its.sum()),
+                applies=9 * n + step_applies, step_applies=step_applies)
+
+
+def _pinned_worker_init(cpu):
+    try:
+        os.sched_setaffinity(0, {cpu})
+    except (AttributeError, OSError):
+        pass
+
+
+def _host_cpu():
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    return model, avail
+
+
+def cpu_baseline(domains, desc, nsteps, tol, budget_s=12.0, max_cores=16):
+    """The FP64 oracle as it stands on the host cores, on a bounded sample of the workload: each job is one
+    whole domain through the oracle (see _oracle_domain_job).  Single-threaded, pinned to one core (the
+    paper's protocol), over the sample in order until budget_s is spent; then the sample that finished,
+    repeated so every worker has about two jobs, on all available cores (one oracle process per core).
+    value = node-applies/s of the all-core run, counted as on the GPU."""
+    import multiprocessing as mp
+    model, avail = _host_cpu()
+    cores = max(1, min(avail, max_cores))
+    ctx = mp.get_context("fork")
+    done, t_single = [], 0.0
+    with ctx.Pool(1, initializer=_pinned_worker_init, initargs=(sorted(os.sched_getaffinity(0))[0],)) as pool:
+        for job in domains:
+            t0 = time.perf_counter()
+            done.append(pool.apply(_oracle_domain_job, (job,)))
+            t_single += time.perf_counter() - t0
+            if t_single >= budget_s:
+                break
+    k = len(done)
+    reps = max(1, -(-2 * cores // k))
+    jobs = [domains[i] for i in range(k)] * reps
+    t0 = time.perf_counter()
+    with ctx.Pool(cores) as pool:
+        many = pool.map(_oracle_domain_job, jobs, chunksize=1)
+    t_all = time.perf_counter() - t0
+    tot = lambda rs, key: sum(r[key] for r in rs)
+    single = dict(value=tot(done, "applies") / t_single, cores=1, seconds=t_single,
+                  solves_per_s=tot(done, "n") / tot(done, "t_solve"),
+                  solves_per_s_with_search=tot(done, "n") / tot(done, "t_build"),
+                  step_node_applies_per_s=tot(done, "step_applies") / tot(done, "t_step"),
+                  apply_node_applies_per_s=9 * tot(done, "n") / tot(done, "t_apply"),
+                  krylov_iters_per_time_step=tot(done, "iters") / (k * nsteps))
+    return dict(value=tot(many, "applies") / t_all, unit="node-applies/s", cores=cores, kind="oracle",
+                sample=(f"{desc}: {k} domain(s) ({tot(done, 'n')} nodes) each through the oracle's whole benchmark "
+                        f"step (brute-force stencil build, 3 operators on 3 fields, {nsteps} time steps at rel. "
+                        f"residual {tol}); single thread pinned to one core for {t_single:.1f} s, then the same "
+                        f"domains x{reps} on {cores} cores ({t_all:.1f} s)"),
+                host_cpu=model, host_cores_available=avail, seconds=t_all, single_thread=single)
+
+
+def cpu_sample(s, args, multi, m, Ra):
+    """Seeded sample of the workload for the CPU baseline.  Many domains: domains of at most 12 000 nodes
+    (the oracle's neighbour search is O(N^2) per domain) in a seeded order.  One domain: the same generator
+    at a coarser spacing (about 5 000 - 15 000 nodes), since the oracle's O(N^2) build of the full set
+    would take hours."""
+    import numpy as np
+    from paper_2303_01760_amd import nodegen as ng
+    if multi:
+        rng = np.random.default_rng(2303017603)
+        order = [int(k) for k in rng.permutation(s.n_domains) if s.off[k + 1] - s.off[k] <= 12000]
+        jobs = []
+        for k in order:
+            a, b = s.off[k], s.off[k + 1]
+            h = float(s.h[k])
+            jobs.append((s.x[:, a:b].copy(), s.kind[a:b].copy(), s.normal[:, a:b].copy(), s.tbc[a:b].copy(), h,
+                         int(s.m[k]), Ra, 0.1 * float(np.min(s.h)) ** 2 / 2, args.tol, args.time_steps))
+        return jobs, "seeded domains of the batch with at most 12 000 nodes"
+    coarse = {"c2": lambda: ng.obstacles2d(h=0.01), "c5": lambda: ng.obstacles2d(h=0.008),
+              "c4": lambda: ng.obstacles3d(h=0.04)}[args.workload]()
+    dt = 0.1 * coarse.h ** 2 / 2
+    job = (coarse.x, coarse.kind, coarse.normal, coarse.tbc, coarse.h, m, Ra, dt, args.tol, args.time_steps)
+    return [job] * 64, f"the same geometry at h={coarse.h} ({coarse.n} nodes)"
 
 
 WORKLOADS = {
@@ -248,25 +383,26 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--time-steps", type=int, default=5, help="explicit time steps per benchmark step")
-    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="c2")
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="c3")
     ap.add_argument("--m", type=int, default=0, help="scattered polynomial degree (0: the workload's)")
     ap.add_argument("--tol", type=float, default=1e-10, help="relative residual of each pressure solve")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-all-scattered", action="store_true")
     ap.add_argument("--skip-fp32-form", action="store_true")
-    ap.add_argument("--no-autotune", action="store_true", help="keep the default tile of the internal node order")
-    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
-                    help="summarise two rocprofv3 --pmc runs into the traffic record and exit")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the library's default layout and launch parameters")
+    ap.add_argument("--pmc-summary", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "BENCH_JSON"),
+                    help="summarise two rocprofv3 --pmc runs of PMC_COMMAND (for --workload) into the traffic "
+                         "record and exit")
     ap.add_argument("--trace-summary", nargs=3, metavar=("TRACE_CSV", "STATS_CSV", "OUT"),
                     help="summarise a rocprofv3 --kernel-trace run of this script (same --steps/--warmup) and exit")
     ap.add_argument("--trace-command", default="rocprofv3 --kernel-trace --stats --output-format csv -d <dir> -o run "
                                                 "-- python3 bench.py")
     args = ap.parse_args()
     if args.pmc_summary:
-        pmc_summary(args.pmc_summary[0], args.pmc_summary[1], TRAFFIC_FILE)
+        pmc_summary(args.pmc_summary[0], args.pmc_summary[1], args.pmc_summary[2], args.workload)
         return 0
     if args.trace_summary:
-        trace_summary(args.trace_summary[0], args.trace_summary[1], args.warmup, args.steps, KRYLOV_CHUNK,
+        trace_summary(args.trace_summary[0], args.trace_summary[1], args.warmup, args.steps,
                       args.trace_command, args.trace_summary[2])
         return 0
     if args.gpus != 1:
@@ -316,21 +452,26 @@ def main():
     del src, dst
     log(f"stream copy: {copy_gbs:.0f} GB/s")
 
-    # the tile of the internal node order, picked per layout by the autotuner (outside the timed region)
-    tiles, tuning = {}, {}
-    if not args.no_autotune:
-        from paper_2303_01760_amd import autotune
-        for mode in ([hsm.MODE_HYBRID] + ([] if args.skip_all_scattered else [hsm.MODE_ALL_SCATTERED])):
-            best, tms = autotune.tune_tile(x, kind, nrm, hdom, m, mode=mode, domain_offsets=dom_off)
-            tiles[mode] = best
-            tuning["hybrid" if mode == hsm.MODE_HYBRID else "all_scattered"] = dict(
-                chosen_tile_log2=best, fused_apply_ms={str(k): v for k, v in tms.items()})
-            log(f"autotune (mode {mode}): tile 2^{best} cells per axis; apply ms {tms}")
+    # layout and launch parameters, picked per layout by the autotuner (outside the timed region)
+    from paper_2303_01760_amd import autotune
+    knobs, tuning = {}, {}
+    for mode in ([hsm.MODE_HYBRID] + ([] if args.skip_all_scattered else [hsm.MODE_ALL_SCATTERED])):
+        if args.no_autotune:
+            knobs[mode] = dict(autotune.DEFAULTS)
+            continue
+        t0 = time.perf_counter()
+        res = autotune.tune(x, kind, nrm, hdom, m, mode=mode, domain_offsets=dom_off, use_cache=False, log=log,
+                            sim_kw=dict(Ra=Ra, Pr=0.71, dt=dt, T_ref=0.5, tol=args.tol, v0=v0, T0=T0d))
+        knobs[mode] = res["choice"]
+        tuning["hybrid" if mode == hsm.MODE_HYBRID else "all_scattered"] = dict(
+            choice=res["choice"], timings=res["timings"], units=res["units"], tuning_s=time.perf_counter() - t0)
+        log(f"autotune (mode {mode}): {res['choice']} ({time.perf_counter() - t0:.1f} s)")
 
     def one_step(mode, rec, field_dtype=hsm.F64, keep=False):
         t0 = time.perf_counter()
+        kb = knobs[mode]
         st = hsm.build_stencils(x, kind, nrm, hdom, m, mode=mode, domain_offsets=dom_off,
-                                tile_log2=tiles.get(mode, 0))
+                                tile_log2=kb["tile_log2"], solve_groups=kb["solve_groups"])
         rec["build_s"] += time.perf_counter() - t0
         info = st.info()
         rec["build_dev_ms"] += info["build_ms"][0] + info["build_ms"][1] + info["build_ms"][2]
@@ -343,7 +484,9 @@ def main():
         rec["info"] = info
         # profile=1: start/stop events around every graph launch on the stepper's stream
         sim = hsm.Sim(st, v0, T0d, Ra=Ra, Pr=0.71, dt=dt, T_ref=0.5, krylov_tol=args.tol, krylov_maxiter=200000,
-                      krylov_chunk=KRYLOV_CHUNK, profile=1, field_dtype=field_dtype)
+                      krylov_chunk=kb["krylov_chunk"], block_nodes=kb["block_nodes"],
+                      gather_chunk=kb["gather_chunk"], xcd_order=kb["xcd_order"], profile=1,
+                      field_dtype=field_dtype)
         try:
             sim.step(args.time_steps)
         except hsm.HsmError:
@@ -527,7 +670,7 @@ def main():
             b_ms, n_b = pt["krylov_batch"]
             work = hy["node_mv"] * bytes_it / (2.0 * s.n)
             achieved = work / (b_ms * n_b * 1e-3) / 1e9
-        tr = traffic_record() if args.workload == "c2" else None
+        tr = traffic_record(args.workload)
         roofline = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS,
                         traffic=(tr["hbm_bytes_per_iteration"] if tr else None),
                         kernel=(f"BiCGSTAB iterations of {s.n_domains} domains, each stopping on its own "
@@ -535,7 +678,9 @@ def main():
                                 if multi else f"BiCGSTAB iteration (k_bicg_pv<{D}> + k_bicg_st<{D}>)"),
                         bytes_per_launch=bytes_it,
                         bytes_pv=kernel_bytes(buckets, s.n, "bicg_pv"), bytes_st=kernel_bytes(buckets, s.n, "bicg_st"),
-                        mean_launch_ms=it_ms, iterations_timed=pt["krylov_iter"][1], copy_kernel_gbs=copy_gbs)
+                        mean_launch_ms=it_ms, iterations_timed=pt["krylov_iter"][1], copy_kernel_gbs=copy_gbs,
+                        node_rows_matvec=hy["node_mv"],
+                        traffic_over_algorithmic=(tr["over_algorithmic"] if tr and "over_algorithmic" in tr else None))
     else:
         # no time stepping: the dominant kernel is the fused 3-operator apply
         ap = hy["apply"]["f64"]
@@ -602,11 +747,9 @@ def main():
     if fp32:
         out["fp32_form"] = fp32
     if not args.no_cpu_baseline:
-        if multi:
-            log("cpu baseline: measured on the single-domain workloads only")
-        else:
-            log("cpu baseline (oracle) ...")
-            out["cpu_baseline"] = cpu_baseline(s, m)
+        log("cpu baseline (oracle) ...")
+        jobs, desc = cpu_sample(s, args, multi, m, Ra)
+        out["cpu_baseline"] = cpu_baseline(jobs, desc, args.time_steps, args.tol)
     print(json.dumps(out), flush=True)
     return 0
 

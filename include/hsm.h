@@ -82,6 +82,9 @@ typedef struct {
   const int32_t *host_n;               /* [n_domains] RBF-FD stencil size, or NULL for 2 C(m+d, m) */
   int32_t tile_log2;                   /* internal node order: tiles of 2^tile_log2 search cells per axis
                                           (1..5); 0 for the default (8x8 in 2D, 4x4x4 in 3D) */
+  int32_t solve_groups;                /* RBF-FD local systems per wave64: 0 for the most that fit (3 when
+                                          the system size is <= 21, 2 when <= 32, else 1); 1, 2 or 3 (capped
+                                          at what fits).  The weights do not depend on it. */
 } hsm_nodeset;
 
 /* Summary of a built stencil set. */
@@ -229,6 +232,12 @@ typedef struct {
   int32_t launch_mode;     /* 0: replay captured HIP graphs, 1: launch kernels directly (same kernels) */
   int32_t profile;         /* 1: bracket each phase (pre, Krylov batch, post) with HIP events; see hsm_sim_phase_times */
   int32_t reduce_mode;     /* Krylov dot products: 0 auto, 1 each block reduces all partials, 2 one-block kernel */
+  int32_t block_nodes;     /* nodes (threads) per block of the node kernels: 0 (= 256), 64, 128 or 256 */
+  int32_t gather_chunk;    /* stencil entries per gather round of the BiCGSTAB p/v kernel: 0 (= 8), 4, 6, 8, 12 */
+  int32_t xcd_order;       /* 1: where the dot products use the reduction kernels (several domains, or more
+                              than 1024 blocks), each XCD runs one contiguous run of the Krylov kernels' blocks
+                              (its L2 then holds the neighbours they gather); 0: consecutive blocks on
+                              consecutive XCDs */
 } hsm_sim_params;
 
 typedef struct {

@@ -426,6 +426,38 @@ int ora_build(int d, int64_t N, const double *x, const uint8_t *kind, const doub
   return rc;
 }
 
+/* Weights of given stencils (CSR: off[ns+1], idx, centre first) at the
+ * nodes listed in `nodes`: the same local solves as ora_build (MON on the
+ * axis cross where cls = 0, RBF-FD of degree m[q] otherwise, with the wall
+ * fallback to degree m-1), without the neighbour search.  w: [d+1][nnz].
+ * Used to time the local solves on their own. */
+int ora_weights_csr(int d, int64_t N, const double *x, const uint8_t *kind, int64_t ns, const int64_t *nodes,
+                    const int64_t *off, const int32_t *idx, const uint8_t *cls, const int32_t *m, double *w,
+                    int64_t *bad_node) {
+  const int R = d + 1;
+  const int64_t nnz = off[ns];
+  int maxw = 1;
+  for (int64_t q = 0; q < ns; ++q)
+    if (off[q + 1] - off[q] > maxw) maxw = (int)(off[q + 1] - off[q]);
+  double *xs = malloc(sizeof(double) * maxw * d);
+  double *wl = malloc(sizeof(double) * maxw * R);
+  if (!xs || !wl) { free(xs); free(wl); return ORA_E_INVALID; }
+  if (bad_node) *bad_node = -1;
+  int rc = ORA_OK;
+  for (int64_t q = 0; q < ns && rc == ORA_OK; ++q) {
+    const int wdt = (int)(off[q + 1] - off[q]);
+    for (int t = 0; t < wdt; ++t)
+      for (int a = 0; a < d; ++a) xs[t * d + a] = x[a * N + idx[off[q] + t]];
+    rc = (cls[q] == 0) ? ora_mon(d, xs, wl) : ora_rbffd(d, m[q], wdt, xs, wl);
+    if (rc == ORA_E_SINGULAR && cls[q] != 0 && kind[nodes[q]] != 0 && m[q] >= 2) rc = ora_rbffd(d, m[q] - 1, wdt, xs, wl);
+    if (rc) { if (bad_node) *bad_node = nodes[q]; break; }
+    for (int r = 0; r < R; ++r)
+      for (int t = 0; t < wdt; ++t) w[r * nnz + off[q] + t] = wl[r * wdt + t];
+  }
+  free(xs); free(wl);
+  return rc;
+}
+
 /* ------------------------------------------------------------ apply ----- */
 /* Eq. (1): out_i = sum_j w_ij u_{idx_ij}, accumulated in stencil order.
  * CSR stencils: off[N+1], idx[nnz], w[nnz]. */

@@ -58,6 +58,7 @@ def lib():
         L.ora_mon.argtypes = [ctypes.c_int, _p, _p]
         L.ora_build.argtypes = [ctypes.c_int, _i64, _p, _p, _p, _p, _i32, _p, _p, _p, ctypes.c_int,
                                 _i64, _p, ctypes.c_int, _p, _p, _p, _p, _p, _p]
+        L.ora_weights_csr.argtypes = [ctypes.c_int, _i64, _p, _p, _i64, _p, _p, _p, _p, _p, _p, _p]
         L.ora_apply.restype = None
         L.ora_apply.argtypes = [_i64, _p, _p, _p, _p, _p]
         L.ora_pressure_dense.argtypes = [_i64, _p, _p, _p, _p, _p, _i32, _p, _p]
@@ -272,6 +273,27 @@ def to_csr(st):
     w = np.stack([st["w"][:, r, :][mask] for r in range(d + 1)])
     wn = st["wn"][mask]
     return dict(off=off, idx=idx, w=w, wn=wn, d=d, cls=st["cls"], width=st["width"])
+
+
+def weights_csr(x, kind, csr, m, nodes=None):
+    """The local solves alone for the stencils of a CSR set (no neighbour
+    search): weights [d+1, nnz] of the nodes `nodes` (default 0..n-1), MON
+    where csr["cls"] is 0, RBF-FD of degree m (scalar or per stencil)
+    elsewhere.  Same arithmetic as build()."""
+    x = _c(x, np.float64)
+    d, N = x.shape
+    off = _c(csr["off"], np.int64)
+    ns = len(off) - 1
+    nodes = _c(np.arange(ns) if nodes is None else nodes, np.int64)
+    mm = _c(np.broadcast_to(np.asarray(m, np.int32), (ns,)), np.int32)
+    w = np.empty((d + 1, int(off[-1])), np.float64)
+    bad = np.array([-1], np.int64)
+    rc = lib().ora_weights_csr(d, N, _ptr(x), _ptr(_c(kind, np.uint8)), ns, _ptr(nodes), _ptr(off),
+                               _ptr(_c(csr["idx"], np.int32)), _ptr(_c(csr["cls"], np.uint8)), _ptr(mm), _ptr(w),
+                               _ptr(bad))
+    if rc:
+        raise OracleError(rc, int(bad[0]))
+    return w
 
 
 def apply(csr, wrow, u):

@@ -218,6 +218,7 @@ hsm_status hsm_build_stencils(const hsm_nodeset *ns, int32_t mode, void *stream,
   }
   if (ns->n_domains < 1 || ns->n_domains > (1 << 20)) { set_error(HSM_E_INVALID, "n_domains out of range"); return HSM_E_INVALID; }
   if (ns->tile_log2 < 0 || ns->tile_log2 > 5) { set_error(HSM_E_INVALID, "tile_log2 must be 0 (default) or 1..5"); return HSM_E_INVALID; }
+  if (ns->solve_groups < 0 || ns->solve_groups > 3) { set_error(HSM_E_INVALID, "solve_groups must be 0 (auto), 1, 2 or 3"); return HSM_E_INVALID; }
   if (!check_ptr(ns->host_domain_offsets, "host_domain_offsets") || !check_ptr(ns->host_h_regular, "host_h_regular") ||
       !check_ptr(ns->host_m, "host_m"))
     return HSM_E_INVALID;

@@ -616,6 +616,7 @@ hsm_status build_stencils_impl(const hsm_nodeset *ns, int32_t mode, hipStream_t 
   auto st = new hsm_stencils();
   std::unique_ptr<hsm_stencils> guard(st);
   st->d = d; st->mode = mode; st->n_domains = nd; st->N = N;
+  st->solve_groups = ns->solve_groups;
   st->dom_off.assign(ns->host_domain_offsets, ns->host_domain_offsets + nd + 1);
   HSM_HIP(hipGetDevice(&st->device));
 

@@ -186,6 +186,7 @@ struct hsm_stencils {
   hsm::DBuf normal;      // double [d][N] internal order
   hsm::DBuf cls;         // uint8 [N] caller order
   int32_t device = 0;
+  int32_t solve_groups = 0;      // RBF-FD systems per wave (0: the most that fit)
   double build_ms[4] = {0, 0, 0, 0};
   mutable bool w32_ready = false;
   mutable hsm::DBuf dtab[2];     // device copies of the apply bucket table (FP64, FP32 weights)

@@ -37,6 +37,9 @@ struct hsm_sim {
   int d = 0;
   int64_t N = 0;
   int chunk = 32;
+  int bs = kBS;                // threads (and at most nodes) per block of the node kernels
+  int kp = 8;                  // entries per gather chunk of the p/v kernel
+  bool xcd = false;            // XCD-contiguous block order in the Krylov kernels (reduction-kernel path)
   DBuf v, vs, T[2], vec[2], pairs[4], partR, partA, partB, sc, wP[kMaxBuckets];
   double *x = nullptr, *rh = nullptr;
   double2 *ST = nullptr, *PV[2] = {nullptr, nullptr}, *RV = nullptr;
@@ -102,6 +105,7 @@ SimArgs make_args(hsm_sim *m, int par, int kpar) {
   a.maxiter = m->prm.krylov_maxiter;
   a.chunk = m->chunk;
   a.sepred = m->sepred ? 1 : 0;
+  a.xcd_order = m->xcd ? 1 : 0;
   a.v = m->v.p;
   a.vs = m->vs.p;
   a.T = m->T[par].p;
@@ -121,7 +125,7 @@ SimArgs make_args(hsm_sim *m, int par, int kpar) {
 template <int D>
 hsm_status enqueue_pre(hsm_sim *m, int par, hipStream_t s) {
   SimArgs a = make_args(m, par, 0);
-  const dim3 g((unsigned)m->nblk), b(kBS);
+  const dim3 g((unsigned)m->nblk), b((unsigned)m->bs);
   if (m->f32) {
     hipLaunchKernelGGL((k_predict<D, float>), g, b, 0, s, a);
     hipLaunchKernelGGL((k_rhs<D, float>), g, b, 0, s, a);
@@ -138,10 +142,15 @@ hsm_status enqueue_pre(hsm_sim *m, int par, hipStream_t s) {
 // iteration number, so a batch may be split across launch paths.
 template <int D>
 hsm_status enqueue_krylov(hsm_sim *m, int slot, hipStream_t s, int it0, int it1, bool flags) {
-  const dim3 g((unsigned)m->kry_grid), b(kBS);
+  const dim3 g((unsigned)m->kry_grid), b((unsigned)m->bs);
   for (int it = it0; it < it1; ++it) {
     SimArgs a = make_args(m, 0, it & 1);
-    hipLaunchKernelGGL(k_bicg_pv<D>, g, b, 0, s, a, it);
+    switch (m->kp) {
+      case 4: hipLaunchKernelGGL((k_bicg_pv<D, 4>), g, b, 0, s, a, it); break;
+      case 6: hipLaunchKernelGGL((k_bicg_pv<D, 6>), g, b, 0, s, a, it); break;
+      case 12: hipLaunchKernelGGL((k_bicg_pv<D, 12>), g, b, 0, s, a, it); break;
+      default: hipLaunchKernelGGL((k_bicg_pv<D, 8>), g, b, 0, s, a, it); break;
+    }
     if (m->sepred) hipLaunchKernelGGL(k_reduce_a, dim3((unsigned)red_grid(m->K)), dim3(kRedThreads), 0, s, a, it);
     hipLaunchKernelGGL(k_bicg_st<D>, g, b, 0, s, a, it);
     if (m->sepred) hipLaunchKernelGGL(k_reduce_b, dim3((unsigned)red_grid(m->K)), dim3(kRedThreads), 0, s, a, it);
@@ -160,7 +169,7 @@ hsm_status enqueue_krylov(hsm_sim *m, int slot, hipStream_t s, int it0, int it1,
 template <int D>
 hsm_status enqueue_post(hsm_sim *m, int par, hipStream_t s) {
   SimArgs a = make_args(m, par, 0);
-  const dim3 g((unsigned)m->nblk), b(kBS);
+  const dim3 g((unsigned)m->nblk), b((unsigned)m->bs);
   if (m->f32) {
     hipLaunchKernelGGL((k_correct_heat<D, float>), g, b, 0, s, a);
     hipLaunchKernelGGL((k_neumann<D, float>), g, b, 0, s, a);
@@ -340,6 +349,21 @@ hsm_status hsm_sim_create(const hsm_stencils *st, const hsm_sim_params *prm, con
   auto m = std::make_unique<hsm_sim>();
   m->st = st; m->prm = *prm; m->d = st->d; m->N = st->N;
   m->chunk = prm->krylov_chunk ? prm->krylov_chunk : 32;
+  if (prm->block_nodes != 0 && prm->block_nodes != 64 && prm->block_nodes != 128 && prm->block_nodes != 256) {
+    set_error(HSM_E_INVALID, "block_nodes must be 0 (256), 64, 128 or 256");
+    return HSM_E_INVALID;
+  }
+  if (prm->gather_chunk != 0 && prm->gather_chunk != 4 && prm->gather_chunk != 6 && prm->gather_chunk != 8 &&
+      prm->gather_chunk != 12) {
+    set_error(HSM_E_INVALID, "gather_chunk must be 0 (8), 4, 6, 8 or 12");
+    return HSM_E_INVALID;
+  }
+  if (prm->xcd_order != 0 && prm->xcd_order != 1) {
+    set_error(HSM_E_INVALID, "xcd_order must be 0 or 1");
+    return HSM_E_INVALID;
+  }
+  m->bs = prm->block_nodes ? prm->block_nodes : kBS;
+  m->kp = prm->gather_chunk ? prm->gather_chunk : 8;
   if (m->chunk & 1) m->chunk += 1;   // even: ping-pong buffers line up across batches
   const int64_t N = st->N, d = st->d;
   hipStream_t us = (hipStream_t)stream;
@@ -377,7 +401,7 @@ hsm_status hsm_sim_create(const hsm_stencils *st, const hsm_sim_params *prm, con
       ++k;
     }
   }
-  // blocks: up to kBS consecutive nodes of one bucket and one domain
+  // blocks: up to m->bs consecutive nodes of one bucket and one domain
   std::vector<int32_t> dom_int;
   if (m->K > 1) {
     std::vector<int32_t> hperm(N);
@@ -394,7 +418,7 @@ hsm_status hsm_sim_create(const hsm_stencils *st, const hsm_sim_params *prm, con
     for (int64_t j = 0; j < B.count;) {
       const int32_t dom = m->K > 1 ? dom_int[B.start + j] : 0;
       int64_t e = j + 1;
-      while (e < B.count && e - j < kBS && (m->K == 1 || dom_int[B.start + e] == dom)) ++e;
+      while (e < B.count && e - j < m->bs && (m->K == 1 || dom_int[B.start + e] == dom)) ++e;
       BlockDesc bd;
       std::memset(&bd, 0, sizeof(bd));
       bd.idx = B.idx.p;
@@ -442,7 +466,9 @@ hsm_status hsm_sim_create(const hsm_stencils *st, const hsm_sim_params *prm, con
   // grid of the blocks the device holds at once, walking the list, measured
   // 9 % slower on 512 domains: the hardware refills a full grid faster than
   // a block walks its share)
-  m->kry_grid = m->nblk;
+  // the XCD-contiguous order needs at least 8 ceil(nblk / 8) workgroups (one grid slot per list position)
+  m->xcd = m->sepred && prm->xcd_order != 0;
+  m->kry_grid = m->xcd ? (m->nblk + kXcds - 1) / kXcds * kXcds : m->nblk;
   if ((rc = m->active.alloc(sizeof(int32_t) * (m->nblk + 1)))) return rc;
   if ((rc = m->dom.alloc(sizeof(DomState) * m->K)) || (rc = m->dom_nodes.alloc(sizeof(int64_t) * m->K)) ||
       (rc = m->bscale.alloc(sizeof(double) * m->K)))

@@ -83,6 +83,7 @@ struct SimArgs {
   int32_t *active;                 // [nblk] blocks of unfinished domains (per-domain path), rebuilt as domains finish
   double dt, Ra, Pr, T_ref, tol;
   int32_t maxiter, chunk;
+  int32_t xcd_order;   // 1: the Krylov kernels hand each XCD one contiguous run of the block list (list_pos)
   int32_t sepred;      // 1: grid totals (border rows included) come from the reduction kernels;
                        // 0: one domain, each block reduces the partials and handles the border itself
   // fields, in the field storage type (double, or float in the FP32 form)
@@ -125,6 +126,21 @@ template <int D, class F>
 __device__ __forceinline__ void with_width(int w, F &&f) {
   if constexpr (D == 2) with_width2(w, f);
   else with_width3(w, f);
+}
+
+// Position in the list of blocks to run that workgroup w takes.  Workgroups
+// are dispatched to the XCDs round-robin (w on XCD w % kXcds), and each XCD
+// has its own L2: with xcd_order, XCD x takes the contiguous run
+// [x C, (x + 1) C) of the list, C = ceil(nact / kXcds), so the neighbours a
+// block gathers are mostly in blocks its own L2 has just read; otherwise
+// position w (consecutive blocks on different XCDs, all of them sweeping one
+// window of the node arrays).  Positions >= nact have nothing to do; the
+// grid holds at least kXcds C workgroups.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int64_t list_pos(int64_t w, int64_t nact, int xcd_order) {
+  if (!xcd_order) return w;
+  const int64_t C = (nact + kXcds - 1) / kXcds, q = w / kXcds;
+  return q < C ? (w % kXcds) * C + q : nact;
 }
 
 // Field operators of the FP32 form act on differences from the centre value,
@@ -172,7 +188,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 template <int NQ>
 __device__ __forceinline__ void block_partials(double (&v)[NQ], double *part, int64_t row = -1, bool again = false) {
   __shared__ double red[kBS / 64][NQ];
-  const int wv = threadIdx.x >> 6;
+  const int wv = threadIdx.x >> 6, nw = (int)(blockDim.x >> 6);   // blocks of 64 to kBS threads
 #pragma unroll
   for (int q = 0; q < NQ; ++q) v[q] = wave_sum(v[q]);
   if ((threadIdx.x & 63) == 0)
@@ -182,8 +198,7 @@ __device__ __forceinline__ void block_partials(double (&v)[NQ], double *part, in
   if (threadIdx.x < NQ) {
     const int q = threadIdx.x;
     double s = red[0][q];
-#pragma unroll
-    for (int k = 1; k < kBS / 64; ++k) s += red[k][q];
+    for (int k = 1; k < nw; ++k) s += red[k][q];
     part[(row < 0 ? (int64_t)blockIdx.x : row) * NQ + q] = s;
   }
   if (again) __syncthreads();                  // the shared array is reused by this block's next row
@@ -195,12 +210,13 @@ __device__ __forceinline__ void block_partials(double (&v)[NQ], double *part, in
 template <int NQ>
 __device__ __forceinline__ void reduce_prev(const double *__restrict__ part, int64_t nblk, double (&tot)[NQ]) {
   __shared__ double red[kBS / 64][NQ];
+  const int64_t bs = blockDim.x;               // 64 to kBS threads
   // all loads of the first four passes issued before any sum (same order as a plain loop)
   constexpr int U = 4;
   double vals[U][NQ];
 #pragma unroll
   for (int u = 0; u < U; ++u) {
-    const int64_t b = threadIdx.x + (int64_t)u * kBS;
+    const int64_t b = threadIdx.x + (int64_t)u * bs;
 #pragma unroll
     for (int q = 0; q < NQ; ++q) vals[u][q] = (b < nblk) ? part[b * NQ + q] : 0.0;
   }
@@ -211,10 +227,10 @@ __device__ __forceinline__ void reduce_prev(const double *__restrict__ part, int
 #pragma unroll
     for (int u = 1; u < U; ++u) acc[q] += vals[u][q];
   }
-  for (int64_t b = threadIdx.x + (int64_t)U * kBS; b < nblk; b += kBS)
+  for (int64_t b = threadIdx.x + (int64_t)U * bs; b < nblk; b += bs)
 #pragma unroll
     for (int q = 0; q < NQ; ++q) acc[q] += part[b * NQ + q];
-  const int wv = threadIdx.x >> 6;
+  const int wv = threadIdx.x >> 6, nw = (int)(bs >> 6);
 #pragma unroll
   for (int q = 0; q < NQ; ++q) acc[q] = wave_sum(acc[q]);
   if ((threadIdx.x & 63) == 0)
@@ -224,8 +240,7 @@ __device__ __forceinline__ void reduce_prev(const double *__restrict__ part, int
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
     double s = red[0][q];
-#pragma unroll
-    for (int k = 1; k < kBS / 64; ++k) s += red[k][q];
+    for (int k = 1; k < nw; ++k) s += red[k][q];
     tot[q] = s;
   }
 }
@@ -757,7 +772,7 @@ __global__ __launch_bounds__(kBS) void k_rhs(SimArgs a) {
 // neighbour: (s, t), (p, v) (two generations) and (r, v).  The border row
 // and column (zero mean, multiplier) are slot N of every vector.
 // The node rows of one block of k_bicg_pv (cpN: c_d times the border entry of p').
-template <int D>
+template <int D, int KP>
 __device__ __forceinline__ void pv_rows(const SimArgs &a, const BlockDesc &b, bool again, bool first,
                                         int early, double omega, double beta, double alpha_p, double cpN) {
   const int64_t N = a.N;
@@ -798,7 +813,7 @@ __device__ __forceinline__ void pv_rows(const SimArgs &a, const BlockDesc &b, bo
             [&](int, double wj, double rj) __attribute__((always_inline)) { acc = fma(wj, rj, acc); },
             [&]() __attribute__((always_inline)) { pin(acc); });
       } else {
-        gather_chunks<W, 8>(
+        gather_chunks<W, KP>(
             b.idx, cnt32, t32, wl,
             [&](int32_t nb) __attribute__((always_inline)) {
               return Pack<double2, 2>{{ld_at<double2>(STb, nb), ld_at<double2>(PVb, nb)}};
@@ -820,7 +835,9 @@ __device__ __forceinline__ void pv_rows(const SimArgs &a, const BlockDesc &b, bo
   block_partials<kNA>(part, a.partA, b.prow, again);
 }
 
-template <int D>
+// KP: entries per gather chunk (a tuning parameter: more loads in flight
+// against more registers held).
+template <int D, int KP>
 __global__ __launch_bounds__(kBS) void k_bicg_pv(SimArgs a, int it) {
   Scalars *sc = a.sc;
   const int par = it & 1;
@@ -838,21 +855,23 @@ __global__ __launch_bounds__(kBS) void k_bicg_pv(SimArgs a, int it) {
     // last batch end) of unfinished domains; each domain's scalars were
     // decided by k_reduce_b (or k_reduce_r)
     const int32_t *lst = lsel ? a.active : a.dom_blk;
-    for (int64_t v = blockIdx.x; v < nact; v += gridDim.x) {
+    // the grid holds a workgroup for every block, so each takes at most one list position
+    const int64_t v = list_pos(blockIdx.x, nact, a.xcd_order);
+    if (v < nact) {
       const int32_t bi = a.K == 1 ? (int32_t)v : lst[v];   // one domain: every block, in order
       const BlockDesc b = a.blk[bi];
       const DomState &ds = a.dom[b.domain];
       const int64_t NB = N + b.domain;
-      if (ds.done) continue;
+      if (ds.done) return;
       if (first) {
-        pv_rows<D>(a, b, true, true, 0, 0.0, 0.0, 0.0, a.bscale[b.domain] * a.RV[NB].x);   // p0 = r0 on the border row
+        pv_rows<D, KP>(a, b, true, true, 0, 0.0, 0.0, 0.0, a.bscale[b.domain] * a.RV[NB].x);   // p0 = r0 on the border row
       } else {
         const int early = ds.early[par];
-        if (early == 2) continue;
+        if (early == 2) return;
         const double omega = ds.omega[par], beta = ds.beta[par];
         const double2 stb = ST[NB], pvb = PVo[NB];  // the border row, as k_reduce_a will store it
         const double pN = fma(beta, fma(-omega, pvb.y, pvb.x), fma(-omega, stb.y, stb.x));
-        pv_rows<D>(a, b, true, false, early, omega, beta, ds.alpha[par ^ 1], a.bscale[b.domain] * pN);
+        pv_rows<D, KP>(a, b, true, false, early, omega, beta, ds.alpha[par ^ 1], a.bscale[b.domain] * pN);
       }
     }
     return;
@@ -914,7 +933,7 @@ __global__ __launch_bounds__(kBS) void k_bicg_pv(SimArgs a, int it) {
     }
     if (early == 2) return;
   }
-  pv_rows<D>(a, b, false, first, early, omega, beta, alpha_p, a.bscale[0] * pN);
+  pv_rows<D, KP>(a, b, false, first, early, omega, beta, alpha_p, a.bscale[0] * pN);
 }
 
 // The node rows of one block of k_bicg_st (csN: c_d times the border entry of s).
@@ -968,11 +987,12 @@ __global__ __launch_bounds__(kBS) void k_bicg_st(SimArgs a, int it) {
   if (a.sepred) {
     // the listed blocks of unfinished domains; alpha was decided by k_reduce_a
     const int32_t *lst = lsel ? a.active : a.dom_blk;
-    for (int64_t v = blockIdx.x; v < nact; v += gridDim.x) {
+    const int64_t v = list_pos(blockIdx.x, nact, a.xcd_order);
+    if (v < nact) {
       const int32_t bi = a.K == 1 ? (int32_t)v : lst[v];
       const BlockDesc b = a.blk[bi];
       const DomState &ds = a.dom[b.domain];
-      if (ds.done) continue;
+      if (ds.done) return;
       const double alpha = ds.alpha[par];
       const double2 rvb = a.RV[N + b.domain];   // the border row, as k_reduce_b will store it
       st_rows<D>(a, b, true, alpha, a.bscale[b.domain] * fma(-alpha, rvb.y, rvb.x));

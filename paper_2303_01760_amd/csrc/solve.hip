@@ -474,16 +474,21 @@ __global__ __launch_bounds__(128) void k_mon(SolveArgs a) {
   }
 }
 
+// groups: systems per wave requested (0: the most that fit), capped at what
+// fits (3 when S <= 21, 2 when S <= 32); the list mode solves one per wave.
 template <int D, int M, int NS>
-void launch_rbffd(const SolveArgs &a, hipStream_t s, int64_t nlist = -1) {
+void launch_rbffd(const SolveArgs &a, hipStream_t s, int64_t nlist = -1, int groups = 0) {
   constexpr int S = NS + Monos<D, M>::Q;
-  if constexpr (S <= 21) {
-    if (nlist < 0) {
+  constexpr int Gmax = S <= 21 ? 3 : S <= 32 ? 2 : 1;
+  const int G = nlist >= 0 ? 1 : (groups <= 0 || groups > Gmax) ? Gmax : groups;
+  if constexpr (Gmax >= 3) {
+    if (G == 3) {
       hipLaunchKernelGGL((k_rbffd<D, M, NS, 3>), dim3((unsigned)((a.count + 2) / 3)), dim3(64), 0, s, a);
       return;
     }
-  } else if constexpr (S <= 32) {
-    if (nlist < 0) {
+  }
+  if constexpr (Gmax >= 2) {
+    if (G == 2) {
       hipLaunchKernelGGL((k_rbffd<D, M, NS, 2>), dim3((unsigned)((a.count + 1) / 2)), dim3(64), 0, s, a);
       return;
     }
@@ -650,14 +655,14 @@ hsm_status solve_bucket(const hsm_stencils *st, const Bucket &b, const double *x
     else hipLaunchKernelGGL(k_mon<3>, dim3(g), dim3(128), 0, s, a);
   } else {
     const int m = b.m, n = b.width;
-    if (d == 2 && m == 1 && n == 6) launch_rbffd<2, 1, 6>(a, s);
-    else if (d == 2 && m == 2 && n == 12) launch_rbffd<2, 2, 12>(a, s);
-    else if (d == 2 && m == 3 && n == 20) launch_rbffd<2, 3, 20>(a, s);
-    else if (d == 2 && m == 4 && n == 30) launch_rbffd<2, 4, 30>(a, s);
-    else if (d == 3 && m == 1 && n == 8) launch_rbffd<3, 1, 8>(a, s);
-    else if (d == 3 && m == 2 && n == 20) launch_rbffd<3, 2, 20>(a, s);
-    else if (d == 3 && m == 2 && n == 30) launch_rbffd<3, 2, 30>(a, s);
-    else if (d == 3 && m == 3 && n == 40) launch_rbffd<3, 3, 40>(a, s);
+    if (d == 2 && m == 1 && n == 6) launch_rbffd<2, 1, 6>(a, s, -1, st->solve_groups);
+    else if (d == 2 && m == 2 && n == 12) launch_rbffd<2, 2, 12>(a, s, -1, st->solve_groups);
+    else if (d == 2 && m == 3 && n == 20) launch_rbffd<2, 3, 20>(a, s, -1, st->solve_groups);
+    else if (d == 2 && m == 4 && n == 30) launch_rbffd<2, 4, 30>(a, s, -1, st->solve_groups);
+    else if (d == 3 && m == 1 && n == 8) launch_rbffd<3, 1, 8>(a, s, -1, st->solve_groups);
+    else if (d == 3 && m == 2 && n == 20) launch_rbffd<3, 2, 20>(a, s, -1, st->solve_groups);
+    else if (d == 3 && m == 2 && n == 30) launch_rbffd<3, 2, 30>(a, s, -1, st->solve_groups);
+    else if (d == 3 && m == 3 && n == 40) launch_rbffd<3, 3, 40>(a, s, -1, st->solve_groups);
     else {
       set_error(HSM_E_INVALID, "no local-solve kernel for this (d, m, n)");
       return HSM_E_INVALID;

@@ -28,7 +28,8 @@ _p = ctypes.c_void_p
 class NodeSetC(ctypes.Structure):
     _fields_ = [("d", ctypes.c_int32), ("n_domains", ctypes.c_int32),
                 ("host_domain_offsets", _p), ("x", _p), ("kind", _p), ("normal", _p),
-                ("host_h_regular", _p), ("host_m", _p), ("host_n", _p), ("tile_log2", ctypes.c_int32)]
+                ("host_h_regular", _p), ("host_m", _p), ("host_n", _p), ("tile_log2", ctypes.c_int32),
+                ("solve_groups", ctypes.c_int32)]
 
 
 class StencilsInfoC(ctypes.Structure):
@@ -44,7 +45,8 @@ class SimParamsC(ctypes.Structure):
     _fields_ = [("Ra", ctypes.c_double), ("Pr", ctypes.c_double), ("dt", ctypes.c_double),
                 ("T_ref", ctypes.c_double), ("krylov_tol", ctypes.c_double), ("krylov_maxiter", ctypes.c_int32),
                 ("field_dtype", ctypes.c_int32), ("krylov_chunk", ctypes.c_int32), ("launch_mode", ctypes.c_int32),
-                ("profile", ctypes.c_int32), ("reduce_mode", ctypes.c_int32)]
+                ("profile", ctypes.c_int32), ("reduce_mode", ctypes.c_int32), ("block_nodes", ctypes.c_int32),
+                ("gather_chunk", ctypes.c_int32), ("xcd_order", ctypes.c_int32)]
 
 
 class SimStatsC(ctypes.Structure):
@@ -232,7 +234,7 @@ class Stencils:
 
 
 def build_stencils(x: torch.Tensor, kind: torch.Tensor, normal: torch.Tensor, h, m, mode=MODE_HYBRID,
-                   domain_offsets=None, n=None, tile_log2=0, stream=None) -> Stencils:
+                   domain_offsets=None, n=None, tile_log2=0, solve_groups=0, stream=None) -> Stencils:
     """hsm_build_stencils on device tensors x [d,N] f64, kind [N] u8, normal [d,N] f64."""
     d, N = x.shape
     offs = np.asarray(domain_offsets if domain_offsets is not None else [0, N], np.int64)
@@ -242,7 +244,7 @@ def build_stencils(x: torch.Tensor, kind: torch.Tensor, normal: torch.Tensor, h,
     ns_ = None if n is None else np.ascontiguousarray(np.broadcast_to(np.asarray(n, np.int32), (nd,)))
     c = NodeSetC(d, nd, offs.ctypes.data, _dptr(x, torch.float64), _dptr(kind, torch.uint8),
                  _dptr(normal, torch.float64), hs.ctypes.data, ms.ctypes.data,
-                 None if ns_ is None else ns_.ctypes.data, int(tile_log2))
+                 None if ns_ is None else ns_.ctypes.data, int(tile_log2), int(solve_groups))
     h_out = _p()
     _check(lib().hsm_build_stencils(ctypes.byref(c), int(mode), _stream(stream), ctypes.byref(h_out)))
     return Stencils(h_out.value, d, N)
@@ -264,10 +266,10 @@ class Sim:
 
     def __init__(self, st: Stencils, v: torch.Tensor, T: torch.Tensor, p=None, *, Ra, Pr, dt, T_ref,
                  krylov_tol=1e-12, krylov_maxiter=20000, field_dtype=F64, krylov_chunk=0, launch_mode=0,
-                 profile=0, reduce_mode=0, stream=None):
+                 profile=0, reduce_mode=0, block_nodes=0, gather_chunk=0, xcd_order=0, stream=None):
         self.st = st
         prm = SimParamsC(Ra, Pr, dt, T_ref, krylov_tol, krylov_maxiter, field_dtype, krylov_chunk, launch_mode,
-                         profile, reduce_mode)
+                         profile, reduce_mode, block_nodes, gather_chunk, xcd_order)
         h = _p()
         _check(lib().hsm_sim_create(st.handle, ctypes.byref(prm), _dptr(v, torch.float64), _dptr(T, torch.float64),
                                     None if p is None else _dptr(p, torch.float64), _stream(stream),

@@ -38,3 +38,24 @@ def test_fill_keeps_half_a_spacing_from_the_box():
         fill = q.kind == 0
         gap = np.minimum(q.x[:, fill], 1.0 - q.x[:, fill]).min()
         assert gap >= 0.5 * h_s * (1 - 1e-12), (dim, float(gap), h_s)
+
+
+def test_full_size_step_fixture_matches_the_generator():
+    """The stored oracle fields of the full-size step test were computed on the
+    node set the generator makes now (else regenerate them with
+    tests/golden/make_fullsize_steps.py)."""
+    import hashlib
+    import os
+    z = np.load(os.path.join(os.path.dirname(__file__), "golden", "fullsize_steps_obstacles2d_h0.002.npz"))
+    s = ng.obstacles2d(h=0.002)
+    sha = hashlib.sha256()
+    for a in (s.x, s.kind, s.normal, s.tbc):
+        sha.update(np.ascontiguousarray(a).tobytes())
+    assert sha.hexdigest() == str(z["nodeset_sha256"])
+    assert int(z["n"]) == s.n == 167231
+    S = z["sample"]
+    assert len(S) == len(np.unique(S)) == 4096 and S.min() >= 0 and S.max() < s.n
+    for tag in ("hybrid", "all_scattered"):
+        assert z[f"{tag}_v"].shape == (2, len(S)) and np.all(np.isfinite(z[f"{tag}_v"]))
+        # walls are no-slip in the stored fields
+        assert np.all(z[f"{tag}_v"][:, s.kind[S] != 0] == 0.0)
