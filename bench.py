@@ -61,16 +61,20 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_bytes(sizes_buckets, N, kernel):
+def kernel_bytes(sizes_buckets, N, kernel, nnz_shared=0):
     """Algorithmic HBM bytes of one launch (FP64 values, int32 indices; every
-    array element read or written once).  sizes_buckets: [(type, width, count)]."""
+    array element read or written once).  sizes_buckets: [(type, width, count)].
+    nnz_shared: stencil entries of regular nodes that read the one shared
+    lattice row of the pressure operator (no per-node weight bytes)."""
     nnz = sum(w * c for _, w, c in sizes_buckets)
+    wbytes = 8 * (nnz - nnz_shared)
     if kernel == "bicg_pv":    # idx + weights; gather (s,t), (p,v); read x, rh; write x, (p,v), (r,v)
-        return 12 * nnz + 88 * N
+        return 4 * nnz + wbytes + 88 * N
     if kernel == "bicg_st":    # idx + weights; gather r, v; read rh; write s, t
-        return 12 * nnz + 40 * N
+        return 4 * nnz + wbytes + 40 * N
     if kernel == "iteration":  # one BiCGSTAB iteration = one launch of each
-        return kernel_bytes(sizes_buckets, N, "bicg_pv") + kernel_bytes(sizes_buckets, N, "bicg_st")
+        return (kernel_bytes(sizes_buckets, N, "bicg_pv", nnz_shared) +
+                kernel_bytes(sizes_buckets, N, "bicg_st", nnz_shared))
     raise ValueError(kernel)
 
 
@@ -660,7 +664,8 @@ def main():
         pt = hy["ptimes"]
         # the pressure solve dominates the step; its unit of work is one BiCGSTAB
         # iteration (one launch each of k_bicg_pv and k_bicg_st)
-        bytes_it = kernel_bytes(buckets, s.n, "iteration")
+        nnz_sh = hy["sizes"]["nnz_shared_rows"]
+        bytes_it = kernel_bytes(buckets, s.n, "iteration", nnz_sh)
         it_ms = pt["krylov_iter"][0]
         achieved = bytes_it / (it_ms * 1e-3) / 1e9
         if multi:
@@ -677,7 +682,10 @@ def main():
                                 f"(k_bicg_pv<{D}> + k_bicg_st<{D}> + reductions), bytes of the rows computed"
                                 if multi else f"BiCGSTAB iteration (k_bicg_pv<{D}> + k_bicg_st<{D}>)"),
                         bytes_per_launch=bytes_it,
-                        bytes_pv=kernel_bytes(buckets, s.n, "bicg_pv"), bytes_st=kernel_bytes(buckets, s.n, "bicg_st"),
+                        bytes_pv=kernel_bytes(buckets, s.n, "bicg_pv", nnz_sh),
+                        bytes_st=kernel_bytes(buckets, s.n, "bicg_st", nnz_sh),
+                        shared_lattice_rows=dict(nodes=hy["sizes"]["n_shared_rows"], stencil_entries=nnz_sh),
+                        bytes_per_launch_per_node_rows=kernel_bytes(buckets, s.n, "iteration"),
                         mean_launch_ms=it_ms, iterations_timed=pt["krylov_iter"][1], copy_kernel_gbs=copy_gbs,
                         node_rows_matvec=hy["node_mv"],
                         traffic_over_algorithmic=(tr["over_algorithmic"] if tr and "over_algorithmic" in tr else None))

@@ -238,6 +238,9 @@ typedef struct {
                               than 1024 blocks), each XCD runs one contiguous run of the Krylov kernels' blocks
                               (its L2 then holds the neighbours they gather); 0: consecutive blocks on
                               consecutive XCDs */
+  int32_t lattice_rows;    /* 0: a regular bucket whose pressure rows all equal the lattice row (1 at the
+                              centre, -1/(2d) on the cross) to 1e-12 stores that one row, read by every node;
+                              1: every node keeps its own row (as built) */
 } hsm_sim_params;
 
 typedef struct {
@@ -311,9 +314,11 @@ enum { HSM_PH_PRE = 0, HSM_PH_KRYLOV_ITER = 1, HSM_PH_POST = 2, HSM_PH_KRYLOV_TO
  */
 hsm_status hsm_sim_phase_times(hsm_sim *sim, double *host_mean_ms, int64_t *host_count);
 
-/* The per-step pressure-operator bytes and node counts behind the timings:
- * host_info[0] = N, [1] = total stencil entries (nnz), [2] = interior nodes,
- * [3] = Neumann-wall nodes. */
+/* The per-step pressure-operator bytes and node counts behind the timings
+ * (host_info: 6 entries): [0] = N, [1] = total stencil entries (nnz),
+ * [2] = interior nodes, [3] = Neumann-wall nodes, [4] = regular nodes whose
+ * pressure rows are the shared lattice row (see lattice_rows), [5] = their
+ * stencil entries. */
 hsm_status hsm_sim_sizes(hsm_sim *sim, int64_t *host_info);
 
 void hsm_sim_destroy(hsm_sim *sim);

@@ -52,6 +52,7 @@ struct hsm_sim {
   hipGraph_t gr[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   hsm_sim_stats stats{};
   int64_t n_int = 0, n_neu = 0;
+  int64_t n_shared = 0, nnz_shared = 0;   // regular nodes (and their stencil entries) on the shared lattice row
   // profiling: events captured around kernels (profile mode)
   hipEvent_t ep_pre[2][2] = {}, ep_kry[2][2] = {}, ep_post[2][2] = {};  // start/stop around each phase
   double k_sum_ms[HSM_PH_COUNT] = {};
@@ -358,6 +359,10 @@ hsm_status hsm_sim_create(const hsm_stencils *st, const hsm_sim_params *prm, con
     set_error(HSM_E_INVALID, "gather_chunk must be 0 (8), 4, 6, 8 or 12");
     return HSM_E_INVALID;
   }
+  if (prm->lattice_rows != 0 && prm->lattice_rows != 1) {
+    set_error(HSM_E_INVALID, "lattice_rows must be 0 or 1");
+    return HSM_E_INVALID;
+  }
   if (prm->xcd_order != 0 && prm->xcd_order != 1) {
     set_error(HSM_E_INVALID, "xcd_order must be 0 or 1");
     return HSM_E_INVALID;
@@ -384,9 +389,15 @@ hsm_status hsm_sim_create(const hsm_stencils *st, const hsm_sim_params *prm, con
   m->x = m->vec[0].as<double>(); m->rh = m->vec[1].as<double>();
   m->ST = m->pairs[0].as<double2>(); m->PV[0] = m->pairs[1].as<double2>(); m->PV[1] = m->pairs[2].as<double2>();
   m->RV = m->pairs[3].as<double2>();
-  // pressure-operator rows, per bucket
+  // pressure-operator rows, per bucket.  A regular bucket whose rows all
+  // equal the lattice row (1 at the centre, -1/(2d) on the cross) to within
+  // kLatticeRowTol keeps that one row instead of a row per node: the
+  // Krylov kernels then read W uniform values instead of W per node.
   std::vector<const void *> wp_of(st->buckets.size(), nullptr);
+  std::vector<int32_t> shared_of(st->buckets.size(), 0);
   {
+    DBuf dev;
+    if ((rc = dev.alloc(sizeof(unsigned long long)))) return rc;
     int k = 0;
     for (size_t kb = 0; kb < st->buckets.size(); ++kb) {
       const Bucket &B = st->buckets[kb];
@@ -398,6 +409,28 @@ hsm_status hsm_sim_create(const hsm_stencils *st, const hsm_sim_params *prm, con
       if (B.type == B_REG || B.type == B_SCAT) m->n_int += B.count;
       if (B.type == B_NEU) m->n_neu += B.count;
       wp_of[kb] = m->wP[k].p;
+      if (B.type == B_REG && B.width == 2 * st->d + 1 && prm->lattice_rows == 0) {
+        unsigned long long h = 0;
+        HSM_HIP(hipMemsetAsync(dev.p, 0, sizeof(h), us));
+        hipLaunchKernelGGL(k_lattice_dev, dim3(nblk(B.count, 256)), dim3(256), 0, us, m->wP[k].as<double>(),
+                           B.count, B.width, dev.as<unsigned long long>());
+        HSM_HIP(hipGetLastError());
+        HSM_HIP(hipMemcpyAsync(&h, dev.p, sizeof(h), hipMemcpyDeviceToHost, us));
+        HSM_HIP(hipStreamSynchronize(us));
+        double worst;
+        std::memcpy(&worst, &h, sizeof(worst));
+        if (worst <= kLatticeRowTol) {
+          std::vector<double> row(B.width, -1.0 / (double)(2 * st->d));
+          row[0] = 1.0;
+          if ((rc = m->wP[k].alloc(sizeof(double) * B.width))) return rc;
+          HSM_HIP(hipMemcpyAsync(m->wP[k].p, row.data(), sizeof(double) * B.width, hipMemcpyHostToDevice, us));
+          HSM_HIP(hipStreamSynchronize(us));
+          wp_of[kb] = m->wP[k].p;
+          shared_of[kb] = 1;
+          m->n_shared += B.count;
+          m->nnz_shared += B.count * B.width;
+        }
+      }
       ++k;
     }
   }
@@ -424,6 +457,7 @@ hsm_status hsm_sim_create(const hsm_stencils *st, const hsm_sim_params *prm, con
       bd.idx = B.idx.p;
       bd.w = m->f32 ? B.w32.p : B.w.p;             // field weights in the field storage type
       bd.wP = wp_of[kb];
+      bd.wshared = shared_of[kb];
       bd.bstart = B.start;
       bd.first = (int32_t)j;
       bd.nodes = (int32_t)(e - j);
@@ -593,6 +627,8 @@ hsm_status hsm_sim_sizes(hsm_sim *m, int64_t *info) {
   info[1] = m->st->nnz;
   info[2] = m->n_int;
   info[3] = m->n_neu;
+  info[4] = m->n_shared;
+  info[5] = m->nnz_shared;
   return HSM_OK;
 }
 

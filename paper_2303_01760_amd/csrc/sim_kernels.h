@@ -20,6 +20,12 @@ constexpr int kNB = 6;          // partial sums of the s/t kernel
 constexpr int kMaxIterChunk = 256;
 constexpr int64_t kSepReduceBlocks = 1024;   // above this grid size, totals come from the reduction kernels
 constexpr int kRedThreads = 1024;            // threads of a reduction kernel (one block)
+// A regular bucket shares the lattice pressure row when every row deviates
+// from it by at most this (the rows are O(1): divided by the centre weight).
+// Regular nodes of an exact lattice deviate by rounding only (about 1e-16);
+// the classifier admits cross nodes up to 1e-6 h_r off, whose rows then keep
+// their own weights.
+constexpr double kLatticeRowTol = 1e-12;
 
 // Host-visible summary written once per batch of Krylov iterations.
 struct HostFlags {
@@ -67,7 +73,8 @@ struct BlockDesc {
   int32_t domain;      // the border row of this block's nodes is N + domain
   int32_t prow;        // row of this block's partial sums: its place in the per-domain block lists,
                        // so each domain's rows are contiguous
-  int32_t pad;
+  int32_t wshared;     // 1: wP is one row of `width` doubles that every node of the block uses (regular
+                       // nodes whose pressure rows all equal the lattice row); 0: wP is [width][count]
 };
 static_assert(sizeof(BlockDesc) == 64, "one 64-byte scalar load per block");
 
@@ -99,6 +106,25 @@ struct SimArgs {
   Scalars *sc;
   DomState *dom;                   // [K] (reduction-kernel path)
 };
+
+// The pressure-operator rows of a block: per node (SoA [W][count]), or one
+// row shared by every node of the block (read as uniform scalars).  f gets
+// std::true_type for the shared row; only the regular width can have one.
+template <int D, int W, class F>
+__device__ __forceinline__ void with_rows(const BlockDesc &b, F &&f) {
+  if constexpr (W == 2 * D + 1) {
+    if (b.wshared) {
+      f(std::true_type{});
+      return;
+    }
+  }
+  f(std::false_type{});
+}
+template <bool SH>
+__device__ __forceinline__ double ld_prow(const BlockDesc &b, uint32_t cnt, int j, uint32_t t) {
+  if constexpr (SH) return static_cast<const double *>(b.wP)[j];
+  else return ld_soa<double>(b.wP, cnt, j, t);
+}
 
 template <class F>
 __device__ __forceinline__ void with_width2(int w, F &&f) {
@@ -710,6 +736,8 @@ __global__ __launch_bounds__(kBS) void k_rhs(SimArgs a) {
     constexpr bool kDiff = kDiffForm<FT>;
     with_width<D>(b.width, [&](auto wc) __attribute__((always_inline)) {
       constexpr int W = decltype(wc)::value;
+      with_rows<D, W>(b, [&](auto sh) __attribute__((always_inline)) {
+      constexpr bool SH = decltype(sh)::value;
       double Ap = 0.0;
       AccT div;
       div.init();
@@ -720,7 +748,7 @@ __global__ __launch_bounds__(kBS) void k_rhs(SimArgs a) {
           b.idx, cnt32, t32,
           [&](int j) __attribute__((always_inline)) {
             Pack<double, 1> wp;
-            wp.v[0] = ld_soa<double>(b.wP, cnt32, j, t32);
+            wp.v[0] = ld_prow<SH>(b, cnt32, j, t32);
             Pack<FT, D> wd;
 #pragma unroll
             for (int q = 0; q < D; ++q)   // unused at walls
@@ -749,6 +777,7 @@ __global__ __launch_bounds__(kBS) void k_rhs(SimArgs a) {
           [&]() __attribute__((always_inline)) { pin(Ap); div.settle(); });
       if (!wall) rhs = (div.get_d() / dt) / (double)ld_soa<FT>(b.w, cnt32, D * W, t32);
       r = rhs - (Ap + lam);
+      });
     });
     a.RV[i] = make_double2(r, 0.0);
     a.rh[i] = r;
@@ -806,7 +835,9 @@ __device__ __forceinline__ void pv_rows(const SimArgs &a, const BlockDesc &b, bo
     double acc = 0.0;
     with_width<D>(b.width, [&](auto wc) __attribute__((always_inline)) {
       constexpr int W = decltype(wc)::value;
-      const auto wl = [&](int j) __attribute__((always_inline)) { return ld_soa<double>(b.wP, cnt32, j, t32); };
+      with_rows<D, W>(b, [&](auto sh) __attribute__((always_inline)) {
+      constexpr bool SH = decltype(sh)::value;
+      const auto wl = [&](int j) __attribute__((always_inline)) { return ld_prow<SH>(b, cnt32, j, t32); };
       if (first) {
         gather_chunks<W>(
             b.idx, cnt32, t32, wl, [&](int32_t nb) __attribute__((always_inline)) { return ld_at<double>(RVb, 2 * nb); },
@@ -824,6 +855,7 @@ __device__ __forceinline__ void pv_rows(const SimArgs &a, const BlockDesc &b, bo
             },
             [&]() __attribute__((always_inline)) { pin(acc); });
       }
+      });
     });
     const double vi = acc + cpN;                // + c_d times the border entry of p'
     a.PVn[i] = make_double2(pi, vi);
@@ -952,13 +984,16 @@ __device__ __forceinline__ void st_rows(const SimArgs &a, const BlockDesc &b, bo
     double acc = 0.0;
     with_width<D>(b.width, [&](auto wc) __attribute__((always_inline)) {
       constexpr int W = decltype(wc)::value;
+      with_rows<D, W>(b, [&](auto sh) __attribute__((always_inline)) {
+      constexpr bool SH = decltype(sh)::value;
       gather_chunks<W>(
-          b.idx, cnt32, t32, [&](int j) __attribute__((always_inline)) { return ld_soa<double>(b.wP, cnt32, j, t32); },
+          b.idx, cnt32, t32, [&](int j) __attribute__((always_inline)) { return ld_prow<SH>(b, cnt32, j, t32); },
           [&](int32_t nb) __attribute__((always_inline)) { return ld_at<double2>(RVb, nb); },
           [&](int, double wj, const double2 &rv2) __attribute__((always_inline)) {
             acc = fma(wj, fma(-alpha, rv2.y, rv2.x), acc);
           },
           [&]() __attribute__((always_inline)) { pin(acc); });
+      });
     });
     const double2 rvi = RV[i];
     const double si = fma(-alpha, rvi.y, rvi.x);
@@ -1212,6 +1247,23 @@ __global__ void k_scale_rows(const double *w, int64_t cnt, int W, int slot, doub
   const double *src = w + (int64_t)slot * W * cnt;
   const double dg = src[t];
   for (int j = 0; j < W; ++j) wP[(int64_t)j * cnt + t] = src[(int64_t)j * cnt + t] / dg;
+}
+
+// Largest |wP[j][t] - L_j| over a regular bucket's pressure rows, L the
+// lattice row (1 at the centre, -1/(2d) at each of the 2d cross nodes: the
+// MON Laplacian on an exact lattice cross, divided by its centre weight).
+// Non-negative doubles order as their bit patterns; a NaN deviation maps to
+// the largest pattern.
+__global__ void k_lattice_dev(const double *wP, int64_t cnt, int W, unsigned long long *dev) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= cnt) return;
+  const double off = -1.0 / (double)(W - 1);
+  double m = 0.0;
+  for (int j = 0; j < W; ++j) {
+    const double e = fabs(wP[(int64_t)j * cnt + t] - (j == 0 ? 1.0 : off));
+    m = (e > m || e != e) ? (e != e ? INFINITY : e) : m;
+  }
+  atomicMax(dev, (unsigned long long)__double_as_longlong(m));
 }
 
 __global__ void k_fill(double *p, int64_t n, double v) {

@@ -46,7 +46,7 @@ class SimParamsC(ctypes.Structure):
                 ("T_ref", ctypes.c_double), ("krylov_tol", ctypes.c_double), ("krylov_maxiter", ctypes.c_int32),
                 ("field_dtype", ctypes.c_int32), ("krylov_chunk", ctypes.c_int32), ("launch_mode", ctypes.c_int32),
                 ("profile", ctypes.c_int32), ("reduce_mode", ctypes.c_int32), ("block_nodes", ctypes.c_int32),
-                ("gather_chunk", ctypes.c_int32), ("xcd_order", ctypes.c_int32)]
+                ("gather_chunk", ctypes.c_int32), ("xcd_order", ctypes.c_int32), ("lattice_rows", ctypes.c_int32)]
 
 
 class SimStatsC(ctypes.Structure):
@@ -266,10 +266,11 @@ class Sim:
 
     def __init__(self, st: Stencils, v: torch.Tensor, T: torch.Tensor, p=None, *, Ra, Pr, dt, T_ref,
                  krylov_tol=1e-12, krylov_maxiter=20000, field_dtype=F64, krylov_chunk=0, launch_mode=0,
-                 profile=0, reduce_mode=0, block_nodes=0, gather_chunk=0, xcd_order=0, stream=None):
+                 profile=0, reduce_mode=0, block_nodes=0, gather_chunk=0, xcd_order=0, lattice_rows=0,
+                 stream=None):
         self.st = st
         prm = SimParamsC(Ra, Pr, dt, T_ref, krylov_tol, krylov_maxiter, field_dtype, krylov_chunk, launch_mode,
-                         profile, reduce_mode, block_nodes, gather_chunk, xcd_order)
+                         profile, reduce_mode, block_nodes, gather_chunk, xcd_order, lattice_rows)
         h = _p()
         _check(lib().hsm_sim_create(st.handle, ctypes.byref(prm), _dptr(v, torch.float64), _dptr(T, torch.float64),
                                     None if p is None else _dptr(p, torch.float64), _stream(stream),
@@ -297,9 +298,10 @@ class Sim:
         return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(PHASES)}
 
     def sizes(self) -> dict:
-        info = np.zeros(4, np.int64)
+        info = np.zeros(6, np.int64)
         _check(lib().hsm_sim_sizes(self._h, info.ctypes.data))
-        return dict(N=int(info[0]), nnz=int(info[1]), n_interior=int(info[2]), n_neumann=int(info[3]))
+        return dict(N=int(info[0]), nnz=int(info[1]), n_interior=int(info[2]), n_neumann=int(info[3]),
+                    n_shared_rows=int(info[4]), nnz_shared_rows=int(info[5]))
 
     def read(self, stream=None):
         d, N = self.st.d, self.st.n

@@ -88,6 +88,54 @@ def test_cavity_100_steps_parity(mode, reduce_mode):
     assert abs(stats["krylov_iters_total"] - int(its.sum())) <= 0.1 * its.sum() + 10
 
 
+@pytest.mark.parametrize("lattice_rows", [0, 1])
+def test_shared_lattice_rows_match_per_node_rows_and_oracle(lattice_rows):
+    """The cavity's 39^2 regular nodes sit on an exact lattice: their pressure
+    rows equal the lattice row (1, -1/4, -1/4, -1/4, -1/4) up to rounding, so
+    by default they share that one row; with lattice_rows = 1 each keeps its
+    own.  Both match the oracle after 100 steps."""
+    hsm = _hsm()
+    s, prm, v, T, vo, To, po, its = _cavity_oracle(0)
+    st = _build(s, 2, 0)
+    dev = torch.device("cuda")
+    sim = hsm.Sim(st, torch.tensor(v, device=dev), torch.tensor(T, device=dev), krylov_tol=1e-12,
+                  lattice_rows=lattice_rows, **prm)
+    assert sim.sizes()["n_shared_rows"] == (39 ** 2 if lattice_rows == 0 else 0)
+    assert sim.sizes()["nnz_shared_rows"] == 5 * sim.sizes()["n_shared_rows"]
+    sim.step(100)
+    vg, Tg, pg = [a.cpu().numpy() for a in sim.read()]
+    ev, eT, ep = _rel(vg, vo), _rel(Tg, To), _rel(pg, po)
+    print(f"lattice_rows={lattice_rows}: rel L2 err v {ev:.2e} T {eT:.2e} p {ep:.2e}")
+    assert ev <= FIELD_TOL and eT <= FIELD_TOL and ep <= FIELD_TOL
+
+
+def test_perturbed_regular_nodes_keep_their_own_rows():
+    """Regular nodes moved by up to 1e-9 h (well inside the classifier's 1e-6
+    h_r tolerance) have MON rows that differ from the lattice row by far
+    more than 1e-12: they keep their own rows, and the steps match the oracle."""
+    hsm = _hsm()
+    s = ng.cavity2d(h=0.05)
+    rng = np.random.default_rng(77)
+    inner = s.kind == 0
+    s.x[:, inner] += (rng.random((2, int(inner.sum()))) - 0.5) * 2e-9 * s.h
+    dt = 0.1 * s.h ** 2 / 2
+    prm = dict(Ra=1e4, Pr=0.71, dt=dt, T_ref=0.5)
+    st = _build(s, 2, 0)
+    assert st.info()["n_regular"] > 0
+    v, T = _cavity_init(s)
+    dev = torch.device("cuda")
+    sim = hsm.Sim(st, torch.tensor(v, device=dev), torch.tensor(T, device=dev), krylov_tol=1e-12, **prm)
+    assert sim.sizes()["n_shared_rows"] == 0
+    sim.step(20)
+    vg, Tg, pg = [a.cpu().numpy() for a in sim.read()]
+    ora = O.to_csr(O.build(s.x, s.kind, s.normal, s.h, 2))
+    vo, To, po = v.copy(), T.copy(), np.zeros(s.n + 1)
+    O.Sim(ora, s.kind).step(vo, To, po, 20, tol=1e-12, **prm)
+    ev, eT, ep = _rel(vg, vo), _rel(Tg, To), _rel(pg, po[:-1])
+    print(f"perturbed lattice: rel L2 err v {ev:.2e} T {eT:.2e} p {ep:.2e}")
+    assert ev <= FIELD_TOL and eT <= FIELD_TOL and ep <= FIELD_TOL
+
+
 @pytest.mark.parametrize("mode", [0, 1])
 def test_cavity_100_steps_fp32_form(mode):
     # FP32 v and T with compensated (Dot2) applies, FP64 pressure solve
