@@ -239,15 +239,17 @@ __global__ __launch_bounds__(64) void k_rbffd(SolveArgs a) {
   double s;
   rbffd_rows<D, M, NS, G>(a, t, lane, Rw, B, c, s, grp);
 
-  // elimination.  The pivot row of each step reaches its group through LDS:
-  // the pivot lane writes columns k..S-1 and the right-hand sides to its
-  // group's row, and every lane reads them back as it eliminates (a
-  // broadcast read: the group's lanes read the same address).  One LDS write
-  // and one read per entry, instead of two lane moves per entry and a
-  // register copy of the whole pivot row.  The arithmetic is unchanged.
+  // elimination.  One system per wave (G = 1): the pivot row is read lane by
+  // lane into scalar registers (v_readlane) and used as a scalar operand.
+  // Several systems per wave: the pivot row of each step reaches its group
+  // through LDS: the pivot lane writes columns k..S-1 and the right-hand
+  // sides to its group's row, and every lane reads them back as it
+  // eliminates (a broadcast read: the group's lanes read the same address),
+  // instead of two lane permutes per entry.  The arithmetic is the same
+  // either way.
   constexpr int PW = (S + R + 1) & ~1;         // row length, even: 16-byte aligned rows
-  __shared__ __align__(16) double prow_[G][PW];
-  double *prow = prow_[grp];
+  __shared__ __align__(16) double prow_[G == 1 ? 1 : G][G == 1 ? 2 : PW];
+  double *prow = prow_[G == 1 ? 0 : grp];
   double amax = 0.0;
 #pragma unroll
   for (int k = 0; k < S; ++k) amax = fmax(amax, fabs(Rw[k]));
@@ -267,26 +269,46 @@ __global__ __launch_bounds__(64) void k_rbffd(SolveArgs a) {
     const unsigned long long gm = (G == 1) ? mask : ((mask >> base) & ((1ull << GL) - 1ull));
     const int p = gm ? __ffsll((long long)gm) - 1 : 0;
     piv[k] = p;
-    if (lane == p) {
+    if constexpr (G == 1) {
+      (void)prow;
+      double pr[S], pb[R];
+      const double pk = rdlane(Rw[k], p);
 #pragma unroll
-      for (int j = k; j < S; ++j) prow[j] = Rw[j];
+      for (int j = k + 1; j < S; ++j) pr[j] = rdlane(Rw[j], p);
 #pragma unroll
-      for (int q = 0; q < R; ++q) prow[S + q] = B[q];
-    }
-    __syncthreads();                          // one wave per block: orders the LDS write before the reads
-    if (!singular) {
+      for (int q = 0; q < R; ++q) pb[q] = rdlane(B[q], p);
       if (lane == p) {
         used = true;
         pstep = k;
       } else if (!used) {
-        const double l = Rw[k] / prow[k];
+        const double l = Rw[k] / pk;
 #pragma unroll
-        for (int j = k + 1; j < S; ++j) Rw[j] = Rw[j] - l * prow[j];
+        for (int j = k + 1; j < S; ++j) Rw[j] = Rw[j] - l * pr[j];
 #pragma unroll
-        for (int q = 0; q < R; ++q) B[q] = B[q] - l * prow[S + q];
+        for (int q = 0; q < R; ++q) B[q] = B[q] - l * pb[q];
       }
+    } else {
+      if (lane == p) {
+#pragma unroll
+        for (int j = k; j < S; ++j) prow[j] = Rw[j];
+#pragma unroll
+        for (int q = 0; q < R; ++q) prow[S + q] = B[q];
+      }
+      __syncthreads();                        // one wave per block: orders the LDS write before the reads
+      if (!singular) {
+        if (lane == p) {
+          used = true;
+          pstep = k;
+        } else if (!used) {
+          const double l = Rw[k] / prow[k];
+#pragma unroll
+          for (int j = k + 1; j < S; ++j) Rw[j] = Rw[j] - l * prow[j];
+#pragma unroll
+          for (int q = 0; q < R; ++q) B[q] = B[q] - l * prow[S + q];
+        }
+      }
+      __syncthreads();                        // every read of this pivot row before the next is written
     }
-    __syncthreads();                          // every read of this pivot row before the next is written
   }
   if (G == 1 && singular) {
     if (lane == 0) {

@@ -22,6 +22,7 @@ from __future__ import annotations
 import argparse
 import json
 import math
+import os
 import sys
 import time
 
@@ -48,9 +49,13 @@ def nusselt(st: hsm.Stencils, T: torch.Tensor, nodes: np.ndarray, L: float = 1.0
 
 def run_case(q: ng.NodeSet, *, Ra: float, Pr: float = 0.71, T_ref: float, t_end: float, dt: float,
              cold: np.ndarray, m: int = 2, tol: float = 1e-10, reports: int = 30, max_steps: int | None = None,
-             progress=None, label: str = "") -> dict:
+             progress=None, label: str = "", checkpoint: str | None = None, budget_s: float | None = None) -> dict:
     """Step a node set from v = 0, T = its Dirichlet values (0 elsewhere) to
-    t_end (or max_steps); return the history of Nu over the `cold` nodes."""
+    t_end (or max_steps); return the history of Nu over the `cold` nodes.
+    checkpoint: a .npz file holding v, T, p, the step count and the history
+    so far: the run continues from it if it exists, and rewrites it at every
+    report; budget_s: stop at the first report after this much stepping time
+    (the result then has complete = False)."""
     nsteps = int(math.ceil(t_end / dt - 1e-9))
     if max_steps is not None:
         nsteps = min(nsteps, max_steps)
@@ -62,27 +67,45 @@ def run_case(q: ng.NodeSet, *, Ra: float, Pr: float = 0.71, T_ref: float, t_end:
     t_build = time.perf_counter() - t0
     v0 = torch.zeros((q.d, q.n), dtype=torch.float64, device=dev)
     T0 = torch.tensor(np.where(q.kind == ng.KIND_DIRICHLET, q.tbc, 0.0), device=dev)
-    sim = hsm.Sim(st, v0, T0, Ra=Ra, Pr=Pr, dt=dt, T_ref=T_ref, krylov_tol=tol)
+    p0 = None
     hist = []
-    done, t_step = 0, 0.0
+    done, t_step, iters_before = 0, 0.0, 0
+    if checkpoint and os.path.exists(checkpoint):
+        ck = np.load(checkpoint)
+        if int(ck["n"]) != q.n or float(ck["dt"]) != dt:
+            raise ValueError(f"checkpoint {checkpoint} is for another node set or time step")
+        v0, T0, p0 = (torch.tensor(ck["v"], device=dev), torch.tensor(ck["T"], device=dev),
+                      torch.tensor(ck["p"], device=dev))
+        done, t_step, iters_before = int(ck["done"]), float(ck["stepping_s"]), int(ck["krylov_iters"])
+        hist = [tuple(r) for r in ck["hist"].tolist()]
+    sim = hsm.Sim(st, v0, T0, p0, Ra=Ra, Pr=Pr, dt=dt, T_ref=T_ref, krylov_tol=tol)
     per = max(1, nsteps // reports)
+    t_run = 0.0
     while done < nsteps:
+        if budget_s is not None and t_run > budget_s:
+            break
         k = min(per, nsteps - done)
         torch.cuda.synchronize()
         ts = time.perf_counter()
         sim.step(k)
         torch.cuda.synchronize()
         t_step += time.perf_counter() - ts
+        t_run += time.perf_counter() - ts
         done += k
         stats = sim.stats()
         if stats["status"] != 0:
             raise hsm.HsmError(stats["status"], f"stepping failed at step {done}", -1)
-        _, T, _ = sim.read()
+        v, T, p = sim.read()
         nu = nusselt(st, T, cold)
         hist.append((done * dt, nu))
+        iters = iters_before + stats["krylov_iters_total"]
+        if checkpoint:
+            np.savez(checkpoint + ".tmp.npz", v=v.cpu().numpy(), T=T.cpu().numpy(), p=p.cpu().numpy(), done=done,
+                     n=q.n, dt=dt, stepping_s=t_step, krylov_iters=iters, hist=np.array(hist))
+            os.replace(checkpoint + ".tmp.npz", checkpoint)
         if progress:
             progress(f"{label}: t={done * dt:.5f} ({done}/{nsteps} steps) Nu={nu:.4f} "
-                     f"krylov iters/step {stats['krylov_iters_total'] / done:.1f}")
+                     f"krylov iters/step {iters / done:.1f}")
     v, T, p = [a.cpu().numpy() for a in sim.read()]
     stats = sim.stats()
     info = st.info()
@@ -90,14 +113,15 @@ def run_case(q: ng.NodeSet, *, Ra: float, Pr: float = 0.71, T_ref: float, t_end:
     st.close()
     return dict(N=q.n, n_regular=int(info["n_regular"]), n_scattered=int(info["n_scattered"]),
                 n_scattered_fill=int(np.sum(q.origin == 2)), n_lattice=int(np.sum(q.origin == 0)), Ra=Ra, Pr=Pr,
-                dt=dt, t_end=nsteps * dt, steps=nsteps, krylov_tol=tol,
-                krylov_iters_total=stats["krylov_iters_total"], nu_final=hist[-1][1], nu_history=hist,
-                build_s=t_build, stepping_s=t_step, ms_per_step=1e3 * t_step / nsteps, v=v, T=T)
+                dt=dt, t_end=nsteps * dt, steps=done, complete=done >= nsteps, krylov_tol=tol,
+                krylov_iters_total=iters_before + stats["krylov_iters_total"],
+                nu_final=hist[-1][1] if hist else None, nu_history=hist,
+                build_s=t_build, stepping_s=t_step, ms_per_step=1e3 * t_step / max(done, 1), v=v, T=T)
 
 
 def run(h: float = 0.01, layout: str = "hybrid", Ra: float = 1e6, Pr: float = 0.71, t_end: float = 0.15,
         dt: float | None = None, m: int = 2, tol: float = 1e-10, reports: int = 30, seed: int = ng.SEED_BASE + 6,
-        delta_h: float = 4.0, progress=None) -> dict:
+        delta_h: float = 4.0, progress=None, checkpoint: str | None = None, budget_s: float | None = None) -> dict:
     """The cavity to t_end; layout hybrid / regular / scattered, or
     horizontal / vertical (the split at h*delta_h); returns the Nu history
     and the midline profile."""
@@ -107,7 +131,8 @@ def run(h: float = 0.01, layout: str = "hybrid", Ra: float = 1e6, Pr: float = 0.
         q = ng.dvd2d(h, layout, seed=seed)
     dt = 0.1 * h * h / 2 if dt is None else dt      # the paper's time-step rule
     r = run_case(q, Ra=Ra, Pr=Pr, T_ref=0.0, t_end=t_end, dt=dt, cold=cold_wall_nodes(q), m=m, tol=tol,
-                 reports=reports, progress=progress, label=f"{layout} h={h}")
+                 reports=reports, progress=progress, label=f"{layout} h={h}", checkpoint=checkpoint,
+                 budget_s=budget_s)
     v = r.pop("v")
     r.pop("T")
     mid = np.nonzero(np.abs(q.x[1] - 0.5) <= h)[0]
@@ -129,15 +154,23 @@ def main(argv=None):
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--reports", type=int, default=30)
     ap.add_argument("--out", default=None, help="write the results as JSON here")
+    ap.add_argument("--checkpoint", default=None,
+                    help="directory of per-run .npz checkpoints: a run continues from its checkpoint and rewrites "
+                         "it at every report")
+    ap.add_argument("--budget-s", type=float, default=None, help="stop each run after this much stepping time")
     a = ap.parse_args(argv)
     res = []
     for lay in a.layout:
         for dh in (a.delta_h if lay in ("horizontal", "vertical") else [None]):
+            ck = None
+            if a.checkpoint:
+                os.makedirs(a.checkpoint, exist_ok=True)
+                ck = os.path.join(a.checkpoint, f"dvd_{lay}_h{a.h}_d{dh}_Ra{a.Ra:g}.npz")
             r = run(h=a.h, layout=lay, Ra=a.Ra, t_end=a.t_end, tol=a.tol, reports=a.reports,
                     delta_h=dh if dh is not None else 4.0,
-                    progress=lambda s: print(s, file=sys.stderr, flush=True))
-            print(json.dumps({k: r[k] for k in ("layout", "h", "delta_h", "N", "steps", "nu_final", "stepping_s",
-                                                "krylov_iters_total")}), flush=True)
+                    progress=lambda s: print(s, file=sys.stderr, flush=True), checkpoint=ck, budget_s=a.budget_s)
+            print(json.dumps({k: r[k] for k in ("layout", "h", "delta_h", "N", "steps", "complete", "nu_final",
+                                                "stepping_s", "krylov_iters_total")}), flush=True)
             res.append(r)
     if a.out:
         with open(a.out, "w") as f:

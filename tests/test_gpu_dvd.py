@@ -75,3 +75,24 @@ def test_refined_obstacle_layout_build_and_steps_match_oracle():
     ev, eT, ep = _rel(vg, vo), _rel(Tg, To), _rel(pg, po[:q.n])
     print(f"refined 2D: N={q.n}, weight rel err {werr:.1e}, fields v {ev:.2e} T {eT:.2e} p {ep:.2e}")
     assert ev <= FIELD_TOL and eT <= FIELD_TOL and ep <= FIELD_TOL
+
+
+def test_checkpointed_run_continues_where_it_stopped(tmp_path):
+    """A run stopped by its time budget and continued from its checkpoint
+    reaches the same fields and Nusselt history as one uninterrupted run (the
+    pressure border multiplier restarts from zero, so the two agree to the
+    Krylov tolerance, not bit for bit)."""
+    from paper_2303_01760_amd import dvd
+    q = ng.dvd2d(0.05, "hybrid")
+    dt = 0.1 * q.h ** 2 / 2
+    kw = dict(Ra=1e5, T_ref=0.0, t_end=60 * dt, dt=dt, cold=dvd.cold_wall_nodes(q), tol=1e-12, reports=6)
+    whole = dvd.run_case(q, **kw)
+    ck = str(tmp_path / "ck.npz")
+    part = dvd.run_case(q, **kw, checkpoint=ck, budget_s=0.0)     # stops after its first report
+    assert not part["complete"] and part["steps"] == 10
+    rest = dvd.run_case(q, **kw, checkpoint=ck)
+    assert rest["complete"] and rest["steps"] == 60
+    assert len(rest["nu_history"]) == len(whole["nu_history"])
+    for (ta, na), (tb, nb) in zip(rest["nu_history"], whole["nu_history"]):
+        assert abs(ta - tb) <= 1e-15 and abs(na - nb) <= 1e-8 * abs(nb)
+    assert _rel(rest["v"], whole["v"]) <= FIELD_TOL and _rel(rest["T"], whole["T"]) <= FIELD_TOL
