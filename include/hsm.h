@@ -251,6 +251,8 @@ typedef struct {
   double last_relres;            /* relative residual reached in the last step */
   int64_t node_applies;          /* (operator, field, node) triples evaluated so far */
   int64_t krylov_node_matvecs;   /* node rows through a pressure matrix-vector product so far */
+  int64_t krylov_reduced_batches; /* Krylov batches launched on a grid below the full one (several domains: the
+                                     grid follows the shrinking list of unfinished domains' blocks) */
 } hsm_sim_stats;
 
 /*

@@ -48,8 +48,18 @@ struct hsm_sim {
   hipEvent_t ev_in = nullptr, ev_out = nullptr, ev_chunk[2] = {nullptr, nullptr};
   HostFlags *hflags = nullptr;   // pinned [2]
   bool graphs_ready = false;
-  hipGraphExec_t g_pre[2] = {nullptr, nullptr}, g_kry[2] = {nullptr, nullptr}, g_post[2] = {nullptr, nullptr};
-  hipGraph_t gr[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  hipGraphExec_t g_pre[2] = {nullptr, nullptr}, g_post[2] = {nullptr, nullptr};
+  hipGraph_t gr[4] = {nullptr, nullptr, nullptr, nullptr};
+  // Krylov batches per host-flag slot and grid level: with several domains the
+  // list of blocks to run shrinks as domains finish, and a batch is launched
+  // with the smallest captured grid that still covers it (level L: the full
+  // grid halved L times)
+  static constexpr int kLevels = 8;
+  hipGraphExec_t g_kry[2][kLevels] = {};
+  hipGraph_t gr_kry[2][kLevels] = {};
+  int nlev = 1;
+  int64_t lev_grid[kLevels] = {};
+  int64_t known_nact = 0;     // an upper bound of the blocks still to run (from the latest flags read)
   hsm_sim_stats stats{};
   int64_t n_int = 0, n_neu = 0;
   int64_t n_shared = 0, nnz_shared = 0;   // regular nodes (and their stencil entries) on the shared lattice row
@@ -72,9 +82,10 @@ struct hsm_sim {
   ~hsm_sim() {
     if (s) (void)hipStreamSynchronize(s);
     for (auto &g : g_pre) if (g) (void)hipGraphExecDestroy(g);
-    for (auto &g : g_kry) if (g) (void)hipGraphExecDestroy(g);
+    for (auto &row : g_kry) for (auto &g : row) if (g) (void)hipGraphExecDestroy(g);
     for (auto &g : g_post) if (g) (void)hipGraphExecDestroy(g);
     for (auto &g : gr) if (g) (void)hipGraphDestroy(g);
+    for (auto &row : gr_kry) for (auto &g : row) if (g) (void)hipGraphDestroy(g);
     if (hflags) (void)hipHostFree(hflags);
     for (auto &e : ev_chunk) if (e) (void)hipEventDestroy(e);
     for (auto &row : ep_pre) for (auto &e : row) if (e) (void)hipEventDestroy(e);
@@ -142,8 +153,8 @@ hsm_status enqueue_pre(hsm_sim *m, int par, hipStream_t s) {
 // Krylov iterations [it0, it1) of a batch; the ping-pong parity follows the
 // iteration number, so a batch may be split across launch paths.
 template <int D>
-hsm_status enqueue_krylov(hsm_sim *m, int slot, hipStream_t s, int it0, int it1, bool flags) {
-  const dim3 g((unsigned)m->kry_grid), b((unsigned)m->bs);
+hsm_status enqueue_krylov(hsm_sim *m, int slot, hipStream_t s, int it0, int it1, bool flags, int lev = 0) {
+  const dim3 g((unsigned)m->lev_grid[lev]), b((unsigned)m->bs);
   for (int it = it0; it < it1; ++it) {
     SimArgs a = make_args(m, 0, it & 1);
     switch (m->kp) {
@@ -200,11 +211,12 @@ hsm_status make_graphs(hsm_sim *m) {
   hsm_status rc;
   for (int par = 0; par < 2; ++par) {
     if ((rc = capture(m, m->gr[par], m->g_pre[par], [&] { return enqueue_pre<D>(m, par, m->s); }))) return rc;
-    if ((rc = capture(m, m->gr[4 + par], m->g_post[par], [&] { return enqueue_post<D>(m, par, m->s); })))
+    if ((rc = capture(m, m->gr[2 + par], m->g_post[par], [&] { return enqueue_post<D>(m, par, m->s); })))
       return rc;
-    if ((rc = capture(m, m->gr[2 + par], m->g_kry[par],
-                      [&] { return enqueue_krylov<D>(m, par, m->s, 0, m->chunk, true); })))
-      return rc;
+    for (int lev = 0; lev < m->nlev; ++lev)
+      if ((rc = capture(m, m->gr_kry[par][lev], m->g_kry[par][lev],
+                        [&] { return enqueue_krylov<D>(m, par, m->s, 0, m->chunk, true, lev); })))
+        return rc;
   }
   m->graphs_ready = true;
   return HSM_OK;
@@ -223,13 +235,21 @@ hsm_status do_pre(hsm_sim *m, int par) {
   if (m->prm.profile) HSM_HIP(hipEventRecord(m->ep_pre[par][1], m->s));
   return HSM_OK;
 }
+// The smallest captured grid level that covers `nact` blocks.
+int level_for(const hsm_sim *m, int64_t nact) {
+  int lev = 0;
+  while (lev + 1 < m->nlev && m->lev_grid[lev + 1] >= nact) ++lev;
+  return lev;
+}
 hsm_status do_krylov(hsm_sim *m, int slot) {
   hsm_status rc = HSM_OK;
+  const int lev = level_for(m, m->known_nact);
+  if (lev > 0) m->stats.krylov_reduced_batches += 1;
   if (m->prm.profile) HSM_HIP(hipEventRecord(m->ep_kry[slot][0], m->s));
   if (m->prm.launch_mode == 1)
-    rc = m->d == 2 ? enqueue_krylov<2>(m, slot, m->s, 0, m->chunk, true)
-                   : enqueue_krylov<3>(m, slot, m->s, 0, m->chunk, true);
-  else HSM_HIP(hipGraphLaunch(m->g_kry[slot], m->s));
+    rc = m->d == 2 ? enqueue_krylov<2>(m, slot, m->s, 0, m->chunk, true, lev)
+                   : enqueue_krylov<3>(m, slot, m->s, 0, m->chunk, true, lev);
+  else HSM_HIP(hipGraphLaunch(m->g_kry[slot][lev], m->s));
   if (rc) return rc;
   if (m->prm.profile) HSM_HIP(hipEventRecord(m->ep_kry[slot][1], m->s));
   return HSM_OK;
@@ -270,6 +290,7 @@ hsm_status run_steps(hsm_sim *m, int nsteps) {
   const int max_chunks = m->prm.krylov_maxiter / m->chunk + 2;
   for (int k = 0; k < nsteps; ++k) {
     const int par = m->parity;
+    m->known_nact = m->nblk;                                // a new solve runs every block
     if ((rc = do_pre(m, par))) return rc;
     if ((rc = do_krylov(m, 0))) return rc;
     HSM_HIP(hipEventRecord(m->ev_chunk[0], m->s));
@@ -281,6 +302,9 @@ hsm_status run_steps(hsm_sim *m, int nsteps) {
       HSM_HIP(hipEventRecord(m->ev_chunk[nxt], m->s));
       HSM_HIP(hipEventSynchronize(m->ev_chunk[c & 1]));
       f = m->hflags[c & 1];
+      // blocks of unfinished domains after this batch: the batches queued
+      // from here on run no more (the list only shrinks within a solve)
+      if (m->sepred && m->K > 1) m->known_nact = std::min<int64_t>(m->known_nact, f.nactive);
       if (m->prm.profile) {
         if (c == 0) {
           if ((rc = read_post(m))) return rc;
@@ -503,6 +527,17 @@ hsm_status hsm_sim_create(const hsm_stencils *st, const hsm_sim_params *prm, con
   // the XCD-contiguous order needs at least 8 ceil(nblk / 8) workgroups (one grid slot per list position)
   m->xcd = m->sepred && prm->xcd_order != 0;
   m->kry_grid = m->xcd ? (m->nblk + kXcds - 1) / kXcds * kXcds : m->nblk;
+  // grid levels of the Krylov batches: several domains only (their list of
+  // blocks shrinks as domains finish); each level holds at least 8 workgroups
+  // per XCD-order slot and at least 2048 workgroups
+  m->lev_grid[0] = m->kry_grid;
+  m->nlev = 1;
+  if (m->sepred && m->K > 1)
+    while (m->nlev < hsm_sim::kLevels && m->lev_grid[m->nlev - 1] / 2 >= 2048) {
+      m->lev_grid[m->nlev] = (m->lev_grid[m->nlev - 1] / 2 + kXcds - 1) / kXcds * kXcds;
+      ++m->nlev;
+    }
+  m->known_nact = m->nblk;
   if ((rc = m->active.alloc(sizeof(int32_t) * (m->nblk + 1)))) return rc;
   if ((rc = m->dom.alloc(sizeof(DomState) * m->K)) || (rc = m->dom_nodes.alloc(sizeof(int64_t) * m->K)) ||
       (rc = m->bscale.alloc(sizeof(double) * m->K)))

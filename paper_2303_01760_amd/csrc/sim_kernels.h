@@ -32,6 +32,8 @@ struct HostFlags {
   int32_t done, iters, fail, nonfinite;
   double relres;
   double node_mv;      // node rows through a pressure matrix-vector product so far this step (per-domain path)
+  int32_t nactive;     // blocks the Krylov kernels will run in the next batch (per-domain path)
+  int32_t pad;
 };
 
 // Krylov state.  Values a kernel computes for iteration k live in slot k & 1,
@@ -1098,6 +1100,7 @@ __global__ __launch_bounds__(kRedThreads) void k_chunk_end(SimArgs a) {
   h.nonfinite = sc->nonfinite;
   h.relres = sc->relres;
   h.node_mv = sc->node_mv;
+  h.nactive = sc->nactive;
 }
 
 // -------------------------------------------- projection + heat transport --

@@ -53,7 +53,7 @@ class SimStatsC(ctypes.Structure):
     _fields_ = [("steps", ctypes.c_int64), ("krylov_iters_total", ctypes.c_int64),
                 ("krylov_iters_last", ctypes.c_int32), ("status", ctypes.c_int32),
                 ("last_relres", ctypes.c_double), ("node_applies", ctypes.c_int64),
-                ("krylov_node_matvecs", ctypes.c_int64)]
+                ("krylov_node_matvecs", ctypes.c_int64), ("krylov_reduced_batches", ctypes.c_int64)]
 
 
 _lib = None
@@ -285,7 +285,7 @@ class Sim:
         rc = lib().hsm_sim_get_stats(self._h, ctypes.byref(o))
         d = dict(steps=o.steps, krylov_iters_total=o.krylov_iters_total, krylov_iters_last=o.krylov_iters_last,
                  status=o.status, last_relres=o.last_relres, node_applies=o.node_applies,
-                 krylov_node_matvecs=o.krylov_node_matvecs)
+                 krylov_node_matvecs=o.krylov_node_matvecs, krylov_reduced_batches=o.krylov_reduced_batches)
         if rc not in (OK, E_NONFINITE, E_NOT_CONVERGED):
             _check(rc)
         return d

@@ -298,6 +298,49 @@ def test_many_domains_steps_match_oracle(knobs):
         assert abs(pg[a:b].sum()) <= 1e-9 * np.abs(pg[a:b]).sum()
 
 
+@pytest.mark.parametrize("xcd_order", [0, 1])
+def test_shrinking_grid_batch_matches_domains_alone(xcd_order):
+    # 64 cavities (394k nodes, 6.2k blocks of 64 nodes): enough blocks for
+    # Krylov batches on reduced grids once the coarser domains stop.  Each
+    # domain stepped alone (the one-domain path, pinned to the oracle
+    # elsewhere) must give the batch's fields.
+    hsm = _hsm()
+    hs = [1 / 50, 1 / 70, 1 / 90, 1 / 110]
+    sets = [ng.cavity2d(h=hs[j % 4], seed=700 + j) for j in range(64)]
+    x = np.concatenate([q.x for q in sets], axis=1)
+    kind = np.concatenate([q.kind for q in sets])
+    nrm = np.concatenate([q.normal for q in sets], axis=1)
+    off = np.cumsum([0] + [q.n for q in sets]).astype(np.int64)
+    dom = np.repeat(np.arange(len(sets)), [q.n for q in sets])
+    tbc = np.concatenate([q.tbc for q in sets])
+    T0 = np.where(kind == 1, tbc, 0.5 + 0.2 * np.sin(4 * x[0] + dom) * np.cos(3 * x[1] - 0.5 * dom))
+    prm = dict(Ra=1e5, Pr=0.71, dt=0.1 * min(hs) ** 2 / 2, T_ref=0.5, krylov_tol=1e-11)
+    dev = torch.device("cuda")
+
+    def run(xs, ks, ns, hh, offs, T, **kw):
+        st = hsm.build_stencils(torch.tensor(xs, device=dev), torch.tensor(ks, device=dev),
+                                torch.tensor(ns, device=dev), hh, 2, domain_offsets=offs)
+        sim = hsm.Sim(st, torch.zeros((2, len(ks)), dtype=torch.float64, device=dev), torch.tensor(T, device=dev),
+                      block_nodes=64, **prm, **kw)
+        sim.step(3)
+        stats = sim.stats()
+        out = [a.cpu().numpy() for a in sim.read()]
+        sim.close()
+        st.close()
+        assert stats["status"] == 0, stats
+        return out, stats
+
+    (vg, Tg, pg), stats = run(x, kind, nrm, [q.h for q in sets], off, T0, xcd_order=xcd_order)
+    print(f"64 domains: krylov iters {stats['krylov_iters_total']}, reduced-grid batches "
+          f"{stats['krylov_reduced_batches']}")
+    assert stats["krylov_reduced_batches"] > 0
+    for j, q in enumerate(sets):
+        a, b = off[j], off[j + 1]
+        (v1, T1, p1), _ = run(q.x, q.kind, q.normal, q.h, None, T0[a:b])
+        ev, eT, ep = _rel(vg[:, a:b], v1), _rel(Tg[a:b], T1), _rel(pg[a:b], p1)
+        assert ev <= FIELD_TOL and eT <= FIELD_TOL and ep <= FIELD_TOL, (j, ev, eT, ep)
+
+
 def test_multi_domain_graph_replay_matches_direct_launches():
     hsm = _hsm()
     sets, x, kind, nrm, off, T0 = _three_domains()
