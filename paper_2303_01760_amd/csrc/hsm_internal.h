@@ -339,9 +339,15 @@ constexpr int chunk_of(int W, int K) {
 // the accumulation from being sunk to the end, and a scheduling barrier
 // keeps the next chunk's loads from being hoisted (either would hold every
 // chunk's values live at once).  idx: the bucket's [W][cnt] neighbour indices.
-template <int W, int K = 12, class FW, class FV, class FU, class FS>
+// hook(): called once, after the first chunk's neighbour loads are issued and
+// before any of them is consumed (work on values loaded before the gather,
+// done while the gather is in flight).
+struct NoHook {
+  __device__ __forceinline__ void operator()() const {}
+};
+template <int W, int K = 12, class FW, class FV, class FU, class FS, class FH = NoHook>
 __device__ __forceinline__ void gather_chunks(const void *idx, uint32_t cnt, uint32_t t, FW &&wload, FV &&vload,
-                                              FU &&use, FS &&settle) {
+                                              FU &&use, FS &&settle, FH &&hook = FH{}) {
   constexpr int C = chunk_of(W, K);
   // with two chunks, both chunks' indices in one round of loads: the second
   // chunk then waits for its values (and weights) only, not for its indices
@@ -364,6 +370,7 @@ __device__ __forceinline__ void gather_chunks(const void *idx, uint32_t cnt, uin
     for (int c = 0; c < C; ++c) wv[c] = wload(j0 + c);
 #pragma unroll
     for (int c = 0; c < C; ++c) vv[c] = vload(nb[(pre ? j0 : 0) + c]);
+    if (j0 == 0) hook();
 #pragma unroll
     for (int c = 0; c < C; ++c) use(j0 + c, wv[c], vv[c]);
     if (j0 + C < W) {

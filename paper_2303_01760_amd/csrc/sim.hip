@@ -75,6 +75,8 @@ struct hsm_sim {
   DBuf dom_nodes;                    // int64 [K] nodes per domain
   DBuf bscale;                       // double [K] border scale 1/sqrt(nodes) per domain
   DBuf active;                       // int32 [nblk] blocks of unfinished domains
+  DBuf lblk0, lblk1;                 // descriptors by list position: every block; the blocks of `active`
+  DBuf lpv, lst;                     // DomLaunch [K]: per-domain records of the Krylov node kernels
   int64_t kry_grid = 0;              // grid of the Krylov node kernels (every block descriptor)
   bool f32 = false;           // FP32 field form (HSM_F32_COMP)
   bool sepred = false;        // grid totals by a separate one-block kernel (large grids)
@@ -112,6 +114,10 @@ SimArgs make_args(hsm_sim *m, int par, int kpar) {
   a.dom_nodes = m->dom_nodes.as<int64_t>();
   a.bscale = m->bscale.as<double>();
   a.active = m->active.as<int32_t>();
+  a.lblk0 = m->lblk0.as<BlockDesc>();
+  a.lblk1 = m->lblk1.as<BlockDesc>();
+  a.lpv = m->lpv.as<DomLaunch>();
+  a.lst = m->lst.as<DomLaunch>();
   a.N = m->N;
   a.dt = m->prm.dt; a.Ra = m->prm.Ra; a.Pr = m->prm.Pr; a.T_ref = m->prm.T_ref; a.tol = m->prm.krylov_tol;
   a.maxiter = m->prm.krylov_maxiter;
@@ -150,6 +156,12 @@ hsm_status enqueue_pre(hsm_sim *m, int par, hipStream_t s) {
   return HSM_OK;
 }
 
+template <int D, int KP>
+void launch_pv(bool sep, dim3 g, dim3 b, hipStream_t s, const SimArgs &a, int it) {
+  if (sep) hipLaunchKernelGGL((k_bicg_pv<D, KP, true>), g, b, 0, s, a, it);
+  else hipLaunchKernelGGL((k_bicg_pv<D, KP, false>), g, b, 0, s, a, it);
+}
+
 // Krylov iterations [it0, it1) of a batch; the ping-pong parity follows the
 // iteration number, so a batch may be split across launch paths.
 template <int D>
@@ -158,19 +170,22 @@ hsm_status enqueue_krylov(hsm_sim *m, int slot, hipStream_t s, int it0, int it1,
   for (int it = it0; it < it1; ++it) {
     SimArgs a = make_args(m, 0, it & 1);
     switch (m->kp) {
-      case 4: hipLaunchKernelGGL((k_bicg_pv<D, 4>), g, b, 0, s, a, it); break;
-      case 6: hipLaunchKernelGGL((k_bicg_pv<D, 6>), g, b, 0, s, a, it); break;
-      case 12: hipLaunchKernelGGL((k_bicg_pv<D, 12>), g, b, 0, s, a, it); break;
-      default: hipLaunchKernelGGL((k_bicg_pv<D, 8>), g, b, 0, s, a, it); break;
+      case 4: launch_pv<D, 4>(m->sepred, g, b, s, a, it); break;
+      case 6: launch_pv<D, 6>(m->sepred, g, b, s, a, it); break;
+      case 12: launch_pv<D, 12>(m->sepred, g, b, s, a, it); break;
+      default: launch_pv<D, 8>(m->sepred, g, b, s, a, it); break;
     }
     if (m->sepred) hipLaunchKernelGGL(k_reduce_a, dim3((unsigned)red_grid(m->K)), dim3(kRedThreads), 0, s, a, it);
-    hipLaunchKernelGGL(k_bicg_st<D>, g, b, 0, s, a, it);
+    if (m->sepred) hipLaunchKernelGGL((k_bicg_st<D, true>), g, b, 0, s, a, it);
+    else hipLaunchKernelGGL((k_bicg_st<D, false>), g, b, 0, s, a, it);
     if (m->sepred) hipLaunchKernelGGL(k_reduce_b, dim3((unsigned)red_grid(m->K)), dim3(kRedThreads), 0, s, a, it);
   }
   HSM_HIP(hipGetLastError());
   if (flags) {
     SimArgs a = make_args(m, 0, 0);
     hipLaunchKernelGGL(k_chunk_end, dim3(1), dim3(kRedThreads), 0, s, a);
+    if (m->sepred && m->K > 1)
+      hipLaunchKernelGGL(k_list_desc, dim3((unsigned)((m->nblk + kBS - 1) / kBS)), dim3(kBS), 0, s, a);
     HSM_HIP(hipGetLastError());
     Scalars *sc = m->sc.as<Scalars>();
     HSM_HIP(hipMemcpyAsync(&m->hflags[slot], &sc->mirror, sizeof(HostFlags), hipMemcpyDeviceToHost, s));
@@ -507,6 +522,17 @@ hsm_status hsm_sim_create(const hsm_stencils *st, const hsm_sim_params *prm, con
       (rc = m->dom_blk.alloc(sizeof(int32_t) * (dbl.size() + 1))))
     return rc;
   HSM_HIP(hipMemcpyAsync(m->blk.p, blocks.data(), sizeof(BlockDesc) * blocks.size(), hipMemcpyHostToDevice, us));
+  // descriptors by list position (the Krylov kernels' workgroups): every
+  // block in per-domain order, and room for the list of unfinished domains'
+  // blocks (zeroed; rewritten before each use)
+  std::vector<BlockDesc> listed(dbl.size() + 8);
+  std::memset(listed.data(), 0, sizeof(BlockDesc) * listed.size());
+  for (size_t j2 = 0; j2 < dbl.size(); ++j2) listed[j2] = blocks[dbl[j2]];
+  if ((rc = m->lblk0.alloc(sizeof(BlockDesc) * listed.size())) ||
+      (rc = m->lblk1.alloc(sizeof(BlockDesc) * listed.size())))
+    return rc;
+  HSM_HIP(hipMemcpyAsync(m->lblk0.p, listed.data(), sizeof(BlockDesc) * listed.size(), hipMemcpyHostToDevice, us));
+  HSM_HIP(hipMemsetAsync(m->lblk1.p, 0, sizeof(BlockDesc) * listed.size(), us));
   HSM_HIP(hipMemcpyAsync(m->dom_blk_off.p, dbo.data(), sizeof(int32_t) * dbo.size(), hipMemcpyHostToDevice, us));
   HSM_HIP(hipMemcpyAsync(m->dom_blk.p, dbl.data(), sizeof(int32_t) * dbl.size(), hipMemcpyHostToDevice, us));
   HSM_HIP(hipStreamSynchronize(us));      // the host vectors above go out of scope
@@ -543,6 +569,9 @@ hsm_status hsm_sim_create(const hsm_stencils *st, const hsm_sim_params *prm, con
       (rc = m->bscale.alloc(sizeof(double) * m->K)))
     return rc;
   HSM_HIP(hipMemsetAsync(m->dom.p, 0, sizeof(DomState) * m->K, us));
+  if ((rc = m->lpv.alloc(sizeof(DomLaunch) * m->K)) || (rc = m->lst.alloc(sizeof(DomLaunch) * m->K))) return rc;
+  HSM_HIP(hipMemsetAsync(m->lpv.p, 0, sizeof(DomLaunch) * m->K, us));
+  HSM_HIP(hipMemsetAsync(m->lst.p, 0, sizeof(DomLaunch) * m->K, us));
   {
     // the zero-mean border of domain k holds c_k = 1/sqrt(N_k): the same
     // constraint as a border of ones, with the border's eigenvalue pair at

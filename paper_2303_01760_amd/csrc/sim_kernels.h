@@ -42,10 +42,12 @@ struct Scalars {
   double rho[2], alpha[2], omega[2], beta[2];
   double bnorm2, relres;
   double node_mv;      // per-domain path: node rows that went through a Krylov matvec this step
+  // the four values every Krylov block reads first, in one 16-byte load
   int32_t nactive;     // per-domain path: entries of SimArgs::active
-  int32_t list_sel;    // per-domain path: 0 = every block (SimArgs::dom_blk), 1 = SimArgs::active
-  int32_t done, fail, zero_sol, nonfinite;
-  int32_t it_base, iters, early[2];   // early: 1 = |s| converged, 2 = breakdown, 3 = zero right-hand side
+  int32_t list_sel;    // per-domain path: 0 = every block (SimArgs::lblk0), 1 = SimArgs::lblk1
+  int32_t done, it_base;
+  int32_t fail, zero_sol, nonfinite;
+  int32_t iters, early[2];   // early: 1 = |s| converged, 2 = breakdown, 3 = zero right-hand side
   HostFlags mirror;
 };
 
@@ -59,6 +61,19 @@ struct DomState {
   int32_t early[2];    // decided for the iteration of that parity: 1 = |s| converged, 2 = breakdown
   int32_t done, fail, iters, zero_sol;
 };
+
+// What a Krylov node kernel of the per-domain path needs of its block's
+// domain, written by the reduction kernel before it and read in one 64-byte
+// load.  For k_bicg_pv: c = (omega, beta, alpha of the previous iteration,
+// c_d times the border entry of p'); for k_bicg_st: c = (alpha, c_d times
+// the border entry of s).  done: nothing to do for the domain (finished, or
+// its right-hand side is zero); early: as DomState::early.
+struct alignas(64) DomLaunch {
+  double c[4];
+  int32_t done, early;
+  int32_t pad[6];
+};
+static_assert(sizeof(DomLaunch) == 64, "one 64-byte load per block");
 
 // One block of a stepper launch: up to kBS consecutive nodes of one width
 // bucket, all of one domain (so a block's partial sums are sums over part of
@@ -90,6 +105,14 @@ struct SimArgs {
   const int64_t *dom_nodes;        // [K] nodes per domain
   const double *bscale;            // [K] c_k = 1/sqrt(nodes of domain k): domain k's border row and column hold c_k
   int32_t *active;                 // [nblk] blocks of unfinished domains (per-domain path), rebuilt as domains finish
+  // The Krylov kernels' blocks by list position, descriptors in full: every
+  // block in dom_blk order, and the blocks of `active` (copied by
+  // k_list_desc after each rebuild).  A workgroup reads both descriptors of
+  // its position in the same round as the batch scalars, so the list choice
+  // costs no dependent load.  Both hold at least the Krylov grid's entries.
+  const BlockDesc *lblk0;
+  BlockDesc *lblk1;
+  DomLaunch *lpv, *lst;            // [K] per-domain records for k_bicg_pv and k_bicg_st
   double dt, Ra, Pr, T_ref, tol;
   int32_t maxiter, chunk;
   int32_t xcd_order;   // 1: the Krylov kernels hand each XCD one contiguous run of the block list (list_pos)
@@ -465,6 +488,12 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_r(SimArgs a) {
     ds.zero_sol = tot[0] == 0.0;
     ds.done = ds.zero_sol;
     ds.relres = ds.zero_sol ? 0.0 : sqrt(rr / tot[0]);
+    DomLaunch L{};
+    L.c[3] = cb * r;                            // p0 = r0 on the border row
+    L.done = ds.done;
+    a.lpv[d] = L;
+    L.c[3] = 0.0;
+    a.lst[d] = L;
     if (one) batch_add(f, ds);
   }
   if (one) batch_end(a, f);
@@ -529,6 +558,7 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_a(SimArgs a, int it) {
         ds.fail = 1;
         ds.iters = k;
       } else {
+        // (the launch records are written below, from the outcome)
         ds.mv += nodes;                         // k_bicg_pv's matvec on this domain
         double r, p;
         if (k == 0) {
@@ -552,7 +582,15 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_a(SimArgs a, int it) {
         else {
           ds.alpha[par] = rho / rv;
           ds.mv += nodes;                       // k_bicg_st's matvec follows
+          DomLaunch L{};
+          L.c[0] = ds.alpha[par];
+          L.c[1] = cb * fma(-ds.alpha[par], vb, r);   // c_d times the border entry of s = r - alpha v
+          a.lst[d] = L;
         }
+      }
+      if (ds.done) {                            // no more node work for this domain in this solve
+        a.lst[d].done = 1;
+        a.lpv[d].done = 1;
       }
     }
     if (one) batch_add(f, ds);
@@ -580,13 +618,14 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_b(SimArgs a, int it) {
     j1 = a.dom_blk_off[d + 1];
   }
   double alpha = 0.0, rho = 0.0, bnorm2 = 0.0, rhb = 0.0, cb = 0.0;
-  double2 rv = make_double2(0.0, 0.0);
+  double2 rv = make_double2(0.0, 0.0), pvb = rv;
   if (rs.lead) {
     const DomState &ds = a.dom[d];
     cb = a.bscale[d];
     alpha = ds.alpha[par]; rho = ds.rho[par]; bnorm2 = ds.bnorm2;
     rv = a.RV[N + d];
     rhb = a.rh[N + d];
+    pvb = a.PVn[N + d];                         // (p', v) of the border, stored by k_reduce_a
   }
   if (all_done) return;
   const bool live = has && !dd;
@@ -614,6 +653,14 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_b(SimArgs a, int it) {
   ds.omega[nx] = omega;
   ds.beta[nx] = beta;
   ds.rho[nx] = rho_n;
+  // the next k_bicg_pv's record (its border entry of p', as k_reduce_a will store it)
+  DomLaunch L{};
+  L.c[0] = omega;
+  L.c[1] = beta;
+  L.c[2] = alpha;
+  L.c[3] = cb * fma(beta, fma(-omega, pvb.y, pvb.x), fma(-omega, tb, sb));
+  L.early = e;
+  a.lpv[d] = L;
 }
 
 // ------------------------------------------------------------- predictor --
@@ -802,39 +849,50 @@ __global__ __launch_bounds__(kBS) void k_rhs(SimArgs a) {
 // Vectors gathered together are stored as pairs, one 16-byte load per
 // neighbour: (s, t), (p, v) (two generations) and (r, v).  The border row
 // and column (zero mean, multiplier) are slot N of every vector.
-// The node rows of one block of k_bicg_pv (cpN: c_d times the border entry of p').
+// The node rows of one block of k_bicg_pv (cpN: c_d times the border entry of
+// p').  The node's own values are loaded first and used only once the
+// neighbour loads are in flight (the gather's hook), so the block's loads go
+// out in one round, and the stores come last.
 template <int D, int KP>
 __device__ __forceinline__ void pv_rows(const SimArgs &a, const BlockDesc &b, bool again, bool first,
                                         int early, double omega, double beta, double alpha_p, double cpN) {
   const int64_t N = a.N;
   const double2 *__restrict__ ST = a.ST;
   const double2 *__restrict__ PVo = a.PVo;
+  const double2 *__restrict__ RV = a.RV;
   const int64_t t = b.first + (int64_t)threadIdx.x;
   const bool live = (int)threadIdx.x < b.nodes;
+  const int64_t i = b.bstart + t;
   if (early == 1) {                             // |s| converged: x += alpha p, nothing else
-    if (live) {
-      const int64_t i = b.bstart + t;
-      a.x[i] = fma(alpha_p, PVo[i].x, a.x[i]);
-    }
+    if (live) a.x[i] = fma(alpha_p, PVo[i].x, a.x[i]);
     return;
   }
-  double part[kNA] = {0.0, 0.0, 0.0};           // (rh, v), sum p, |r|^2
+  double2 sti = make_double2(0.0, 0.0), pvi = sti;
+  double xi = 0.0, rhi = 0.0;
   if (live) {
-    const int64_t i = b.bstart + t;
-    const uint32_t cnt32 = (uint32_t)b.count, t32 = (uint32_t)t;
-    const Buf RVb = plane(a.RV, N + 1, 0), STb = plane(ST, N + 1, 0), PVb = plane(PVo, N + 1, 0);
-    const double2 *__restrict__ RV = a.RV;
-    double ri, pi;
     if (first) {
-      ri = RV[i].x;
+      sti = RV[i];                              // (r0, .)
+    } else {
+      sti = ST[i];
+      pvi = PVo[i];
+      xi = a.x[i];
+    }
+    rhi = a.rh[i];
+  }
+  double ri = 0.0, pi = 0.0, xn = 0.0, acc = 0.0;
+  const auto own = [&]() __attribute__((always_inline)) {
+    if (first) {
+      ri = sti.x;
       pi = ri;
     } else {
-      const double2 st = ST[i], pv = PVo[i];
-      a.x[i] = fma(omega, st.x, fma(alpha_p, pv.x, a.x[i]));
-      ri = fma(-omega, st.y, st.x);
-      pi = fma(beta, fma(-omega, pv.y, pv.x), ri);
+      xn = fma(omega, sti.x, fma(alpha_p, pvi.x, xi));
+      ri = fma(-omega, sti.y, sti.x);
+      pi = fma(beta, fma(-omega, pvi.y, pvi.x), ri);
     }
-    double acc = 0.0;
+  };
+  if (live) {
+    const uint32_t cnt32 = (uint32_t)b.count, t32 = (uint32_t)t;
+    const Buf RVb = plane(RV, N + 1, 0), STb = plane(ST, N + 1, 0), PVb = plane(PVo, N + 1, 0);
     with_width<D>(b.width, [&](auto wc) __attribute__((always_inline)) {
       constexpr int W = decltype(wc)::value;
       with_rows<D, W>(b, [&](auto sh) __attribute__((always_inline)) {
@@ -844,7 +902,7 @@ __device__ __forceinline__ void pv_rows(const SimArgs &a, const BlockDesc &b, bo
         gather_chunks<W>(
             b.idx, cnt32, t32, wl, [&](int32_t nb) __attribute__((always_inline)) { return ld_at<double>(RVb, 2 * nb); },
             [&](int, double wj, double rj) __attribute__((always_inline)) { acc = fma(wj, rj, acc); },
-            [&]() __attribute__((always_inline)) { pin(acc); });
+            [&]() __attribute__((always_inline)) { pin(acc); }, own);
       } else {
         gather_chunks<W, KP>(
             b.idx, cnt32, t32, wl,
@@ -855,62 +913,81 @@ __device__ __forceinline__ void pv_rows(const SimArgs &a, const BlockDesc &b, bo
               const double pj = fma(beta, fma(-omega, g.v[1].y, g.v[1].x), fma(-omega, g.v[0].y, g.v[0].x));
               acc = fma(wj, pj, acc);
             },
-            [&]() __attribute__((always_inline)) { pin(acc); });
+            [&]() __attribute__((always_inline)) { pin(acc); }, own);
       }
       });
     });
+  }
+  double part[kNA] = {0.0, 0.0, 0.0};           // (rh, v), sum p, |r|^2
+  if (live) {
+    if (!first) a.x[i] = xn;
     const double vi = acc + cpN;                // + c_d times the border entry of p'
     a.PVn[i] = make_double2(pi, vi);
     a.RV[i] = make_double2(ri, vi);
-    part[0] = a.rh[i] * vi;
+    part[0] = rhi * vi;
     part[1] = pi;
     part[2] = ri * ri;
   }
   block_partials<kNA>(part, a.partA, b.prow, again);
 }
 
+// The descriptor of list position w's block: the Krylov kernels of the
+// per-domain path give each workgroup one position (directly, or in the
+// XCD-contiguous order, which needs the list length first).  Returns false
+// for a position past the list.
+__device__ __forceinline__ bool listed_block(const SimArgs &a, int64_t w, int nact, int lsel, BlockDesc &b) {
+  // both descriptors of position w, loaded with the batch scalars (no branch
+  // before them, so no dependent round); w is below both arrays' length
+  const BlockDesc b0 = a.lblk0[w], b1 = a.lblk1[w];
+  b = lsel ? b1 : b0;
+  if (!a.xcd_order) return w < nact;
+  const int64_t v = list_pos(w, nact, 1);
+  if (v >= nact) return false;
+  b = lsel ? a.lblk1[v] : a.lblk0[v];
+  return true;
+}
+
+// A domain's launch record as one 16-dword load (its fields are then in the
+// same round of loads, whichever of them a test uses first).
+__device__ __forceinline__ DomLaunch load_launch(const DomLaunch *p) {
+  typedef int32_t v16 __attribute__((ext_vector_type(16)));
+  const v16 v = *reinterpret_cast<const v16 *>(p);
+  DomLaunch L;
+  __builtin_memcpy(&L, &v, sizeof(L));
+  return L;
+}
+
 // KP: entries per gather chunk (a tuning parameter: more loads in flight
-// against more registers held).
-template <int D, int KP>
+// against more registers held).  SEP: the reduction-kernel path (a.sepred),
+// a template parameter so that no branch on it separates the first round of
+// loads.
+template <int D, int KP, bool SEP>
 __global__ __launch_bounds__(kBS) void k_bicg_pv(SimArgs a, int it) {
   Scalars *sc = a.sc;
   const int par = it & 1;
   // independent loads first (one wait), then the early exit
   const int done = sc->done, it_base = sc->it_base, nact = sc->nactive, lsel = sc->list_sel;
   const double bnorm2 = sc->bnorm2, alpha_prev = sc->alpha[par ^ 1], rho_prev = sc->rho[par ^ 1];
-  if (done) return;
   const int64_t N = a.N;
   const int k = it_base + it;
   const bool first = (k == 0);
   const double2 *__restrict__ ST = a.ST;
   const double2 *__restrict__ PVo = a.PVo;
-  if (a.sepred) {
+  if constexpr (SEP) {
     // the listed blocks (every block, or those of domains unfinished at the
-    // last batch end) of unfinished domains; each domain's scalars were
-    // decided by k_reduce_b (or k_reduce_r)
-    const int32_t *lst = lsel ? a.active : a.dom_blk;
-    // the grid holds a workgroup for every block, so each takes at most one list position
-    const int64_t v = list_pos(blockIdx.x, nact, a.xcd_order);
-    if (v < nact) {
-      const int32_t bi = a.K == 1 ? (int32_t)v : lst[v];   // one domain: every block, in order
-      const BlockDesc b = a.blk[bi];
-      const DomState &ds = a.dom[b.domain];
-      const int64_t NB = N + b.domain;
-      if (ds.done) return;
-      if (first) {
-        pv_rows<D, KP>(a, b, true, true, 0, 0.0, 0.0, 0.0, a.bscale[b.domain] * a.RV[NB].x);   // p0 = r0 on the border row
-      } else {
-        const int early = ds.early[par];
-        if (early == 2) return;
-        const double omega = ds.omega[par], beta = ds.beta[par];
-        const double2 stb = ST[NB], pvb = PVo[NB];  // the border row, as k_reduce_a will store it
-        const double pN = fma(beta, fma(-omega, pvb.y, pvb.x), fma(-omega, stb.y, stb.x));
-        pv_rows<D, KP>(a, b, true, false, early, omega, beta, ds.alpha[par ^ 1], a.bscale[b.domain] * pN);
-      }
-    }
+    // last batch end); each domain's scalars were decided by k_reduce_b (or
+    // k_reduce_r)
+    BlockDesc b;
+    const bool in = listed_block(a, blockIdx.x, nact, lsel, b);
+    if (done || !in) return;
+    // the domain's record (decided by k_reduce_b, or k_reduce_r for the first iteration)
+    const DomLaunch L = load_launch(a.lpv + b.domain);
+    if (L.done || (!first && L.early == 2)) return;
+    pv_rows<D, KP>(a, b, true, first, first ? 0 : L.early, L.c[0], L.c[1], L.c[2], L.c[3]);
     return;
   }
   // one domain, small grid: every block reduces the partials and takes the same decisions
+  if (done) return;
   const BlockDesc b = a.blk[blockIdx.x];
   double omega = 0.0, beta = 0.0, alpha_p = 0.0, pN;
   int early = 0;
@@ -970,20 +1047,26 @@ __global__ __launch_bounds__(kBS) void k_bicg_pv(SimArgs a, int it) {
   pv_rows<D, KP>(a, b, false, first, early, omega, beta, alpha_p, a.bscale[0] * pN);
 }
 
-// The node rows of one block of k_bicg_st (csN: c_d times the border entry of s).
+// The node rows of one block of k_bicg_st (csN: c_d times the border entry of
+// s).  As in k_bicg_pv: own values first, used in the gather's hook.
 template <int D>
 __device__ __forceinline__ void st_rows(const SimArgs &a, const BlockDesc &b, bool again, double alpha,
                                         double csN) {
   const int64_t N = a.N;
   const int64_t t = b.first + (int64_t)threadIdx.x;
   const bool live = (int)threadIdx.x < b.nodes;
-  double part[kNB] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};   // (t,s), (t,t), (rh,s), (rh,t), (s,s), sum s
+  const int64_t i = b.bstart + t;
+  const double2 *__restrict__ RV = a.RV;
+  double2 rvi = make_double2(0.0, 0.0);
+  double rhi = 0.0, si = 0.0, acc = 0.0;
   if (live) {
-    const int64_t i = b.bstart + t;
+    rvi = RV[i];
+    rhi = a.rh[i];
+  }
+  const auto own = [&]() __attribute__((always_inline)) { si = fma(-alpha, rvi.y, rvi.x); };
+  if (live) {
     const uint32_t cnt32 = (uint32_t)b.count, t32 = (uint32_t)t;
-    const Buf RVb = plane(a.RV, N + 1, 0);
-    const double2 *__restrict__ RV = a.RV;
-    double acc = 0.0;
+    const Buf RVb = plane(RV, N + 1, 0);
     with_width<D>(b.width, [&](auto wc) __attribute__((always_inline)) {
       constexpr int W = decltype(wc)::value;
       with_rows<D, W>(b, [&](auto sh) __attribute__((always_inline)) {
@@ -994,13 +1077,13 @@ __device__ __forceinline__ void st_rows(const SimArgs &a, const BlockDesc &b, bo
           [&](int, double wj, const double2 &rv2) __attribute__((always_inline)) {
             acc = fma(wj, fma(-alpha, rv2.y, rv2.x), acc);
           },
-          [&]() __attribute__((always_inline)) { pin(acc); });
+          [&]() __attribute__((always_inline)) { pin(acc); }, own);
       });
     });
-    const double2 rvi = RV[i];
-    const double si = fma(-alpha, rvi.y, rvi.x);
+  }
+  double part[kNB] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};   // (t,s), (t,t), (rh,s), (rh,t), (s,s), sum s
+  if (live) {
     const double ti = acc + csN;                // + c_d times the border entry of s
-    const double rhi = a.rh[i];
     a.ST[i] = make_double2(si, ti);
     part[0] = ti * si;
     part[1] = ti * ti;
@@ -1012,30 +1095,26 @@ __device__ __forceinline__ void st_rows(const SimArgs &a, const BlockDesc &b, bo
   block_partials<kNB>(part, a.partB, b.prow, again);
 }
 
-template <int D>
+template <int D, bool SEP>
 __global__ __launch_bounds__(kBS) void k_bicg_st(SimArgs a, int it) {
   Scalars *sc = a.sc;
   const int par = it & 1;
   const int done = sc->done, it_base = sc->it_base, early = sc->early[par], nact = sc->nactive, lsel = sc->list_sel;
   const double bnorm2 = sc->bnorm2, rho_k = sc->rho[par];
-  if (done) return;
   const int64_t N = a.N;
   const int k = it_base + it;
-  if (a.sepred) {
-    // the listed blocks of unfinished domains; alpha was decided by k_reduce_a
-    const int32_t *lst = lsel ? a.active : a.dom_blk;
-    const int64_t v = list_pos(blockIdx.x, nact, a.xcd_order);
-    if (v < nact) {
-      const int32_t bi = a.K == 1 ? (int32_t)v : lst[v];
-      const BlockDesc b = a.blk[bi];
-      const DomState &ds = a.dom[b.domain];
-      if (ds.done) return;
-      const double alpha = ds.alpha[par];
-      const double2 rvb = a.RV[N + b.domain];   // the border row, as k_reduce_b will store it
-      st_rows<D>(a, b, true, alpha, a.bscale[b.domain] * fma(-alpha, rvb.y, rvb.x));
-    }
+  if constexpr (SEP) {
+    // the listed blocks of domains unfinished at the last batch end; alpha
+    // was decided by k_reduce_a
+    BlockDesc b;
+    const bool in = listed_block(a, blockIdx.x, nact, lsel, b);
+    if (done || !in) return;
+    const DomLaunch L = load_launch(a.lst + b.domain);   // decided by k_reduce_a
+    if (L.done) return;
+    st_rows<D>(a, b, true, L.c[0], L.c[1]);
     return;
   }
+  if (done) return;
   const BlockDesc b = a.blk[blockIdx.x];
   if (early) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -1101,6 +1180,15 @@ __global__ __launch_bounds__(kRedThreads) void k_chunk_end(SimArgs a) {
   h.relres = sc->relres;
   h.node_mv = sc->node_mv;
   h.nactive = sc->nactive;
+}
+
+// After k_chunk_end rebuilt the list of unfinished domains' blocks: their
+// descriptors in list order, one thread per position.
+__global__ __launch_bounds__(kBS) void k_list_desc(SimArgs a) {
+  const Scalars *sc = a.sc;
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (sc->done || !sc->list_sel || v >= sc->nactive) return;
+  a.lblk1[v] = a.blk[a.active[v]];
 }
 
 // -------------------------------------------- projection + heat transport --
