@@ -241,6 +241,9 @@ typedef struct {
   int32_t lattice_rows;    /* 0: a regular bucket whose pressure rows all equal the lattice row (1 at the
                               centre, -1/(2d) on the cross) to 1e-12 stores that one row, read by every node;
                               1: every node keeps its own row (as built) */
+  int32_t wide_lanes;      /* threads per node of the Krylov kernels for the non-regular widths: 0 (auto:
+                              several, 2..16 so that each takes at most 8 stencil entries, when such nodes are
+                              fewer than half of all nodes; else one), 1: one thread per node, 2: several */
 } hsm_sim_params;
 
 typedef struct {

@@ -6,7 +6,10 @@ of floating-point sums; the weights do not change at all):
   build:  tile_log2     tile edge (2^L search cells per axis) of the internal
                         node order inside each width bucket;
           solve_groups  RBF-FD local systems per wave64 (1, 2, 3 where they fit);
-  Krylov: xcd_order     each XCD takes one contiguous run of the Krylov kernels'
+  Krylov: wide_lanes    one or several threads per node of the non-regular
+                        (wide) stencils in the Krylov kernels (or the
+                        library's automatic choice);
+          xcd_order     each XCD takes one contiguous run of the Krylov kernels'
                         blocks (where the reduction kernels run), or
                         consecutive blocks go to consecutive XCDs;
           block_nodes   nodes (threads) per block of the node kernels;
@@ -44,7 +47,9 @@ import torch
 
 from . import hsm
 
-DEFAULTS = dict(tile_log2=0, solve_groups=0, block_nodes=256, gather_chunk=8, krylov_chunk=32, xcd_order=0)
+DEFAULTS = dict(tile_log2=0, solve_groups=0, block_nodes=256, gather_chunk=8, krylov_chunk=32, xcd_order=0,
+                wide_lanes=0)
+LANE_CANDIDATES = (0, 1, 2)
 TILE_CANDIDATES = {2: (2, 3, 4), 3: (1, 2, 3)}
 DEFAULT_TILE = {2: 3, 3: 2}
 BLOCK_CANDIDATES = (128, 256, 64)
@@ -104,7 +109,7 @@ def _krylov_ns_per_row(st, sim_kw, knobs, steps) -> float:
                   T_ref=sim_kw["T_ref"], krylov_tol=sim_kw["tol"], krylov_maxiter=sim_kw.get("maxiter", 200000),
                   field_dtype=sim_kw.get("field_dtype", hsm.F64), profile=1, block_nodes=knobs["block_nodes"],
                   gather_chunk=knobs["gather_chunk"], krylov_chunk=knobs["krylov_chunk"],
-                  xcd_order=knobs["xcd_order"])
+                  xcd_order=knobs["xcd_order"], wide_lanes=knobs["wide_lanes"])
     try:
         sim.step(steps)
         ms, n = sim.phase_times()["krylov_batch"]
@@ -168,6 +173,7 @@ def tune(x: torch.Tensor, kind: torch.Tensor, normal: torch.Tensor, h, m, sim_kw
         finally:
             st.close()
 
+    pick("wide_lanes", LANE_CANDIDATES, kry)
     pick("tile_log2", TILE_CANDIDATES[d], kry)
     pick("xcd_order", (0, 1), kry)
     pick("block_nodes", BLOCK_CANDIDATES, kry)

@@ -76,6 +76,9 @@ struct hsm_sim {
   DBuf bscale;                       // double [K] border scale 1/sqrt(nodes) per domain
   DBuf active;                       // int32 [nblk] blocks of unfinished domains
   DBuf lblk0, lblk1;                 // descriptors by list position: every block; the blocks of `active`
+  DBuf kblk, kdom_blk_off, kdom_blk; // the Krylov node kernels' partition (bs / lanes nodes a block)
+  int64_t nkblk = 0;
+  bool lanes = false;                // several threads per node of a non-regular width (lanes_for)
   DBuf lpv, lst;                     // DomLaunch [K]: per-domain records of the Krylov node kernels
   int64_t kry_grid = 0;              // grid of the Krylov node kernels (every block descriptor)
   bool f32 = false;           // FP32 field form (HSM_F32_COMP)
@@ -117,6 +120,10 @@ SimArgs make_args(hsm_sim *m, int par, int kpar) {
   a.lblk0 = m->lblk0.as<BlockDesc>();
   a.lblk1 = m->lblk1.as<BlockDesc>();
   a.lpv = m->lpv.as<DomLaunch>();
+  a.kblk = m->kblk.as<BlockDesc>();
+  a.nkblk = m->nkblk;
+  a.kdom_blk_off = m->kdom_blk_off.as<int32_t>();
+  a.kdom_blk = m->kdom_blk.as<int32_t>();
   a.lst = m->lst.as<DomLaunch>();
   a.N = m->N;
   a.dt = m->prm.dt; a.Ra = m->prm.Ra; a.Pr = m->prm.Pr; a.T_ref = m->prm.T_ref; a.tol = m->prm.krylov_tol;
@@ -156,10 +163,15 @@ hsm_status enqueue_pre(hsm_sim *m, int par, hipStream_t s) {
   return HSM_OK;
 }
 
-template <int D, int KP>
+template <int D, int KP, bool LN>
 void launch_pv(bool sep, dim3 g, dim3 b, hipStream_t s, const SimArgs &a, int it) {
-  if (sep) hipLaunchKernelGGL((k_bicg_pv<D, KP, true>), g, b, 0, s, a, it);
-  else hipLaunchKernelGGL((k_bicg_pv<D, KP, false>), g, b, 0, s, a, it);
+  if (sep) hipLaunchKernelGGL((k_bicg_pv<D, KP, true, LN>), g, b, 0, s, a, it);
+  else hipLaunchKernelGGL((k_bicg_pv<D, KP, false, LN>), g, b, 0, s, a, it);
+}
+template <int D, bool LN>
+void launch_st(bool sep, dim3 g, dim3 b, hipStream_t s, const SimArgs &a, int it) {
+  if (sep) hipLaunchKernelGGL((k_bicg_st<D, true, LN>), g, b, 0, s, a, it);
+  else hipLaunchKernelGGL((k_bicg_st<D, false, LN>), g, b, 0, s, a, it);
 }
 
 // Krylov iterations [it0, it1) of a batch; the ping-pong parity follows the
@@ -170,14 +182,14 @@ hsm_status enqueue_krylov(hsm_sim *m, int slot, hipStream_t s, int it0, int it1,
   for (int it = it0; it < it1; ++it) {
     SimArgs a = make_args(m, 0, it & 1);
     switch (m->kp) {
-      case 4: launch_pv<D, 4>(m->sepred, g, b, s, a, it); break;
-      case 6: launch_pv<D, 6>(m->sepred, g, b, s, a, it); break;
-      case 12: launch_pv<D, 12>(m->sepred, g, b, s, a, it); break;
-      default: launch_pv<D, 8>(m->sepred, g, b, s, a, it); break;
+      case 4: m->lanes ? launch_pv<D, 4, true>(m->sepred, g, b, s, a, it) : launch_pv<D, 4, false>(m->sepred, g, b, s, a, it); break;
+      case 6: m->lanes ? launch_pv<D, 6, true>(m->sepred, g, b, s, a, it) : launch_pv<D, 6, false>(m->sepred, g, b, s, a, it); break;
+      case 12: m->lanes ? launch_pv<D, 12, true>(m->sepred, g, b, s, a, it) : launch_pv<D, 12, false>(m->sepred, g, b, s, a, it); break;
+      default: m->lanes ? launch_pv<D, 8, true>(m->sepred, g, b, s, a, it) : launch_pv<D, 8, false>(m->sepred, g, b, s, a, it); break;
     }
     if (m->sepred) hipLaunchKernelGGL(k_reduce_a, dim3((unsigned)red_grid(m->K)), dim3(kRedThreads), 0, s, a, it);
-    if (m->sepred) hipLaunchKernelGGL((k_bicg_st<D, true>), g, b, 0, s, a, it);
-    else hipLaunchKernelGGL((k_bicg_st<D, false>), g, b, 0, s, a, it);
+    if (m->lanes) launch_st<D, true>(m->sepred, g, b, s, a, it);
+    else launch_st<D, false>(m->sepred, g, b, s, a, it);
     if (m->sepred) hipLaunchKernelGGL(k_reduce_b, dim3((unsigned)red_grid(m->K)), dim3(kRedThreads), 0, s, a, it);
   }
   HSM_HIP(hipGetLastError());
@@ -185,7 +197,7 @@ hsm_status enqueue_krylov(hsm_sim *m, int slot, hipStream_t s, int it0, int it1,
     SimArgs a = make_args(m, 0, 0);
     hipLaunchKernelGGL(k_chunk_end, dim3(1), dim3(kRedThreads), 0, s, a);
     if (m->sepred && m->K > 1)
-      hipLaunchKernelGGL(k_list_desc, dim3((unsigned)((m->nblk + kBS - 1) / kBS)), dim3(kBS), 0, s, a);
+      hipLaunchKernelGGL(k_list_desc, dim3((unsigned)((m->nkblk + kBS - 1) / kBS)), dim3(kBS), 0, s, a);
     HSM_HIP(hipGetLastError());
     Scalars *sc = m->sc.as<Scalars>();
     HSM_HIP(hipMemcpyAsync(&m->hflags[slot], &sc->mirror, sizeof(HostFlags), hipMemcpyDeviceToHost, s));
@@ -305,7 +317,7 @@ hsm_status run_steps(hsm_sim *m, int nsteps) {
   const int max_chunks = m->prm.krylov_maxiter / m->chunk + 2;
   for (int k = 0; k < nsteps; ++k) {
     const int par = m->parity;
-    m->known_nact = m->nblk;                                // a new solve runs every block
+    m->known_nact = m->nkblk;                               // a new solve runs every block
     if ((rc = do_pre(m, par))) return rc;
     if ((rc = do_krylov(m, 0))) return rc;
     HSM_HIP(hipEventRecord(m->ev_chunk[0], m->s));
@@ -402,6 +414,10 @@ hsm_status hsm_sim_create(const hsm_stencils *st, const hsm_sim_params *prm, con
     set_error(HSM_E_INVALID, "lattice_rows must be 0 or 1");
     return HSM_E_INVALID;
   }
+  if (prm->wide_lanes < 0 || prm->wide_lanes > 2) {
+    set_error(HSM_E_INVALID, "wide_lanes must be 0 (auto), 1 or 2");
+    return HSM_E_INVALID;
+  }
   if (prm->xcd_order != 0 && prm->xcd_order != 1) {
     set_error(HSM_E_INVALID, "xcd_order must be 0 or 1");
     return HSM_E_INVALID;
@@ -484,57 +500,90 @@ hsm_status hsm_sim_create(const hsm_stencils *st, const hsm_sim_params *prm, con
       dom_int[i] = (int32_t)(std::upper_bound(st->dom_off.begin(), st->dom_off.end(), (int64_t)hperm[i]) -
                              st->dom_off.begin() - 1);
   }
-  std::vector<BlockDesc> blocks;
-  for (size_t kb = 0; kb < st->buckets.size(); ++kb) {
-    const Bucket &B = st->buckets[kb];
-    for (int64_t j = 0; j < B.count;) {
-      const int32_t dom = m->K > 1 ? dom_int[B.start + j] : 0;
-      int64_t e = j + 1;
-      while (e < B.count && e - j < m->bs && (m->K == 1 || dom_int[B.start + e] == dom)) ++e;
-      BlockDesc bd;
-      std::memset(&bd, 0, sizeof(bd));
-      bd.idx = B.idx.p;
-      bd.w = m->f32 ? B.w32.p : B.w.p;             // field weights in the field storage type
-      bd.wP = wp_of[kb];
-      bd.wshared = shared_of[kb];
-      bd.bstart = B.start;
-      bd.first = (int32_t)j;
-      bd.nodes = (int32_t)(e - j);
-      bd.count = (int32_t)B.count;
-      bd.type = B.type;
-      bd.width = B.width;
-      bd.domain = dom;
-      blocks.push_back(bd);
-      j = e;
+  // a partition of the nodes into blocks of up to `per(width)` consecutive
+  // nodes of one bucket and one domain, with the per-domain block lists (the
+  // reduction kernels' rows: prow is a block's place in them)
+  struct Partition {
+    std::vector<BlockDesc> blocks;
+    std::vector<int32_t> dbo, dbl;
+  };
+  const auto partition = [&](auto per) {
+    Partition P;
+    for (size_t kb = 0; kb < st->buckets.size(); ++kb) {
+      const Bucket &B = st->buckets[kb];
+      const int64_t cap = per(B.width);
+      for (int64_t j = 0; j < B.count;) {
+        const int32_t dom = m->K > 1 ? dom_int[B.start + j] : 0;
+        int64_t e = j + 1;
+        while (e < B.count && e - j < cap && (m->K == 1 || dom_int[B.start + e] == dom)) ++e;
+        BlockDesc bd;
+        std::memset(&bd, 0, sizeof(bd));
+        bd.idx = B.idx.p;
+        bd.w = m->f32 ? B.w32.p : B.w.p;         // field weights in the field storage type
+        bd.wP = wp_of[kb];
+        bd.wshared = shared_of[kb];
+        bd.bstart = B.start;
+        bd.first = (int32_t)j;
+        bd.nodes = (int32_t)(e - j);
+        bd.count = (int32_t)B.count;
+        bd.type = B.type;
+        bd.width = B.width;
+        bd.domain = dom;
+        P.blocks.push_back(bd);
+        j = e;
+      }
     }
+    P.dbo.assign(m->K + 1, 0);
+    P.dbl.resize(P.blocks.size());
+    for (const BlockDesc &bd : P.blocks) P.dbo[bd.domain + 1] += 1;
+    for (int32_t d2 = 0; d2 < m->K; ++d2) P.dbo[d2 + 1] += P.dbo[d2];
+    std::vector<int32_t> fill(P.dbo.begin(), P.dbo.end() - 1);
+    for (size_t b2 = 0; b2 < P.blocks.size(); ++b2) P.dbl[fill[P.blocks[b2].domain]++] = (int32_t)b2;
+    for (size_t j2 = 0; j2 < P.dbl.size(); ++j2) P.blocks[P.dbl[j2]].prow = (int32_t)j2;   // one domain: prow = block
+    return P;
+  };
+  const auto upload = [&](const Partition &P, DBuf &blk, DBuf &off, DBuf &lst) -> hsm_status {
+    hsm_status r;
+    if ((r = blk.alloc(sizeof(BlockDesc) * (P.blocks.size() + 1))) || (r = off.alloc(sizeof(int32_t) * P.dbo.size())) ||
+        (r = lst.alloc(sizeof(int32_t) * (P.dbl.size() + 1))))
+      return r;
+    HSM_HIP(hipMemcpyAsync(blk.p, P.blocks.data(), sizeof(BlockDesc) * P.blocks.size(), hipMemcpyHostToDevice, us));
+    HSM_HIP(hipMemcpyAsync(off.p, P.dbo.data(), sizeof(int32_t) * P.dbo.size(), hipMemcpyHostToDevice, us));
+    HSM_HIP(hipMemcpyAsync(lst.p, P.dbl.data(), sizeof(int32_t) * P.dbl.size(), hipMemcpyHostToDevice, us));
+    return HSM_OK;
+  };
+  // every node kernel but the Krylov ones: one node per thread
+  const Partition base = partition([&](int) { return (int64_t)m->bs; });
+  // the Krylov node kernels: lanes_for(width) threads per node, or one.
+  // Several lanes shorten a wide stencil's chain of gather rounds; where most
+  // nodes are wide, their redundant own loads and extra blocks cost more
+  // (measured: 9 % faster Krylov batches on the 512 hybrid domains, 21 % and
+  // 37 % slower in the all-scattered 2D and 3D layouts)
+  if (prm->wide_lanes == 0) {
+    int64_t wide = 0;
+    for (const Bucket &B : st->buckets)
+      if (lanes_for(B.width, st->d) > 1) wide += B.count;
+    m->lanes = 2 * wide < N;
+  } else {
+    m->lanes = prm->wide_lanes == 2;
   }
-  m->nblk = (int64_t)blocks.size();
-  std::vector<int32_t> dbo(m->K + 1, 0), dbl(blocks.size());
-  for (const BlockDesc &bd : blocks) dbo[bd.domain + 1] += 1;
-  for (int32_t d2 = 0; d2 < m->K; ++d2) dbo[d2 + 1] += dbo[d2];
-  {
-    std::vector<int32_t> fill(dbo.begin(), dbo.end() - 1);
-    for (size_t b2 = 0; b2 < blocks.size(); ++b2) dbl[fill[blocks[b2].domain]++] = (int32_t)b2;
-  }
-  for (size_t j2 = 0; j2 < dbl.size(); ++j2) blocks[dbl[j2]].prow = (int32_t)j2;   // one domain: prow = block index
-  if ((rc = m->blk.alloc(sizeof(BlockDesc) * (blocks.size() + 1))) ||
-      (rc = m->dom_blk_off.alloc(sizeof(int32_t) * dbo.size())) ||
-      (rc = m->dom_blk.alloc(sizeof(int32_t) * (dbl.size() + 1))))
+  const Partition kry = partition([&](int w) { return (int64_t)(m->bs / (m->lanes ? lanes_for(w, st->d) : 1)); });
+  m->nblk = (int64_t)base.blocks.size();
+  m->nkblk = (int64_t)kry.blocks.size();
+  if ((rc = upload(base, m->blk, m->dom_blk_off, m->dom_blk)) ||
+      (rc = upload(kry, m->kblk, m->kdom_blk_off, m->kdom_blk)))
     return rc;
-  HSM_HIP(hipMemcpyAsync(m->blk.p, blocks.data(), sizeof(BlockDesc) * blocks.size(), hipMemcpyHostToDevice, us));
   // descriptors by list position (the Krylov kernels' workgroups): every
-  // block in per-domain order, and room for the list of unfinished domains'
-  // blocks (zeroed; rewritten before each use)
-  std::vector<BlockDesc> listed(dbl.size() + 8);
+  // Krylov block in per-domain order, and room for the list of unfinished
+  // domains' blocks (zeroed; rewritten before each use)
+  std::vector<BlockDesc> listed(kry.dbl.size() + 8);
   std::memset(listed.data(), 0, sizeof(BlockDesc) * listed.size());
-  for (size_t j2 = 0; j2 < dbl.size(); ++j2) listed[j2] = blocks[dbl[j2]];
+  for (size_t j2 = 0; j2 < kry.dbl.size(); ++j2) listed[j2] = kry.blocks[kry.dbl[j2]];
   if ((rc = m->lblk0.alloc(sizeof(BlockDesc) * listed.size())) ||
       (rc = m->lblk1.alloc(sizeof(BlockDesc) * listed.size())))
     return rc;
   HSM_HIP(hipMemcpyAsync(m->lblk0.p, listed.data(), sizeof(BlockDesc) * listed.size(), hipMemcpyHostToDevice, us));
   HSM_HIP(hipMemsetAsync(m->lblk1.p, 0, sizeof(BlockDesc) * listed.size(), us));
-  HSM_HIP(hipMemcpyAsync(m->dom_blk_off.p, dbo.data(), sizeof(int32_t) * dbo.size(), hipMemcpyHostToDevice, us));
-  HSM_HIP(hipMemcpyAsync(m->dom_blk.p, dbl.data(), sizeof(int32_t) * dbl.size(), hipMemcpyHostToDevice, us));
   HSM_HIP(hipStreamSynchronize(us));      // the host vectors above go out of scope
   // grid totals: in every block's prologue for one domain on a small grid;
   // otherwise by the reduction kernels, which also own the border rows (a
@@ -544,15 +593,15 @@ hsm_status hsm_sim_create(const hsm_stencils *st, const hsm_sim_params *prm, con
     set_error(HSM_E_INVALID, "reduce_mode 1 (in-kernel reduction) needs a single domain");
     return HSM_E_INVALID;
   }
-  m->sepred = m->K > 1 || prm->reduce_mode == 2 || (prm->reduce_mode == 0 && m->nblk > kSepReduceBlocks);
+  m->sepred = m->K > 1 || prm->reduce_mode == 2 || (prm->reduce_mode == 0 && m->nkblk > kSepReduceBlocks);
   // Krylov node kernels: one block per descriptor; with many domains the
   // blocks past the list of unfinished domains' blocks return at once (a
   // grid of the blocks the device holds at once, walking the list, measured
   // 9 % slower on 512 domains: the hardware refills a full grid faster than
   // a block walks its share)
-  // the XCD-contiguous order needs at least 8 ceil(nblk / 8) workgroups (one grid slot per list position)
+  // the XCD-contiguous order needs at least 8 ceil(nkblk / 8) workgroups (one grid slot per list position)
   m->xcd = m->sepred && prm->xcd_order != 0;
-  m->kry_grid = m->xcd ? (m->nblk + kXcds - 1) / kXcds * kXcds : m->nblk;
+  m->kry_grid = m->xcd ? (m->nkblk + kXcds - 1) / kXcds * kXcds : m->nkblk;
   // grid levels of the Krylov batches: several domains only (their list of
   // blocks shrinks as domains finish); each level holds at least 8 workgroups
   // per XCD-order slot and at least 2048 workgroups
@@ -563,8 +612,8 @@ hsm_status hsm_sim_create(const hsm_stencils *st, const hsm_sim_params *prm, con
       m->lev_grid[m->nlev] = (m->lev_grid[m->nlev - 1] / 2 + kXcds - 1) / kXcds * kXcds;
       ++m->nlev;
     }
-  m->known_nact = m->nblk;
-  if ((rc = m->active.alloc(sizeof(int32_t) * (m->nblk + 1)))) return rc;
+  m->known_nact = m->nkblk;
+  if ((rc = m->active.alloc(sizeof(int32_t) * (m->nkblk + 1)))) return rc;
   if ((rc = m->dom.alloc(sizeof(DomState) * m->K)) || (rc = m->dom_nodes.alloc(sizeof(int64_t) * m->K)) ||
       (rc = m->bscale.alloc(sizeof(double) * m->K)))
     return rc;
@@ -587,8 +636,8 @@ hsm_status hsm_sim_create(const hsm_stencils *st, const hsm_sim_params *prm, con
     HSM_HIP(hipStreamSynchronize(us));
   }
   if ((rc = m->partR.alloc(sizeof(double) * kNR * (m->nblk + 1))) ||
-      (rc = m->partA.alloc(sizeof(double) * kNA * (m->nblk + 1))) ||
-      (rc = m->partB.alloc(sizeof(double) * kNB * (m->nblk + 1))))
+      (rc = m->partA.alloc(sizeof(double) * kNA * (m->nkblk + 1))) ||
+      (rc = m->partB.alloc(sizeof(double) * kNB * (m->nkblk + 1))))
     return rc;
   const int32_t *perm = st->perm.as<int32_t>();
   for (int c = 0; c < d; ++c) {

@@ -112,6 +112,13 @@ struct SimArgs {
   // costs no dependent load.  Both hold at least the Krylov grid's entries.
   const BlockDesc *lblk0;
   BlockDesc *lblk1;
+  // The Krylov node kernels' own partition of the nodes: blocks of bs / Q
+  // nodes for a width with Q lanes per node (lanes_for); per-domain block
+  // ranges and lists as for blk.  partA and partB hold one row per such block.
+  const BlockDesc *kblk;           // [nkblk]
+  int64_t nkblk;
+  const int32_t *kdom_blk_off;     // [K+1]
+  const int32_t *kdom_blk;
   DomLaunch *lpv, *lst;            // [K] per-domain records for k_bicg_pv and k_bicg_st
   double dt, Ra, Pr, T_ref, tol;
   int32_t maxiter, chunk;
@@ -231,6 +238,33 @@ __device__ __forceinline__ double wave_sum(double v) {
   v += dpp_mov<0x141>(v);   // row_half_mirror
   v += dpp_mov<0x140>(v);   // row_mirror
   return (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
+}
+
+// Lanes that share one node's stencil in the Krylov node kernels (and the
+// host's partition of their blocks): one for the regular width, whose
+// lattice row may be one row shared by the block (read as uniform values);
+// otherwise the fewest, a power of two up to 16, that leave each lane at most
+// kLaneEntries entries.  A wide stencil's gather is then one round of loads
+// per lane instead of a chain of chunks, each waiting for the last.  (At
+// most 4, 6 and 8 entries a lane were measured; 8 was fastest in 2D and 3D.)
+constexpr int kLaneEntries = 8;   // most stencil entries a lane takes
+__host__ __device__ constexpr int lanes_for(int W, int D) {
+  if (W == 2 * D + 1) return 1;
+  int q = 1;
+  while (q < 16 && (W + q - 1) / q > kLaneEntries) q *= 2;
+  return q;
+}
+
+// Sum over each aligned group of Q lanes (Q a power of two up to 16), the
+// same value in every lane of the group, added in a fixed order.  Every lane
+// of the wave must be active.
+template <int Q>
+__device__ __forceinline__ double lane_sum(double v) {
+  if constexpr (Q >= 2) v += dpp_mov<0xB1>(v);    // quad_perm [1,0,3,2]
+  if constexpr (Q >= 4) v += dpp_mov<0x4E>(v);    // quad_perm [2,3,0,1]
+  if constexpr (Q >= 8) v += dpp_mov<0x141>(v);   // row_half_mirror
+  if constexpr (Q >= 16) v += dpp_mov<0x140>(v);  // row_mirror
+  return v;
 }
 
 // Deterministic block sum of NQ values (wave sums, then the waves in order);
@@ -426,7 +460,7 @@ __device__ __forceinline__ void build_active(const SimArgs &a) {
   __syncthreads();
   for (int d0 = 0; d0 < a.K; d0 += kRedThreads) {
     const int d = d0 + tid;
-    const int c = (d < a.K && !a.dom[d].done) ? a.dom_blk_off[d + 1] - a.dom_blk_off[d] : 0;
+    const int c = (d < a.K && !a.dom[d].done) ? a.kdom_blk_off[d + 1] - a.kdom_blk_off[d] : 0;
     scan[tid] = c;
     __syncthreads();
     for (int off = 1; off < kRedThreads; off <<= 1) {
@@ -446,7 +480,7 @@ __device__ __forceinline__ void build_active(const SimArgs &a) {
         else lo = mid + 1;
       }
       const int before = lo > 0 ? scan[lo - 1] : 0;
-      a.active[base + e] = a.dom_blk[a.dom_blk_off[d0 + lo] + (e - before)];
+      a.active[base + e] = a.kdom_blk[a.kdom_blk_off[d0 + lo] + (e - before)];
     }
     __syncthreads();
     if (tid == 0) carry = base + total;
@@ -521,8 +555,8 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_a(SimArgs a, int it) {
   if (has) {
     dd = a.dom[d].done;
     e = a.dom[d].early[par];
-    j0 = a.dom_blk_off[d];
-    j1 = a.dom_blk_off[d + 1];
+    j0 = a.kdom_blk_off[d];
+    j1 = a.kdom_blk_off[d + 1];
   }
   double alpha_p = 0.0, omega = 0.0, beta = 0.0, bnorm2 = 0.0, rho = 0.0, xb = 0.0, rhb = 0.0;
   double2 rvb = make_double2(0.0, 0.0), stb = rvb, pvb = rvb;
@@ -614,8 +648,8 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_b(SimArgs a, int it) {
   int dd = 1, j0 = 0, j1 = 0;
   if (has) {
     dd = a.dom[d].done;
-    j0 = a.dom_blk_off[d];
-    j1 = a.dom_blk_off[d + 1];
+    j0 = a.kdom_blk_off[d];
+    j1 = a.kdom_blk_off[d + 1];
   }
   double alpha = 0.0, rho = 0.0, bnorm2 = 0.0, rhb = 0.0, cb = 0.0;
   double2 rv = make_double2(0.0, 0.0), pvb = rv;
@@ -768,7 +802,7 @@ __global__ __launch_bounds__(kBS) void k_rhs(SimArgs a) {
     sc->done = 0; sc->fail = 0; sc->zero_sol = 0; sc->it_base = 0; sc->iters = 0; sc->node_mv = 0.0;
     sc->early[0] = 0; sc->early[1] = 0;
     sc->list_sel = 0;                           // a new solve starts from every block
-    sc->nactive = (int32_t)a.nblk;
+    sc->nactive = (int32_t)a.nkblk;           // the Krylov kernels' list: every block
   }
   if (live) {
     const int64_t i = b.bstart + t;
@@ -850,21 +884,25 @@ __global__ __launch_bounds__(kBS) void k_rhs(SimArgs a) {
 // neighbour: (s, t), (p, v) (two generations) and (r, v).  The border row
 // and column (zero mean, multiplier) are slot N of every vector.
 // The node rows of one block of k_bicg_pv (cpN: c_d times the border entry of
-// p').  The node's own values are loaded first and used only once the
-// neighbour loads are in flight (the gather's hook), so the block's loads go
-// out in one round, and the stores come last.
-template <int D, int KP>
-__device__ __forceinline__ void pv_rows(const SimArgs &a, const BlockDesc &b, bool again, bool first,
-                                        int early, double omega, double beta, double alpha_p, double cpN) {
+// p'), for width W with Q lanes per node (lanes_for).  The node's own values
+// are loaded first and used only once the neighbour loads are in flight (the
+// gather's hook), so the block's loads go out in one round; the stores come
+// last, from the node's first lane.
+template <int D, int KP, bool LN, int W>
+__device__ __forceinline__ void pv_rows_w(const SimArgs &a, const BlockDesc &b, bool again, bool first,
+                                          int early, double omega, double beta, double alpha_p, double cpN) {
+  constexpr int Q = LN ? lanes_for(W, D) : 1;
   const int64_t N = a.N;
   const double2 *__restrict__ ST = a.ST;
   const double2 *__restrict__ PVo = a.PVo;
   const double2 *__restrict__ RV = a.RV;
-  const int64_t t = b.first + (int64_t)threadIdx.x;
-  const bool live = (int)threadIdx.x < b.nodes;
+  const int sub = (int)(threadIdx.x & (Q - 1));
+  const int64_t t = b.first + (int64_t)(threadIdx.x / Q);
+  const bool live = (int)(threadIdx.x / Q) < b.nodes;
+  const bool lead = live && sub == 0;
   const int64_t i = b.bstart + t;
   if (early == 1) {                             // |s| converged: x += alpha p, nothing else
-    if (live) a.x[i] = fma(alpha_p, PVo[i].x, a.x[i]);
+    if (lead) a.x[i] = fma(alpha_p, PVo[i].x, a.x[i]);
     return;
   }
   double2 sti = make_double2(0.0, 0.0), pvi = sti;
@@ -893,19 +931,21 @@ __device__ __forceinline__ void pv_rows(const SimArgs &a, const BlockDesc &b, bo
   if (live) {
     const uint32_t cnt32 = (uint32_t)b.count, t32 = (uint32_t)t;
     const Buf RVb = plane(RV, N + 1, 0), STb = plane(ST, N + 1, 0), PVb = plane(PVo, N + 1, 0);
-    with_width<D>(b.width, [&](auto wc) __attribute__((always_inline)) {
-      constexpr int W = decltype(wc)::value;
-      with_rows<D, W>(b, [&](auto sh) __attribute__((always_inline)) {
+    with_rows<D, W>(b, [&](auto sh) __attribute__((always_inline)) {
       constexpr bool SH = decltype(sh)::value;
-      const auto wl = [&](int j) __attribute__((always_inline)) { return ld_prow<SH>(b, cnt32, j, t32); };
+      const auto wl = [&](int j) __attribute__((always_inline)) {
+        if constexpr (Q == 1) return ld_prow<SH>(b, cnt32, j, t32);
+        else return static_cast<const double *>(b.wP)[(uint64_t)j * cnt32 + t32];
+      };
       if (first) {
-        gather_chunks<W>(
-            b.idx, cnt32, t32, wl, [&](int32_t nb) __attribute__((always_inline)) { return ld_at<double>(RVb, 2 * nb); },
+        gather_lanes<W, Q, 12>(
+            b.idx, cnt32, t32, sub, wl,
+            [&](int32_t nb) __attribute__((always_inline)) { return ld_at<double>(RVb, 2 * nb); },
             [&](int, double wj, double rj) __attribute__((always_inline)) { acc = fma(wj, rj, acc); },
             [&]() __attribute__((always_inline)) { pin(acc); }, own);
       } else {
-        gather_chunks<W, KP>(
-            b.idx, cnt32, t32, wl,
+        gather_lanes<W, Q, KP>(
+            b.idx, cnt32, t32, sub, wl,
             [&](int32_t nb) __attribute__((always_inline)) {
               return Pack<double2, 2>{{ld_at<double2>(STb, nb), ld_at<double2>(PVb, nb)}};
             },
@@ -915,11 +955,11 @@ __device__ __forceinline__ void pv_rows(const SimArgs &a, const BlockDesc &b, bo
             },
             [&]() __attribute__((always_inline)) { pin(acc); }, own);
       }
-      });
     });
   }
+  acc = lane_sum<Q>(acc);
   double part[kNA] = {0.0, 0.0, 0.0};           // (rh, v), sum p, |r|^2
-  if (live) {
+  if (lead) {
     if (!first) a.x[i] = xn;
     const double vi = acc + cpN;                // + c_d times the border entry of p'
     a.PVn[i] = make_double2(pi, vi);
@@ -929,6 +969,13 @@ __device__ __forceinline__ void pv_rows(const SimArgs &a, const BlockDesc &b, bo
     part[2] = ri * ri;
   }
   block_partials<kNA>(part, a.partA, b.prow, again);
+}
+template <int D, int KP, bool LN>
+__device__ __forceinline__ void pv_rows(const SimArgs &a, const BlockDesc &b, bool again, bool first,
+                                        int early, double omega, double beta, double alpha_p, double cpN) {
+  with_width<D>(b.width, [&](auto wc) __attribute__((always_inline)) {
+    pv_rows_w<D, KP, LN, decltype(wc)::value>(a, b, again, first, early, omega, beta, alpha_p, cpN);
+  });
 }
 
 // The descriptor of list position w's block: the Krylov kernels of the
@@ -957,11 +1004,49 @@ __device__ __forceinline__ DomLaunch load_launch(const DomLaunch *p) {
   return L;
 }
 
+// Node t's stencil gather, shared by Q lanes: lane `sub` takes entries sub,
+// sub + Q, ... (the last round leaves lanes idle where Q does not divide W;
+// their index and weight are not loaded and they add nothing).  Indices and
+// weights are plain global loads (an entry's plane varies across lanes); all
+// of a lane's neighbour loads go out in one round, then hook(), then use()
+// in entry order.  Q == 1: gather_chunks.
+template <int W, int Q, int K, class FW, class FV, class FU, class FS, class FH>
+__device__ __forceinline__ void gather_lanes(const void *idx, uint32_t cnt, uint32_t t, int sub, FW &&wload,
+                                             FV &&vload, FU &&use, FS &&settle, FH &&hook) {
+  if constexpr (Q == 1) {
+    gather_chunks<W, K>(idx, cnt, t, wload, vload, use, settle, hook);
+  } else {
+    constexpr int E = (W + Q - 1) / Q;
+    const int last = W - (E - 1) * Q;           // lanes with an entry in the last round
+    const int32_t *__restrict__ ix = static_cast<const int32_t *>(idx);
+    int32_t nb[E];
+    decltype(wload(0)) wv[E];
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+      const int j = k * Q + sub;
+      nb[k] = 0;                                // an idle lane gathers node 0 (in bounds) and adds nothing
+      wv[k] = 0;
+      if (k < E - 1 || sub < last) {
+        nb[k] = ix[(uint64_t)j * cnt + t];
+        wv[k] = wload(j);
+      }
+    }
+    decltype(vload(0)) vv[E];
+#pragma unroll
+    for (int k = 0; k < E; ++k) vv[k] = vload(nb[k]);
+    hook();
+#pragma unroll
+    for (int k = 0; k < E; ++k)
+      if (k < E - 1 || sub < last) use(k * Q + sub, wv[k], vv[k]);
+    settle();
+  }
+}
+
 // KP: entries per gather chunk (a tuning parameter: more loads in flight
 // against more registers held).  SEP: the reduction-kernel path (a.sepred),
 // a template parameter so that no branch on it separates the first round of
-// loads.
-template <int D, int KP, bool SEP>
+// loads.  LN: several lanes per node of a non-regular width (lanes_for).
+template <int D, int KP, bool SEP, bool LN>
 __global__ __launch_bounds__(kBS) void k_bicg_pv(SimArgs a, int it) {
   Scalars *sc = a.sc;
   const int par = it & 1;
@@ -983,17 +1068,17 @@ __global__ __launch_bounds__(kBS) void k_bicg_pv(SimArgs a, int it) {
     // the domain's record (decided by k_reduce_b, or k_reduce_r for the first iteration)
     const DomLaunch L = load_launch(a.lpv + b.domain);
     if (L.done || (!first && L.early == 2)) return;
-    pv_rows<D, KP>(a, b, true, first, first ? 0 : L.early, L.c[0], L.c[1], L.c[2], L.c[3]);
+    pv_rows<D, KP, LN>(a, b, true, first, first ? 0 : L.early, L.c[0], L.c[1], L.c[2], L.c[3]);
     return;
   }
   // one domain, small grid: every block reduces the partials and takes the same decisions
   if (done) return;
-  const BlockDesc b = a.blk[blockIdx.x];
+  const BlockDesc b = a.kblk[blockIdx.x];
   double omega = 0.0, beta = 0.0, alpha_p = 0.0, pN;
   int early = 0;
   if (first) {
     double tot[kNR];
-    reduce_prev<kNR>(a.partR, gridDim.x, tot);
+    reduce_prev<kNR>(a.partR, a.nblk, tot);   // k_rhs: one row per node block
     const double rN = -(a.bscale[0] * tot[2]);  // border row of r0: 0 - c sum x
     const double rho_k = fma(rN, rN, tot[1]);   // (rh, r0) = |r0|^2
     pN = rN;
@@ -1044,17 +1129,21 @@ __global__ __launch_bounds__(kBS) void k_bicg_pv(SimArgs a, int it) {
     }
     if (early == 2) return;
   }
-  pv_rows<D, KP>(a, b, false, first, early, omega, beta, alpha_p, a.bscale[0] * pN);
+  pv_rows<D, KP, LN>(a, b, false, first, early, omega, beta, alpha_p, a.bscale[0] * pN);
 }
 
 // The node rows of one block of k_bicg_st (csN: c_d times the border entry of
-// s).  As in k_bicg_pv: own values first, used in the gather's hook.
-template <int D>
-__device__ __forceinline__ void st_rows(const SimArgs &a, const BlockDesc &b, bool again, double alpha,
-                                        double csN) {
+// s), for width W with Q lanes per node.  As in k_bicg_pv: own values first,
+// used in the gather's hook; stores from the node's first lane.
+template <int D, bool LN, int W>
+__device__ __forceinline__ void st_rows_w(const SimArgs &a, const BlockDesc &b, bool again, double alpha,
+                                          double csN) {
+  constexpr int Q = LN ? lanes_for(W, D) : 1;
   const int64_t N = a.N;
-  const int64_t t = b.first + (int64_t)threadIdx.x;
-  const bool live = (int)threadIdx.x < b.nodes;
+  const int sub = (int)(threadIdx.x & (Q - 1));
+  const int64_t t = b.first + (int64_t)(threadIdx.x / Q);
+  const bool live = (int)(threadIdx.x / Q) < b.nodes;
+  const bool lead = live && sub == 0;
   const int64_t i = b.bstart + t;
   const double2 *__restrict__ RV = a.RV;
   double2 rvi = make_double2(0.0, 0.0);
@@ -1067,22 +1156,24 @@ __device__ __forceinline__ void st_rows(const SimArgs &a, const BlockDesc &b, bo
   if (live) {
     const uint32_t cnt32 = (uint32_t)b.count, t32 = (uint32_t)t;
     const Buf RVb = plane(RV, N + 1, 0);
-    with_width<D>(b.width, [&](auto wc) __attribute__((always_inline)) {
-      constexpr int W = decltype(wc)::value;
-      with_rows<D, W>(b, [&](auto sh) __attribute__((always_inline)) {
+    with_rows<D, W>(b, [&](auto sh) __attribute__((always_inline)) {
       constexpr bool SH = decltype(sh)::value;
-      gather_chunks<W>(
-          b.idx, cnt32, t32, [&](int j) __attribute__((always_inline)) { return ld_prow<SH>(b, cnt32, j, t32); },
+      const auto wl = [&](int j) __attribute__((always_inline)) {
+        if constexpr (Q == 1) return ld_prow<SH>(b, cnt32, j, t32);
+        else return static_cast<const double *>(b.wP)[(uint64_t)j * cnt32 + t32];
+      };
+      gather_lanes<W, Q, 12>(
+          b.idx, cnt32, t32, sub, wl,
           [&](int32_t nb) __attribute__((always_inline)) { return ld_at<double2>(RVb, nb); },
           [&](int, double wj, const double2 &rv2) __attribute__((always_inline)) {
             acc = fma(wj, fma(-alpha, rv2.y, rv2.x), acc);
           },
           [&]() __attribute__((always_inline)) { pin(acc); }, own);
-      });
     });
   }
+  acc = lane_sum<Q>(acc);
   double part[kNB] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};   // (t,s), (t,t), (rh,s), (rh,t), (s,s), sum s
-  if (live) {
+  if (lead) {
     const double ti = acc + csN;                // + c_d times the border entry of s
     a.ST[i] = make_double2(si, ti);
     part[0] = ti * si;
@@ -1094,8 +1185,15 @@ __device__ __forceinline__ void st_rows(const SimArgs &a, const BlockDesc &b, bo
   }
   block_partials<kNB>(part, a.partB, b.prow, again);
 }
+template <int D, bool LN>
+__device__ __forceinline__ void st_rows(const SimArgs &a, const BlockDesc &b, bool again, double alpha,
+                                        double csN) {
+  with_width<D>(b.width, [&](auto wc) __attribute__((always_inline)) {
+    st_rows_w<D, LN, decltype(wc)::value>(a, b, again, alpha, csN);
+  });
+}
 
-template <int D, bool SEP>
+template <int D, bool SEP, bool LN>
 __global__ __launch_bounds__(kBS) void k_bicg_st(SimArgs a, int it) {
   Scalars *sc = a.sc;
   const int par = it & 1;
@@ -1111,11 +1209,11 @@ __global__ __launch_bounds__(kBS) void k_bicg_st(SimArgs a, int it) {
     if (done || !in) return;
     const DomLaunch L = load_launch(a.lst + b.domain);   // decided by k_reduce_a
     if (L.done) return;
-    st_rows<D>(a, b, true, L.c[0], L.c[1]);
+    st_rows<D, LN>(a, b, true, L.c[0], L.c[1]);
     return;
   }
   if (done) return;
-  const BlockDesc b = a.blk[blockIdx.x];
+  const BlockDesc b = a.kblk[blockIdx.x];
   if (early) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       sc->done = 1;
@@ -1153,7 +1251,7 @@ __global__ __launch_bounds__(kBS) void k_bicg_st(SimArgs a, int it) {
     }
   }
   if (stop) return;
-  st_rows<D>(a, b, false, alpha, a.bscale[0] * sN);
+  st_rows<D, LN>(a, b, false, alpha, a.bscale[0] * sN);
 }
 
 // End of a batch of iterations (one block of kRedThreads).  With several
@@ -1188,7 +1286,7 @@ __global__ __launch_bounds__(kBS) void k_list_desc(SimArgs a) {
   const Scalars *sc = a.sc;
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (sc->done || !sc->list_sel || v >= sc->nactive) return;
-  a.lblk1[v] = a.blk[a.active[v]];
+  a.lblk1[v] = a.kblk[a.active[v]];
 }
 
 // -------------------------------------------- projection + heat transport --

@@ -46,7 +46,8 @@ class SimParamsC(ctypes.Structure):
                 ("T_ref", ctypes.c_double), ("krylov_tol", ctypes.c_double), ("krylov_maxiter", ctypes.c_int32),
                 ("field_dtype", ctypes.c_int32), ("krylov_chunk", ctypes.c_int32), ("launch_mode", ctypes.c_int32),
                 ("profile", ctypes.c_int32), ("reduce_mode", ctypes.c_int32), ("block_nodes", ctypes.c_int32),
-                ("gather_chunk", ctypes.c_int32), ("xcd_order", ctypes.c_int32), ("lattice_rows", ctypes.c_int32)]
+                ("gather_chunk", ctypes.c_int32), ("xcd_order", ctypes.c_int32), ("lattice_rows", ctypes.c_int32),
+                ("wide_lanes", ctypes.c_int32)]
 
 
 class SimStatsC(ctypes.Structure):
@@ -267,10 +268,10 @@ class Sim:
     def __init__(self, st: Stencils, v: torch.Tensor, T: torch.Tensor, p=None, *, Ra, Pr, dt, T_ref,
                  krylov_tol=1e-12, krylov_maxiter=20000, field_dtype=F64, krylov_chunk=0, launch_mode=0,
                  profile=0, reduce_mode=0, block_nodes=0, gather_chunk=0, xcd_order=0, lattice_rows=0,
-                 stream=None):
+                 wide_lanes=0, stream=None):
         self.st = st
         prm = SimParamsC(Ra, Pr, dt, T_ref, krylov_tol, krylov_maxiter, field_dtype, krylov_chunk, launch_mode,
-                         profile, reduce_mode, block_nodes, gather_chunk, xcd_order, lattice_rows)
+                         profile, reduce_mode, block_nodes, gather_chunk, xcd_order, lattice_rows, wide_lanes)
         h = _p()
         _check(lib().hsm_sim_create(st.handle, ctypes.byref(prm), _dptr(v, torch.float64), _dptr(T, torch.float64),
                                     None if p is None else _dptr(p, torch.float64), _stream(stream),

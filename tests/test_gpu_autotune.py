@@ -35,7 +35,8 @@ def _run(s, knobs, steps=10):
     sim = hsm.Sim(st, v0, T0, Ra=1e5, Pr=0.71, dt=0.1 * s.h ** 2 / 2, T_ref=0.5, krylov_tol=1e-12,
                   krylov_maxiter=100000, block_nodes=knobs.get("block_nodes", 0),
                   gather_chunk=knobs.get("gather_chunk", 0), krylov_chunk=knobs.get("krylov_chunk", 0),
-                  xcd_order=knobs.get("xcd_order", 0), reduce_mode=knobs.get("reduce_mode", 0))
+                  xcd_order=knobs.get("xcd_order", 0), reduce_mode=knobs.get("reduce_mode", 0),
+                  wide_lanes=knobs.get("wide_lanes", 0))
     sim.step(steps)
     assert sim.stats()["status"] == 0
     out = [a.cpu().numpy() for a in sim.read()]
@@ -48,7 +49,9 @@ def _run(s, knobs, steps=10):
     dict(tile_log2=2, solve_groups=1, block_nodes=64, gather_chunk=4, krylov_chunk=16),
     dict(tile_log2=4, solve_groups=2, block_nodes=128, gather_chunk=12, krylov_chunk=64, xcd_order=1,
          reduce_mode=2),
-    dict(xcd_order=1, reduce_mode=2),
+    dict(xcd_order=1, reduce_mode=2, wide_lanes=2),
+    dict(wide_lanes=1, block_nodes=64),
+    dict(wide_lanes=2, block_nodes=64, reduce_mode=1),
     dict(tile_log2=3, solve_groups=3, block_nodes=256, gather_chunk=6, krylov_chunk=32),
 ])
 def test_searched_parameters_keep_results(knobs):
