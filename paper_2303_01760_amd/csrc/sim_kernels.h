@@ -255,15 +255,14 @@ __host__ __device__ constexpr int lanes_for(int W, int D) {
   return q;
 }
 
-// Sum over each aligned group of Q lanes (Q a power of two up to 16), the
-// same value in every lane of the group, added in a fixed order.  Every lane
-// of the wave must be active.
-template <int Q>
-__device__ __forceinline__ double lane_sum(double v) {
-  if constexpr (Q >= 2) v += dpp_mov<0xB1>(v);    // quad_perm [1,0,3,2]
-  if constexpr (Q >= 4) v += dpp_mov<0x4E>(v);    // quad_perm [2,3,0,1]
-  if constexpr (Q >= 8) v += dpp_mov<0x141>(v);   // row_half_mirror
-  if constexpr (Q >= 16) v += dpp_mov<0x140>(v);  // row_mirror
+// Sum over each aligned group of Q lanes (Q a power of two up to 16, the
+// same in every lane), the same value in every lane of the group, added in a
+// fixed order.  Every lane of the wave must be active.
+__device__ __forceinline__ double lane_sum(double v, int Q) {
+  if (Q >= 2) v += dpp_mov<0xB1>(v);    // quad_perm [1,0,3,2]
+  if (Q >= 4) v += dpp_mov<0x4E>(v);    // quad_perm [2,3,0,1]
+  if (Q >= 8) v += dpp_mov<0x141>(v);   // row_half_mirror
+  if (Q >= 16) v += dpp_mov<0x140>(v);  // row_mirror
   return v;
 }
 
@@ -884,21 +883,23 @@ __global__ __launch_bounds__(kBS) void k_rhs(SimArgs a) {
 // neighbour: (s, t), (p, v) (two generations) and (r, v).  The border row
 // and column (zero mean, multiplier) are slot N of every vector.
 // The node rows of one block of k_bicg_pv (cpN: c_d times the border entry of
-// p'), for width W with Q lanes per node (lanes_for).  The node's own values
-// are loaded first and used only once the neighbour loads are in flight (the
-// gather's hook), so the block's loads go out in one round; the stores come
-// last, from the node's first lane.
-template <int D, int KP, bool LN, int W>
-__device__ __forceinline__ void pv_rows_w(const SimArgs &a, const BlockDesc &b, bool again, bool first,
-                                          int early, double omega, double beta, double alpha_p, double cpN) {
-  constexpr int Q = LN ? lanes_for(W, D) : 1;
+// p'), Q threads per node (Q = lanes_for(width) with LN, else 1; uniform in
+// the block).  The node's own values are loaded first and used only once the
+// neighbour loads are in flight (the gather's hook), so the block's loads go
+// out in one round; the stores come last, from the node's first lane.  Only
+// the gather is compiled per width.
+template <int D, int KP, bool LN>
+__device__ __forceinline__ void pv_rows(const SimArgs &a, const BlockDesc &b, bool again, bool first,
+                                        int early, double omega, double beta, double alpha_p, double cpN) {
   const int64_t N = a.N;
   const double2 *__restrict__ ST = a.ST;
   const double2 *__restrict__ PVo = a.PVo;
   const double2 *__restrict__ RV = a.RV;
-  const int sub = (int)(threadIdx.x & (Q - 1));
-  const int64_t t = b.first + (int64_t)(threadIdx.x / Q);
-  const bool live = (int)(threadIdx.x / Q) < b.nodes;
+  const int Q = LN ? lanes_for(b.width, D) : 1;
+  const int node = (int)threadIdx.x >> __builtin_ctz((unsigned)Q);
+  const int sub = (int)threadIdx.x & (Q - 1);
+  const int64_t t = b.first + (int64_t)node;
+  const bool live = node < b.nodes;
   const bool lead = live && sub == 0;
   const int64_t i = b.bstart + t;
   if (early == 1) {                             // |s| converged: x += alpha p, nothing else
@@ -931,33 +932,37 @@ __device__ __forceinline__ void pv_rows_w(const SimArgs &a, const BlockDesc &b, 
   if (live) {
     const uint32_t cnt32 = (uint32_t)b.count, t32 = (uint32_t)t;
     const Buf RVb = plane(RV, N + 1, 0), STb = plane(ST, N + 1, 0), PVb = plane(PVo, N + 1, 0);
-    with_rows<D, W>(b, [&](auto sh) __attribute__((always_inline)) {
-      constexpr bool SH = decltype(sh)::value;
-      const auto wl = [&](int j) __attribute__((always_inline)) {
-        if constexpr (Q == 1) return ld_prow<SH>(b, cnt32, j, t32);
-        else return static_cast<const double *>(b.wP)[(uint64_t)j * cnt32 + t32];
-      };
-      if (first) {
-        gather_lanes<W, Q, 12>(
-            b.idx, cnt32, t32, sub, wl,
-            [&](int32_t nb) __attribute__((always_inline)) { return ld_at<double>(RVb, 2 * nb); },
-            [&](int, double wj, double rj) __attribute__((always_inline)) { acc = fma(wj, rj, acc); },
-            [&]() __attribute__((always_inline)) { pin(acc); }, own);
-      } else {
-        gather_lanes<W, Q, KP>(
-            b.idx, cnt32, t32, sub, wl,
-            [&](int32_t nb) __attribute__((always_inline)) {
-              return Pack<double2, 2>{{ld_at<double2>(STb, nb), ld_at<double2>(PVb, nb)}};
-            },
-            [&](int, double wj, const Pack<double2, 2> &g) __attribute__((always_inline)) {
-              const double pj = fma(beta, fma(-omega, g.v[1].y, g.v[1].x), fma(-omega, g.v[0].y, g.v[0].x));
-              acc = fma(wj, pj, acc);
-            },
-            [&]() __attribute__((always_inline)) { pin(acc); }, own);
-      }
+    with_width<D>(b.width, [&](auto wc) __attribute__((always_inline)) {
+      constexpr int W = decltype(wc)::value;
+      constexpr int QW = LN ? lanes_for(W, D) : 1;
+      with_rows<D, W>(b, [&](auto sh) __attribute__((always_inline)) {
+        constexpr bool SH = decltype(sh)::value;
+        const auto wl = [&](int j) __attribute__((always_inline)) {
+          if constexpr (QW == 1) return ld_prow<SH>(b, cnt32, j, t32);
+          else return static_cast<const double *>(b.wP)[(uint64_t)j * cnt32 + t32];
+        };
+        if (first) {
+          gather_lanes<W, QW, 12>(
+              b.idx, cnt32, t32, sub, wl,
+              [&](int32_t nb) __attribute__((always_inline)) { return ld_at<double>(RVb, 2 * nb); },
+              [&](int, double wj, double rj) __attribute__((always_inline)) { acc = fma(wj, rj, acc); },
+              [&]() __attribute__((always_inline)) { pin(acc); }, own);
+        } else {
+          gather_lanes<W, QW, KP>(
+              b.idx, cnt32, t32, sub, wl,
+              [&](int32_t nb) __attribute__((always_inline)) {
+                return Pack<double2, 2>{{ld_at<double2>(STb, nb), ld_at<double2>(PVb, nb)}};
+              },
+              [&](int, double wj, const Pack<double2, 2> &g) __attribute__((always_inline)) {
+                const double pj = fma(beta, fma(-omega, g.v[1].y, g.v[1].x), fma(-omega, g.v[0].y, g.v[0].x));
+                acc = fma(wj, pj, acc);
+              },
+              [&]() __attribute__((always_inline)) { pin(acc); }, own);
+        }
+      });
     });
   }
-  acc = lane_sum<Q>(acc);
+  if (LN) acc = lane_sum(acc, Q);
   double part[kNA] = {0.0, 0.0, 0.0};           // (rh, v), sum p, |r|^2
   if (lead) {
     if (!first) a.x[i] = xn;
@@ -969,13 +974,6 @@ __device__ __forceinline__ void pv_rows_w(const SimArgs &a, const BlockDesc &b, 
     part[2] = ri * ri;
   }
   block_partials<kNA>(part, a.partA, b.prow, again);
-}
-template <int D, int KP, bool LN>
-__device__ __forceinline__ void pv_rows(const SimArgs &a, const BlockDesc &b, bool again, bool first,
-                                        int early, double omega, double beta, double alpha_p, double cpN) {
-  with_width<D>(b.width, [&](auto wc) __attribute__((always_inline)) {
-    pv_rows_w<D, KP, LN, decltype(wc)::value>(a, b, again, first, early, omega, beta, alpha_p, cpN);
-  });
 }
 
 // The descriptor of list position w's block: the Krylov kernels of the
@@ -1133,16 +1131,17 @@ __global__ __launch_bounds__(kBS) void k_bicg_pv(SimArgs a, int it) {
 }
 
 // The node rows of one block of k_bicg_st (csN: c_d times the border entry of
-// s), for width W with Q lanes per node.  As in k_bicg_pv: own values first,
-// used in the gather's hook; stores from the node's first lane.
-template <int D, bool LN, int W>
-__device__ __forceinline__ void st_rows_w(const SimArgs &a, const BlockDesc &b, bool again, double alpha,
-                                          double csN) {
-  constexpr int Q = LN ? lanes_for(W, D) : 1;
+// s), Q threads per node as in k_bicg_pv: own values first, used in the
+// gather's hook; stores from the node's first lane.
+template <int D, bool LN>
+__device__ __forceinline__ void st_rows(const SimArgs &a, const BlockDesc &b, bool again, double alpha,
+                                        double csN) {
   const int64_t N = a.N;
-  const int sub = (int)(threadIdx.x & (Q - 1));
-  const int64_t t = b.first + (int64_t)(threadIdx.x / Q);
-  const bool live = (int)(threadIdx.x / Q) < b.nodes;
+  const int Q = LN ? lanes_for(b.width, D) : 1;
+  const int node = (int)threadIdx.x >> __builtin_ctz((unsigned)Q);
+  const int sub = (int)threadIdx.x & (Q - 1);
+  const int64_t t = b.first + (int64_t)node;
+  const bool live = node < b.nodes;
   const bool lead = live && sub == 0;
   const int64_t i = b.bstart + t;
   const double2 *__restrict__ RV = a.RV;
@@ -1156,22 +1155,26 @@ __device__ __forceinline__ void st_rows_w(const SimArgs &a, const BlockDesc &b, 
   if (live) {
     const uint32_t cnt32 = (uint32_t)b.count, t32 = (uint32_t)t;
     const Buf RVb = plane(RV, N + 1, 0);
-    with_rows<D, W>(b, [&](auto sh) __attribute__((always_inline)) {
-      constexpr bool SH = decltype(sh)::value;
-      const auto wl = [&](int j) __attribute__((always_inline)) {
-        if constexpr (Q == 1) return ld_prow<SH>(b, cnt32, j, t32);
-        else return static_cast<const double *>(b.wP)[(uint64_t)j * cnt32 + t32];
-      };
-      gather_lanes<W, Q, 12>(
-          b.idx, cnt32, t32, sub, wl,
-          [&](int32_t nb) __attribute__((always_inline)) { return ld_at<double2>(RVb, nb); },
-          [&](int, double wj, const double2 &rv2) __attribute__((always_inline)) {
-            acc = fma(wj, fma(-alpha, rv2.y, rv2.x), acc);
-          },
-          [&]() __attribute__((always_inline)) { pin(acc); }, own);
+    with_width<D>(b.width, [&](auto wc) __attribute__((always_inline)) {
+      constexpr int W = decltype(wc)::value;
+      constexpr int QW = LN ? lanes_for(W, D) : 1;
+      with_rows<D, W>(b, [&](auto sh) __attribute__((always_inline)) {
+        constexpr bool SH = decltype(sh)::value;
+        const auto wl = [&](int j) __attribute__((always_inline)) {
+          if constexpr (QW == 1) return ld_prow<SH>(b, cnt32, j, t32);
+          else return static_cast<const double *>(b.wP)[(uint64_t)j * cnt32 + t32];
+        };
+        gather_lanes<W, QW, 12>(
+            b.idx, cnt32, t32, sub, wl,
+            [&](int32_t nb) __attribute__((always_inline)) { return ld_at<double2>(RVb, nb); },
+            [&](int, double wj, const double2 &rv2) __attribute__((always_inline)) {
+              acc = fma(wj, fma(-alpha, rv2.y, rv2.x), acc);
+            },
+            [&]() __attribute__((always_inline)) { pin(acc); }, own);
+      });
     });
   }
-  acc = lane_sum<Q>(acc);
+  if (LN) acc = lane_sum(acc, Q);
   double part[kNB] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};   // (t,s), (t,t), (rh,s), (rh,t), (s,s), sum s
   if (lead) {
     const double ti = acc + csN;                // + c_d times the border entry of s
@@ -1184,13 +1187,6 @@ __device__ __forceinline__ void st_rows_w(const SimArgs &a, const BlockDesc &b, 
     part[5] = si;
   }
   block_partials<kNB>(part, a.partB, b.prow, again);
-}
-template <int D, bool LN>
-__device__ __forceinline__ void st_rows(const SimArgs &a, const BlockDesc &b, bool again, double alpha,
-                                        double csN) {
-  with_width<D>(b.width, [&](auto wc) __attribute__((always_inline)) {
-    st_rows_w<D, LN, decltype(wc)::value>(a, b, again, alpha, csN);
-  });
 }
 
 template <int D, bool SEP, bool LN>
