@@ -261,11 +261,13 @@ def _many_domains(n):
     return sets, x, kind, nrm, off, T0
 
 
-@pytest.mark.parametrize("knobs", [{}, dict(xcd_order=1, block_nodes=128, gather_chunk=6)])
+@pytest.mark.parametrize("knobs", [{}, dict(xcd_order=1, block_nodes=128, gather_chunk=6), dict(wide_lanes=2),
+                                   dict(wide_lanes=1, block_nodes=64)])
 def test_many_domains_steps_match_oracle(knobs):
     # 40 domains: several reduction blocks (sixteen domains to a block), and
     # domains that stop at different iterations; also with the XCD-contiguous
-    # order of the list of unfinished domains' blocks
+    # order of the list of unfinished domains' blocks, and with the wide
+    # stencils taken by several lanes per node or by one
     hsm = _hsm()
     sets, x, kind, nrm, off, T0 = _many_domains(40)
     hs = [q.h for q in sets]
