@@ -489,7 +489,8 @@ def main():
         # profile=1: start/stop events around every graph launch on the stepper's stream
         sim = hsm.Sim(st, v0, T0d, Ra=Ra, Pr=0.71, dt=dt, T_ref=0.5, krylov_tol=args.tol, krylov_maxiter=200000,
                       krylov_chunk=kb["krylov_chunk"], block_nodes=kb["block_nodes"],
-                      gather_chunk=kb["gather_chunk"], xcd_order=kb["xcd_order"], wide_lanes=kb["wide_lanes"], profile=1,
+                      gather_chunk=kb["gather_chunk"], xcd_order=kb["xcd_order"], wide_lanes=kb["wide_lanes"],
+                      reduce_mode=kb["reduce_mode"], profile=1,
                       field_dtype=field_dtype)
         try:
             sim.step(args.time_steps)

@@ -16,7 +16,10 @@ of floating-point sums; the weights do not change at all):
           gather_chunk  stencil entries per gather round of the BiCGSTAB p/v
                         kernel (loads in flight against registers held);
           krylov_chunk  BiCGSTAB iterations per device-side batch between
-                        convergence checks.
+                        convergence checks;
+          reduce_mode   one domain only: the Krylov dot products reduced in
+                        every block's prologue, or by the reduction kernels
+                        (or the library's choice by grid size).
 
 What is timed:
   solve_groups: the device time of the RBF-FD buckets' local solves (the
@@ -48,7 +51,7 @@ import torch
 from . import hsm
 
 DEFAULTS = dict(tile_log2=0, solve_groups=0, block_nodes=256, gather_chunk=8, krylov_chunk=32, xcd_order=0,
-                wide_lanes=0)
+                wide_lanes=0, reduce_mode=0)
 LANE_CANDIDATES = (0, 1, 2)
 TILE_CANDIDATES = {2: (2, 3, 4), 3: (1, 2, 3)}
 DEFAULT_TILE = {2: 3, 3: 2}
@@ -109,7 +112,7 @@ def _krylov_ns_per_row(st, sim_kw, knobs, steps) -> float:
                   T_ref=sim_kw["T_ref"], krylov_tol=sim_kw["tol"], krylov_maxiter=sim_kw.get("maxiter", 200000),
                   field_dtype=sim_kw.get("field_dtype", hsm.F64), profile=1, block_nodes=knobs["block_nodes"],
                   gather_chunk=knobs["gather_chunk"], krylov_chunk=knobs["krylov_chunk"],
-                  xcd_order=knobs["xcd_order"], wide_lanes=knobs["wide_lanes"])
+                  xcd_order=knobs["xcd_order"], wide_lanes=knobs["wide_lanes"], reduce_mode=knobs["reduce_mode"])
     try:
         sim.step(steps)
         ms, n = sim.phase_times()["krylov_batch"]
@@ -179,6 +182,8 @@ def tune(x: torch.Tensor, kind: torch.Tensor, normal: torch.Tensor, h, m, sim_kw
     pick("block_nodes", BLOCK_CANDIDATES, kry)
     pick("gather_chunk", GATHER_CANDIDATES, kry)
     pick("krylov_chunk", BATCH_CANDIDATES, kry)
+    if domain_offsets is None or len(domain_offsets) == 2:   # several domains always use the reduction kernels
+        pick("reduce_mode", (0, 1, 2), kry)
     rec = dict(choice=cur, timings=timings, key=key, tuning_s=time.perf_counter() - t_start,
                units=dict(solve_groups="ms of RBF-FD solves per build",
                           other="ns of Krylov batch time per matvec node row"))
