@@ -232,7 +232,7 @@ typedef struct {
   int32_t launch_mode;     /* 0: replay captured HIP graphs, 1: launch kernels directly (same kernels) */
   int32_t profile;         /* 1: bracket each phase (pre, Krylov batch, post) with HIP events; see hsm_sim_phase_times */
   int32_t reduce_mode;     /* Krylov dot products: 0 auto, 1 each block reduces all partials, 2 one-block kernel */
-  int32_t block_nodes;     /* nodes (threads) per block of the node kernels: 0 (= 256), 64, 128 or 256 */
+  int32_t block_nodes;     /* nodes (threads) per block of the node kernels: 0 (= 256), 64, 128, 256 or 512 */
   int32_t gather_chunk;    /* stencil entries per gather round of the BiCGSTAB p/v kernel: 0 (= 8), 4, 6, 8, 12 */
   int32_t xcd_order;       /* 1: where the dot products use the reduction kernels (several domains, or more
                               than 1024 blocks), each XCD runs one contiguous run of the Krylov kernels' blocks

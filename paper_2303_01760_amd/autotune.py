@@ -55,7 +55,7 @@ DEFAULTS = dict(tile_log2=0, solve_groups=0, block_nodes=256, gather_chunk=8, kr
 LANE_CANDIDATES = (0, 1, 2)
 TILE_CANDIDATES = {2: (2, 3, 4), 3: (1, 2, 3)}
 DEFAULT_TILE = {2: 3, 3: 2}
-BLOCK_CANDIDATES = (128, 256, 64)
+BLOCK_CANDIDATES = (128, 256, 64, 512)
 GATHER_CANDIDATES = (8, 6, 12, 4)
 BATCH_CANDIDATES = (32, 16, 64)
 

@@ -401,8 +401,9 @@ hsm_status hsm_sim_create(const hsm_stencils *st, const hsm_sim_params *prm, con
   auto m = std::make_unique<hsm_sim>();
   m->st = st; m->prm = *prm; m->d = st->d; m->N = st->N;
   m->chunk = prm->krylov_chunk ? prm->krylov_chunk : 32;
-  if (prm->block_nodes != 0 && prm->block_nodes != 64 && prm->block_nodes != 128 && prm->block_nodes != 256) {
-    set_error(HSM_E_INVALID, "block_nodes must be 0 (256), 64, 128 or 256");
+  if (prm->block_nodes != 0 && prm->block_nodes != 64 && prm->block_nodes != 128 && prm->block_nodes != 256 &&
+      prm->block_nodes != 512) {
+    set_error(HSM_E_INVALID, "block_nodes must be 0 (256), 64, 128, 256 or 512");
     return HSM_E_INVALID;
   }
   if (prm->gather_chunk != 0 && prm->gather_chunk != 4 && prm->gather_chunk != 6 && prm->gather_chunk != 8 &&
@@ -422,7 +423,7 @@ hsm_status hsm_sim_create(const hsm_stencils *st, const hsm_sim_params *prm, con
     set_error(HSM_E_INVALID, "xcd_order must be 0 or 1");
     return HSM_E_INVALID;
   }
-  m->bs = prm->block_nodes ? prm->block_nodes : kBS;
+  m->bs = prm->block_nodes ? prm->block_nodes : 256;
   m->kp = prm->gather_chunk ? prm->gather_chunk : 8;
   if (m->chunk & 1) m->chunk += 1;   // even: ping-pong buffers line up across batches
   const int64_t N = st->N, d = st->d;

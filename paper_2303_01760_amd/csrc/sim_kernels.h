@@ -13,7 +13,7 @@
 namespace hsm {
 namespace {
 
-constexpr int kBS = 256;
+constexpr int kBS = 512;   // the largest block of the node kernels (block_nodes; 256 by default)
 constexpr int kNR = 3;          // partial sums of the right-hand-side kernel
 constexpr int kNA = 3;          // partial sums of the p/v kernel
 constexpr int kNB = 6;          // partial sums of the s/t kernel
