@@ -1,7 +1,8 @@
 """The measurement code of bench.py: the algorithmic byte model of one
 BiCGSTAB iteration, the scaling of counter-measured traffic by the plain copy
-kernel, and the kernel-source check that keeps a stale traffic record out of
-the bench line.  CPU only; the counter files are written here."""
+kernel, the kernel-source check that keeps a stale traffic record out of the
+bench line, and the kernel-trace summary's iteration time.  CPU only; the
+counter and trace files are written here."""
 import csv
 import json
 
@@ -92,3 +93,49 @@ def test_traffic_record_needs_the_measured_kernel_sources(tmp_path, monkeypatch)
     assert bench.traffic_record("c3") is None                     # measured on other kernels
     json.dump(dict(kernel_source_sha256=bench.kernel_source_sha(), hbm_bytes_per_iteration=1.0), open(path, "w"))
     assert bench.traffic_record("c3")["hbm_bytes_per_iteration"] == 1.0
+
+
+def test_trace_summary_iteration_from_batch_spans(tmp_path):
+    # a synthetic kernel trace: an autotuner candidate build with a time step,
+    # then the timed build, its right-hand side and three batches of four
+    # iterations; the third batch's p/v launches return at once (queued past
+    # convergence), so only the first two count as full batches
+    ns = lambda us: int(us * 1000)
+    rows = []
+
+    def k(name, start_us, dur_us, grid=256):
+        rows.append(dict(Kernel_Name=f"void hsm::(anonymous namespace)::{name}(hsm::SimArgs)", Grid_Size_X=grid,
+                         Start_Timestamp=ns(start_us), End_Timestamp=ns(start_us + dur_us)))
+
+    k("k_bbox_part", 0, 1)
+    k("k_predict<2, double>", 5, 1)
+    k("k_bbox_part", 100, 1)
+    k("k_predict<2, double>", 105, 1)
+    k("k_rhs<2, double>", 110, 2)               # the first batch starts where this ends: 112 us
+    t = 112.0
+    for per_it, pv_us in ((20.0, 5.0), (25.0, 6.0), (4.0, 1.0)):
+        for j in range(4):
+            k("k_bicg_pv<2, 8, true, true>", t + j * per_it, pv_us)
+            k("k_bicg_st<2, true, true>", t + j * per_it + pv_us, 2.0)
+        t += 4 * per_it
+        k("k_chunk_end", t - 1.0, 1.0, grid=1024)    # ends at t
+    trace = tmp_path / "trace.csv"
+    with open(trace, "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=list(rows[0]))
+        w.writeheader()
+        for r in rows[::-1]:                    # any order: the summary sorts by start time
+            w.writerow(r)
+    stats = tmp_path / "stats.csv"
+    with open(stats, "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=["Name", "Calls", "AverageNs", "Percentage"])
+        w.writeheader()
+        w.writerow(dict(Name="k_bicg_pv<2, 8, true, true>", Calls=12, AverageNs=4000, Percentage=50.0))
+    out = tmp_path / "summary.txt"
+    bench.trace_summary(str(trace), str(stats), 0, 1, "cmd", str(out))
+    text = out.read_text()
+    assert "full batches of 4 iterations: 2" in text
+    assert "mean iteration time (chunk_end-to-chunk_end span / 4): 22.50 us" in text
+    # every batch, idle or not: 80 + 100 + 16 us
+    assert "all batches (the last of each solve partly idle; with many domains, each domain stops on its own): " \
+           "3, total 0.196 ms" in text
+    assert "k_bicg_pv<2, 8, true, true> [grid 256]" in text
