@@ -90,3 +90,38 @@ def test_bench_refuses_more_than_one_gpu():
     assert r.returncode != 0
     assert "one GPU" in r.stderr
     assert r.stdout.strip() == ""
+
+
+def test_binding_structs_match_the_c_header(tmp_path):
+    # the ctypes mirrors of the ABI's structs against the header itself:
+    # every field's offset and each struct's size, from a C program that
+    # includes include/hsm.h (compiled here with the host compiler)
+    import ctypes
+    import os
+    import shutil
+    import subprocess
+    from paper_2303_01760_amd import hsm as H
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    structs = {"hsm_nodeset": H.NodeSetC, "hsm_stencils_info": H.StencilsInfoC, "hsm_sim_params": H.SimParamsC,
+               "hsm_sim_stats": H.SimStatsC}
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "hsm.h"', "int main(void) {"]
+    for cname, cls in structs.items():
+        lines.append(f'  printf("{cname} sizeof %zu\\n", sizeof({cname}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    subprocess.run([cc, "-std=c11", "-I", os.path.join(root, "include"), str(src), "-o", str(exe)], check=True)
+    got = {}
+    for ln in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.splitlines():
+        cname, key, val = ln.split()
+        got[(cname, key)] = int(val)
+    for cname, cls in structs.items():
+        assert got[(cname, "sizeof")] == ctypes.sizeof(cls), cname
+        for fname, _ in cls._fields_:
+            assert got[(cname, fname)] == getattr(cls, fname).offset, (cname, fname)
