@@ -80,6 +80,15 @@ def test_size_limits_and_empty_selections_are_rejected_on_the_host():
     assert L.hsm_stencils_condition(None, None, None) == hsm.E_INVALID
 
 
+def test_binding_fails_loudly_without_the_library(tmp_path, monkeypatch):
+    # no CPU fallback: with the HIP library absent every entry point raises
+    from paper_2303_01760_amd import hsm
+    monkeypatch.setattr(hsm, "_lib", None)
+    monkeypatch.setattr(hsm, "LIB_PATH", str(tmp_path / "libhsm.so"))
+    with pytest.raises(RuntimeError, match="not built"):
+        hsm.lib()
+
+
 def test_bench_refuses_more_than_one_gpu():
     # the library has no multi-GPU path: bench.py says so and exits non-zero before touching a device
     import subprocess
